@@ -1,0 +1,187 @@
+"""Newmark integration of one trajectory with sensitivities (oracle; test infrastructure only).
+
+Follows App. E of the paper: the trajectory ODE (Eq. E1/E2)
+    omega_1^2 M a + omega_1 D u + K q + f_nl(q) - e = 0,   u = q', a = q''  (' = d/dphi_1)
+is stepped with the average-acceleration rule (Eqs. E4-E5); every step solves
+Eq. (E6) S q_{k+1} + f_nl(q_{k+1}) = b_k (Eq. E7) by full-tangent Newton, and
+the sensitivities d[q;u](2pi)/d[q;u](0) (Eq. E8) are the exact derivative of
+the converged discrete map.
+
+Readings where the paper is silent (listed in the design doc as well):
+  * the state is [q; u] with u = dq/dphi_1 (App. E), not [q; qdot];
+  * a_0 is the acceleration consistent with the equation of motion at phi_1 = 0;
+  * Newton predictor q_k + D u_k + D^2/2 a_k; stop when ||dq||_inf <= tol *
+    max(||q||_inf, q_scale), or when the update stops shrinking while already
+    below 1e3 tol (the FP64 noise floor); at most `maxit` iterations;
+  * the "adjoint system" of App. E is read as the variational (sensitivity) system.
+
+Pins (tests/test_oracle_newmark.py): the closed-form average-acceleration
+response of an undamped oscillator (unit amplitude, phase 2 atan(Omega h/2) per
+step), discrete energy conservation, the discrete linear steady state, and
+central finite differences of the sensitivities and of the omega-derivatives.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+class StepNewtonError(RuntimeError):
+    pass
+
+
+def internal_force(sysm, q: np.ndarray) -> np.ndarray:
+    """f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l."""
+    n = len(q)
+    f = np.zeros(n)
+    if len(sysm.t2_val):
+        i, j, k = sysm.t2_idx.T
+        f += np.bincount(i, weights=sysm.t2_val * q[j] * q[k], minlength=n)
+    if len(sysm.t3_val):
+        i, j, k, l = sysm.t3_idx.T
+        f += np.bincount(i, weights=sysm.t3_val * q[j] * q[k] * q[l], minlength=n)
+    return f
+
+
+def tangent(sysm, q: np.ndarray) -> np.ndarray:
+    """K_t(q) = d f_nl / d q (dense)."""
+    n = len(q)
+    Kt = np.zeros((n, n))
+    if len(sysm.t2_val):
+        i, j, k = sysm.t2_idx.T
+        v = sysm.t2_val
+        np.add.at(Kt, (i, j), v * q[k])
+        np.add.at(Kt, (i, k), v * q[j])
+    if len(sysm.t3_val):
+        i, j, k, l = sysm.t3_idx.T
+        v = sysm.t3_val
+        np.add.at(Kt, (i, j), v * q[k] * q[l])
+        np.add.at(Kt, (i, k), v * q[j] * q[l])
+        np.add.at(Kt, (i, l), v * q[j] * q[k])
+    return Kt
+
+
+def forcing(sysm, omega, phases, phi1: float) -> np.ndarray:
+    """e(phi_1, phi^_s + rho^ phi_1) of Eq. (E1).
+
+    Forcing i = 1 has argument phi_1; forcing i = 2..e has phi_{i,s} + rho_i phi_1.
+    """
+    e = sysm.F[0] * math.cos(phi1)
+    for i in range(2, sysm.e + 1):
+        rho_i = omega[i - 1] / omega[0]
+        e = e + sysm.F[i - 1] * math.cos(phases[i - 2] + rho_i * phi1)
+    return e
+
+
+def forcing_domega(sysm, omega, phases, phi1: float, i: int) -> np.ndarray:
+    """d e / d omega_i (1-based i) through rho_j = omega_j / omega_1."""
+    out = np.zeros(sysm.n)
+    for j in range(2, sysm.e + 1):
+        arg = phases[j - 2] + omega[j - 1] / omega[0] * phi1
+        if i == 1:
+            dr = -omega[j - 1] / omega[0] ** 2
+        elif i == j:
+            dr = 1.0 / omega[0]
+        else:
+            continue
+        out = out - sysm.F[j - 1] * math.sin(arg) * dr * phi1
+    return out
+
+
+def _solve(A, B):
+    return np.linalg.solve(A, B)
+
+
+def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
+              omega_sens: bool = False, tol: float = 1e-12, maxit: int = 30,
+              q_scale: float = 0.0, history: bool = False):
+    """Integrate one trajectory from phi_1 = 0 to 2 pi in S1 Newmark steps.
+
+    Returns dict with zT = [q; u](2 pi), Phi (2n x 2n) if sens, dz_domega
+    (2n x e) if omega_sens, iters (Newton iterations per step), q_hist if history.
+    """
+    M, D, K = sysm.M, sysm.D, sysm.K
+    n = sysm.n
+    omega = np.asarray(omega, dtype=float)
+    w1 = omega[0]
+    h = 2.0 * math.pi / S1
+    c0, c1, c2 = 4.0 / h ** 2, 4.0 / h, 2.0 / h
+    S = w1 ** 2 * c0 * M + w1 * c2 * D + K
+    q = np.array(z0[:n], dtype=float)
+    u = np.array(z0[n:], dtype=float)
+    Mw = w1 ** 2 * M
+    a = _solve(Mw, forcing(sysm, omega, phases, 0.0) - w1 * D @ u - K @ q
+               - internal_force(sysm, q))
+    if sens:
+        Q = np.hstack([np.eye(n), np.zeros((n, n))])
+        U = np.hstack([np.zeros((n, n)), np.eye(n)])
+        A = -_solve(Mw, np.hstack([K + tangent(sysm, q), w1 * D]))
+    ne = sysm.e
+    if omega_sens:
+        # d q0/d omega = d u0/d omega = 0; d a0/d omega_i from the consistency equation
+        Qw = np.zeros((n, ne))
+        Uw = np.zeros((n, ne))
+        Aw = np.zeros((n, ne))
+        for i in range(1, ne + 1):
+            rhs = forcing_domega(sysm, omega, phases, 0.0, i)
+            if i == 1:
+                rhs = rhs - D @ u - 2.0 * w1 * M @ a
+            Aw[:, i - 1] = _solve(Mw, rhs)
+    iters = np.zeros(S1, dtype=np.int64)
+    qh = [q.copy()] if history else None
+    for k in range(S1):
+        phi_next = (k + 1) * h
+        e1 = forcing(sysm, omega, phases, phi_next)
+        b = e1 + Mw @ (c0 * q + c1 * u + a) + w1 * D @ (c2 * q + u)
+        qn = q + h * u + 0.5 * h * h * a
+        prev = math.inf
+        ok = False
+        for it in range(maxit):
+            r = S @ qn + internal_force(sysm, qn) - b
+            T = S + tangent(sysm, qn)
+            dq = _solve(T, r)
+            qn = qn - dq
+            nd = float(np.max(np.abs(dq)))
+            scale = max(float(np.max(np.abs(qn))), q_scale)
+            iters[k] = it + 1
+            if nd <= tol * scale or (nd <= 1e3 * tol * scale and nd > 0.5 * prev):
+                ok = True
+                break
+            prev = nd
+        if not ok:
+            raise StepNewtonError(f"step Newton did not converge at step {k}")
+        un = c2 * (qn - q) - u
+        an = c0 * (qn - q) - c1 * u - a
+        if sens or omega_sens:
+            T = S + tangent(sysm, qn)
+        if sens:
+            rhs = Mw @ (c0 * Q + c1 * U + A) + w1 * D @ (c2 * Q + U)
+            Qn = _solve(T, rhs)
+            Un = c2 * (Qn - Q) - U
+            An = c0 * (Qn - Q) - c1 * U - A
+            Q, U, A = Qn, Un, An
+        if omega_sens:
+            rhs = Mw @ (c0 * Qw + c1 * Uw + Aw) + w1 * D @ (c2 * Qw + Uw)
+            for i in range(1, ne + 1):
+                col = forcing_domega(sysm, omega, phases, phi_next, i)
+                if i == 1:
+                    dS = 2.0 * w1 * c0 * M + c2 * D
+                    col = (col - dS @ qn + 2.0 * w1 * M @ (c0 * q + c1 * u + a)
+                           + D @ (c2 * q + u))
+                rhs[:, i - 1] += col
+            Qwn = _solve(T, rhs)
+            Uwn = c2 * (Qwn - Qw) - Uw
+            Awn = c0 * (Qwn - Qw) - c1 * Uw - Aw
+            Qw, Uw, Aw = Qwn, Uwn, Awn
+        q, u, a = qn, un, an
+        if history:
+            qh.append(q.copy())
+    out = {"zT": np.concatenate([q, u]), "iters": iters, "aT": a}
+    if sens:
+        out["Phi"] = np.vstack([Q, U])
+    if omega_sens:
+        out["dz_domega"] = np.vstack([Qw, Uw])
+    if history:
+        out["q_hist"] = np.array(qh)
+    return out

@@ -1,0 +1,56 @@
+"""Pins of the oracle's predictors: secant, snapshot POD, MLP gradients."""
+import numpy as np
+import pytest
+
+from oracle import learned
+
+
+def test_secant_exact_on_affine_path():
+    rng = np.random.default_rng(0)
+    Z0, dZ = rng.normal(size=(5, 7)), rng.normal(size=(5, 7))
+    p0, dp = rng.normal(size=3), rng.normal(size=3)
+    path = lambda t: Z0 + t * dZ
+    par = lambda t: p0 + t * dp
+    Zp = learned.secant_predict(par(0.0), par(0.4), par(1.1), path(0.0), path(0.4))
+    assert np.allclose(Zp, path(1.1), atol=1e-12)
+
+
+def test_pod_matches_svd_and_is_orthonormal():
+    rng = np.random.default_rng(1)
+    N, m, r = 300, 40, 12
+    X = rng.normal(size=(N, 6)) @ rng.normal(size=(6, m)) + 0.05 * rng.normal(size=(N, m))
+    mean, B, sv = learned.pod_snapshots(X, r)
+    assert np.allclose(B.T @ B, np.eye(r), atol=1e-10)
+    Xc = X - X.mean(axis=1, keepdims=True)
+    s_ref = np.linalg.svd(Xc, compute_uv=False)
+    assert np.allclose(sv[:r], s_ref[:r], rtol=1e-9)
+    rec = B @ (B.T @ Xc)
+    err = np.linalg.norm(Xc - rec)
+    assert np.isclose(err, np.sqrt(np.sum(s_ref[r:] ** 2)), rtol=1e-8)
+
+
+@pytest.mark.parametrize("sizes", [(3, 8, 8, 4), (3, 256, 256, 64)])
+def test_mlp_gradients_match_finite_differences(sizes):
+    rng = np.random.default_rng(2)
+    params = learned.mlp_init(sizes, seed=3)
+    x = rng.normal(size=(5, sizes[0]))
+    t = rng.normal(size=(5, sizes[-1]))
+    g = learned.mlp_backward(params, x, t)
+    h = 1e-6
+    picks = [(0, 0, (1, 2)), (0, 1, (3,)), (1, 0, (2, 5)), (1, 1, (0,)), (2, 0, (1, 3)), (2, 1, (2,))]
+    for li, pi, idx in picks:
+        p = params[li][pi]
+        old = p[idx]
+        p[idx] = old + h
+        lp = learned.mlp_loss(params, x, t)
+        p[idx] = old - h
+        lm = learned.mlp_loss(params, x, t)
+        p[idx] = old
+        fd = (lp - lm) / (2 * h)
+        assert np.isclose(g[li][pi][idx], fd, rtol=1e-6, atol=1e-10), (li, pi, idx)
+
+
+def test_gelu_reference_values():
+    # GELU(x) = x Phi(x): Phi(1) = 0.841344746..., Phi(-1) = 0.158655253...
+    assert np.isclose(learned.gelu(np.array(1.0)), 0.8413447460685429, rtol=1e-14)
+    assert np.isclose(learned.gelu(np.array(-1.0)), -0.15865525393145707, rtol=1e-14)
