@@ -1,0 +1,162 @@
+/*
+ * fse.h -- C-ABI of the FSE-Shooting hot path on one MI355X (gfx950).
+ *
+ * FSE-Shooting (Fourier-series-expansion shooting, Wu, Hong, Li, Jiang 2025)
+ * computes quasi-periodic responses of
+ *
+ *     M q'' + D q' + K q + f_nl(q) = sum_{i=1..e} F_i cos(omega_i t)       (Eq. 1, Eq. 25)
+ *
+ * by shooting on the Fourier coefficients Z(0) of the initial (d-1)-torus:
+ * Z(0) -> z(0, phi~) (inverse DFT, Eq. 20) -> every trajectory integrated over
+ * phi_1 in [0, 2 pi] by average-acceleration Newmark (App. E) -> z(2 pi, phi~)
+ * -> Z(2 pi) (DFT, Eq. 21) -> R = (I (x) R(rho)) Z(2 pi) - Z(0) (Eqs. 15-16).
+ *
+ * Conventions (bit-exact parts of the contract):
+ *   - harmonic table K~ of App. B (Eqs. B1-B2): (L+1) x (d-1) int32 rows, row-major,
+ *     rows 0..L-1 the harmonic vectors k~_1..k~_L, last row zero;  U = 2L + 1;
+ *   - Fourier coefficients Z: [2n][U], state-major (Eq. 10), state order [q; u]
+ *     with u = dq/dphi_1 (App. E); column 0 the constant term, columns 2l-1 /
+ *     2l the cos / sin coefficients of row l-1 of K~ (Eq. 11);
+ *   - samples: S~ = prod S_j points, phi_2 fastest (Eq. D1); zbar: [2n][S~];
+ *   - sensitivities Phi_s = d[q;u](2 pi) / d[q;u](0) (Eq. E8): [2n][2n] row-major.
+ *
+ * Memory: fse_init_torus reads HOST arrays and deep-copies them to the device.
+ * Every array argument of the compute calls (omega excepted where noted) is a
+ * DEVICE pointer (e.g. a torch tensor's data_ptr()) owned by the caller; work
+ * is enqueued on the context stream (fse_set_stream) and the call returns after
+ * that stream has completed it, unless stated otherwise.
+ *
+ * Errors: every call returns fse_status; FSE_OK == 0.  On error the message is
+ * available from fse_last_error(ctx) and no output is guaranteed to be valid.
+ * Calls on one context are not thread-safe; distinct contexts are independent.
+ */
+#ifndef FSE_H
+#define FSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fse_ctx fse_ctx;
+
+typedef enum {
+  FSE_OK = 0,
+  FSE_E_INVAL = 1,        /* bad argument: sizes, CSR structure, Nyquist, d > 4, e > d   */
+  FSE_E_NOMEM = 2,        /* device allocation failed                                    */
+  FSE_E_DEVICE = 3,       /* HIP runtime error                                           */
+  FSE_E_NOCONV = 4,       /* per-step Newton did not converge (step index in message)    */
+  FSE_E_SINGULAR = 5,     /* zero / non-finite pivot in a banded or dense factorisation  */
+  FSE_E_NAN = 6,          /* non-finite state                                            */
+  FSE_E_UNSUPPORTED = 7   /* valid request this build does not handle (message says why) */
+} fse_status;
+
+typedef enum {
+  FSE_PREC_FP64 = 0,        /* FP64 everywhere                                            */
+  FSE_PREC_MIXED_FP32 = 1   /* sensitivities propagated in FP32 with FP64 state/residuals */
+} fse_precision;
+
+/* System of Eq. (1) with Theta = I.  Matrices in CSR (0-based, sorted column
+ * indices, symmetric); f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l with
+ * index tuples (i,j,k) / (i,j,k,l) stored as rows of t2_idx / t3_idx.  The
+ * tangent d f_nl / dq must be symmetric (forces derived from a potential,
+ * as for the paper's von Karman and shell models); fse_init_torus checks it.
+ * F: [e][n] load amplitude vectors, forcing i has frequency omega_i. */
+typedef struct {
+  int32_t n;
+  const int32_t *M_ptr, *M_idx; const double *M_val;
+  const int32_t *D_ptr, *D_idx; const double *D_val;
+  const int32_t *K_ptr, *K_idx; const double *K_val;
+  int64_t nnz2; const int32_t *t2_idx; const double *t2_val;
+  int64_t nnz3; const int32_t *t3_idx; const double *t3_val;
+  int32_t e; const double *F;
+} fse_system;
+
+/* Torus and time discretisation (Sec. 3.1, App. B, App. D, App. E).
+ * K_len[j-2] = L_j and K_list the concatenated positive harmonic orders k_j
+ * (ascending) for j = 2..d; S[j-2] = S_j >= 2 max(k_j) + 1 (Nyquist, Sec. 3.1);
+ * S1 Newmark steps per 2 pi of phi_1 (beta = 1/4, gamma = 1/2).
+ * step_tol / step_maxit: per-step Newton stops when ||dq||_inf <= step_tol *
+ * ||q||_inf (or when the update stops shrinking below 1e3 step_tol, the FP64
+ * noise floor); defaults 1e-12 / 30 when <= 0.  max_batch: continuation points
+ * (omega vectors) a single call may integrate together. */
+typedef struct {
+  int32_t d, e;
+  const int32_t *K_len;
+  const int32_t *K_list;
+  const int32_t *S;
+  int32_t S1;
+  double step_tol;
+  int32_t step_maxit;
+  int32_t max_batch;
+  int32_t precision;      /* fse_precision */
+} fse_torus_desc;
+
+/* Builds the torus tables (harmonic table, grid, Gamma, Gamma^-1 of Eqs. D1-D3),
+ * converts the system to banded device storage and allocates all work buffers
+ * for up to max_batch points.  Host pointers.  *out receives the context. */
+fse_status fse_init_torus(const fse_system *sys, const fse_torus_desc *desc, fse_ctx **out);
+
+/* Layout queries (host outputs, any may be NULL): number of Fourier
+ * coefficients U, number of samples S~, half bandwidth of the banded storage,
+ * and the harmonic table [(U+1)/2][d-1] of App. B. */
+fse_status fse_get_layout(const fse_ctx *ctx, int32_t *U, int32_t *Stilde,
+                          int32_t *half_band, int32_t *ktable);
+
+/* Stream (hipStream_t) on which all work of this context is enqueued; NULL is
+ * the null stream.  The stream must belong to the context's device. */
+fse_status fse_set_stream(fse_ctx *ctx, void *hip_stream);
+
+/* Steps 2-3 of Sec. 3.3 for B <= max_batch points.  omega: HOST [B][d].
+ * Z0: [B][2n][U].  zT (out): [B][2n][S~] terminal samples zbar(2 pi, phi~_s).
+ * Phi (out, may be NULL): [B][S~][2n][2n] sensitivities (Eq. E8); computed only
+ * when Phi != NULL.  Newton statistics of the state integration are available
+ * through fse_step_stats. */
+fse_status fse_integrate_batch(fse_ctx *ctx, int32_t B, const double *omega,
+                               const double *Z0, double *zT, double *Phi);
+
+/* Max and total per-step Newton iterations of the last integration (host). */
+fse_status fse_step_stats(const fse_ctx *ctx, int32_t *max_iters, int64_t *total_iters);
+
+/* Steps 2-5 of Sec. 3.3: residual R = (I (x) R(rho)) Z(2 pi) - Z(0) (Eq. 16),
+ * [B][2n][U]; rnorm (HOST, may be NULL): ||R||_2 per point.
+ * J (may be NULL): [B][2nU][2nU] row-major Jacobian of Eq. (22) (requires the
+ * sensitivities).  dRdw (may be NULL): [B][2nU][d] derivatives of Eq. (23)-(24). */
+fse_status fse_shooting_residual_jacobian(fse_ctx *ctx, int32_t B, const double *omega,
+                                          const double *Z0, double *R, double *rnorm,
+                                          double *J, double *dRdw);
+
+/* One Newton-Raphson update of step 6 of Sec. 3.3 for one point with all base
+ * frequencies known (d = e; the frequency conditions of Eq. 17b hold exactly so
+ * omega is unchanged): Z0 <- Z0 - J^-1 R, dense LU with partial pivoting in FP64.
+ * omega: HOST [d]; Z0: [2n][U] in/out; res_norm (HOST): ||R||_2 before the
+ * update. */
+fse_status fse_newton_step(fse_ctx *ctx, const double *omega, double *Z0, double *res_norm);
+
+/* Newton iterations until ||R||_2 < tol (App. C stopping rule) or maxit.
+ * iters / res_norm (HOST): iterations used and the final ||R||_2.
+ * Returns FSE_E_NOCONV if the tolerance was not reached. */
+fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, double tol,
+                            int32_t maxit, int32_t *iters, double *res_norm);
+
+/* Lyapunov exponents of App. F from the sensitivities at Z0: Psi_s of Eq. (F3),
+ * trigonometric interpolation on the torus basis at phi~ = 2 pi (i-1) rho,
+ * N_Ly steps of Gram-Schmidt as Householder QR with positive diagonal.
+ * Q0: [2n][2n] initial orthonormal basis or NULL for the identity.
+ * sigma (HOST out): [2n] exponents in QR column order (1/s). */
+fse_status fse_lyapunov(fse_ctx *ctx, const double *omega, const double *Z0, int32_t N_Ly,
+                        const double *Q0, double *sigma);
+
+/* Device time (ms, HIP events on the context stream) of the kernels of the
+ * last fse_integrate_batch: [0] total, [1] state integration, [2] sensitivity
+ * propagation, [3] AFT; launches_out: launches of the sensitivity kernel. */
+fse_status fse_last_timing(const fse_ctx *ctx, double *ms4, int32_t *launches_out);
+
+const char *fse_last_error(const fse_ctx *ctx);
+void fse_destroy(fse_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSE_H */

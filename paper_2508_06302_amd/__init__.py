@@ -1,0 +1,214 @@
+"""FSE-Shooting on one MI355X: Python binding of libfse.so (include/fse.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are torch tensors on the current CUDA (HIP) device; the library
+works on torch's current stream.  There is no CPU fallback: without the built
+library or without a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+
+__all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integrate_batch",
+           "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
+           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "FSE_PREC_FP64",
+           "FSE_PREC_MIXED_FP32"]
+
+FSE_PREC_FP64 = 0
+FSE_PREC_MIXED_FP32 = 1
+
+
+class FseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.FSE_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("FSE-Shooting needs a GPU (HIP device); none is available")
+    return torch
+
+
+def _csr(A):
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    ptr = np.zeros(n + 1, np.int32)
+    idx, val = [], []
+    for i in range(n):
+        nz = np.flatnonzero(A[i])
+        idx.append(nz.astype(np.int32))
+        val.append(A[i, nz])
+        ptr[i + 1] = ptr[i] + len(nz)
+    return ptr, np.concatenate(idx).astype(np.int32), np.concatenate(val).astype(np.float64)
+
+
+def _p(arr, ct):
+    return arr.ctypes.data_as(C.POINTER(ct))
+
+
+class Context:
+    """Owns an fse_ctx; keeps the host arrays alive for the duration of init."""
+
+    def __init__(self, handle, lib, n, d, U, St, bw, ktable):
+        self.h, self.lib = handle, lib
+        self.n, self.d, self.U, self.Stilde, self.half_band = n, d, U, St, bw
+        self.ktable = ktable
+
+    def check(self, status):
+        if status != 0:
+            msg = self.lib.fse_last_error(self.h).decode()
+            raise FseError(status, msg)
+
+    def bind_stream(self):
+        torch = _torch()
+        self.check(self.lib.fse_set_stream(self.h, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.lib.fse_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def fse_init_torus(system, torus, max_batch=1, precision=FSE_PREC_FP64, step_tol=1e-12,
+                   step_maxit=30) -> Context:
+    """system: fse_inputs.System (dense M, D, K; COO tensors); torus: fse_inputs.Torus."""
+    lib = _lib.load()
+    _torch()
+    n = system.n
+    Mp, Mi, Mv = _csr(system.M)
+    Dp, Di, Dv = _csr(system.D)
+    Kp, Ki, Kv = _csr(system.K)
+    t2i = np.ascontiguousarray(system.t2_idx, dtype=np.int32)
+    t2v = np.ascontiguousarray(system.t2_val, dtype=np.float64)
+    t3i = np.ascontiguousarray(system.t3_idx, dtype=np.int32)
+    t3v = np.ascontiguousarray(system.t3_val, dtype=np.float64)
+    F = np.ascontiguousarray(system.F, dtype=np.float64)
+    sysc = _lib.FseSystem(n, _p(Mp, C.c_int32), _p(Mi, C.c_int32), _p(Mv, C.c_double),
+                          _p(Dp, C.c_int32), _p(Di, C.c_int32), _p(Dv, C.c_double),
+                          _p(Kp, C.c_int32), _p(Ki, C.c_int32), _p(Kv, C.c_double),
+                          len(t2v), _p(t2i, C.c_int32), _p(t2v, C.c_double),
+                          len(t3v), _p(t3i, C.c_int32), _p(t3v, C.c_double),
+                          F.shape[0], _p(F, C.c_double))
+    klen = np.array([len(k) for k in torus.K] or [0], np.int32)
+    klist = np.concatenate([np.asarray(k, np.int32) for k in torus.K] or [np.zeros(1, np.int32)])
+    klist = np.ascontiguousarray(klist, dtype=np.int32)
+    S = np.array(list(torus.S) or [1], np.int32)
+    desc = _lib.FseTorusDesc(torus.d, torus.e, _p(klen, C.c_int32), _p(klist, C.c_int32),
+                             _p(S, C.c_int32), torus.S1, step_tol, step_maxit, max_batch, precision)
+    h = C.c_void_p()
+    st = lib.fse_init_torus(C.byref(sysc), C.byref(desc), C.byref(h))
+    if st != 0:
+        msg = lib.fse_last_error(h).decode() if h else "init failed"
+        if h:
+            lib.fse_destroy(h)
+        raise FseError(st, msg)
+    U, St, bw = C.c_int32(), C.c_int32(), C.c_int32()
+    lib.fse_get_layout(h, C.byref(U), C.byref(St), C.byref(bw), None)
+    kt = np.zeros(((U.value + 1) // 2, max(torus.d - 1, 1)), np.int32)
+    lib.fse_get_layout(h, None, None, None, _p(kt, C.c_int32))
+    ctx = Context(h, lib, n, torus.d, U.value, St.value, bw.value, kt[:, : torus.d - 1])
+    ctx.bind_stream()
+    return ctx
+
+
+def fse_get_layout(ctx: Context):
+    return ctx.U, ctx.Stilde, ctx.half_band, ctx.ktable.copy()
+
+
+def _omega(omega, B, d):
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(B, d))
+    return om
+
+
+def _dev(x, shape):
+    torch = _torch()
+    t = torch.as_tensor(x, dtype=torch.float64, device="cuda").reshape(shape).contiguous()
+    return t
+
+
+def fse_integrate_batch(ctx: Context, omega, Z0, want_phi=False):
+    """omega [B][d] (host), Z0 [B][2n][U] -> zT [B][2n][S~], Phi [B][S~][2n][2n] or None."""
+    torch = _torch()
+    ctx.bind_stream()
+    B = int(np.asarray(omega).reshape(-1, ctx.d).shape[0])
+    om = _omega(omega, B, ctx.d)
+    z0 = _dev(Z0, (B, 2 * ctx.n, ctx.U))
+    zT = torch.empty((B, 2 * ctx.n, ctx.Stilde), dtype=torch.float64, device="cuda")
+    phi = (torch.empty((B, ctx.Stilde, 2 * ctx.n, 2 * ctx.n), dtype=torch.float64, device="cuda")
+           if want_phi else None)
+    ctx.check(ctx.lib.fse_integrate_batch(ctx.h, B, _p(om, C.c_double), C.c_void_p(z0.data_ptr()),
+                                          C.c_void_p(zT.data_ptr()),
+                                          C.c_void_p(phi.data_ptr()) if phi is not None else None))
+    return zT, phi
+
+
+def fse_step_stats(ctx: Context):
+    mx, tot = C.c_int32(), C.c_int64()
+    ctx.check(ctx.lib.fse_step_stats(ctx.h, C.byref(mx), C.byref(tot)))
+    return mx.value, tot.value
+
+
+def fse_shooting_residual_jacobian(ctx: Context, omega, Z0, want_J=False):
+    """-> (R [B][2n][U], ||R||_2 [B], J [B][2nU][2nU] or None)."""
+    torch = _torch()
+    ctx.bind_stream()
+    B = int(np.asarray(omega).reshape(-1, ctx.d).shape[0])
+    om = _omega(omega, B, ctx.d)
+    z0 = _dev(Z0, (B, 2 * ctx.n, ctx.U))
+    R = torch.empty_like(z0)
+    rn = np.zeros(B)
+    N = 2 * ctx.n * ctx.U
+    J = torch.empty((B, N, N), dtype=torch.float64, device="cuda") if want_J else None
+    ctx.check(ctx.lib.fse_shooting_residual_jacobian(
+        ctx.h, B, _p(om, C.c_double), C.c_void_p(z0.data_ptr()), C.c_void_p(R.data_ptr()),
+        _p(rn, C.c_double), C.c_void_p(J.data_ptr()) if J is not None else None, None))
+    return R, rn, J
+
+
+def fse_newton_step(ctx: Context, omega, Z0):
+    """Z0 (torch cuda tensor [2n][U], updated in place) -> ||R||_2 before the update."""
+    ctx.bind_stream()
+    om = _omega(omega, 1, ctx.d)
+    rn = C.c_double()
+    ctx.check(ctx.lib.fse_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
+                                      C.byref(rn)))
+    return rn.value
+
+
+def fse_newton_solve(ctx: Context, omega, Z0, tol=1e-8, maxit=20):
+    """Z0 (torch cuda tensor, in place) -> (iterations, final ||R||_2)."""
+    ctx.bind_stream()
+    om = _omega(omega, 1, ctx.d)
+    it, rn = C.c_int32(), C.c_double()
+    ctx.check(ctx.lib.fse_newton_solve(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
+                                       tol, maxit, C.byref(it), C.byref(rn)))
+    return it.value, rn.value
+
+
+def fse_lyapunov(ctx: Context, omega, Z0, N_Ly=1000, Q0=None):
+    ctx.bind_stream()
+    om = _omega(omega, 1, ctx.d)
+    z0 = _dev(Z0, (2 * ctx.n, ctx.U))
+    q0 = _dev(Q0, (2 * ctx.n, 2 * ctx.n)) if Q0 is not None else None
+    sig = np.zeros(2 * ctx.n)
+    ctx.check(ctx.lib.fse_lyapunov(ctx.h, _p(om, C.c_double), C.c_void_p(z0.data_ptr()), N_Ly,
+                                   C.c_void_p(q0.data_ptr()) if q0 is not None else None,
+                                   _p(sig, C.c_double)))
+    return sig
+
+
+def fse_last_timing(ctx: Context):
+    ms = np.zeros(4)
+    nl = C.c_int32()
+    ctx.check(ctx.lib.fse_last_timing(ctx.h, _p(ms, C.c_double), C.byref(nl)))
+    return {"total_ms": ms[0], "state_ms": ms[1], "sens_ms": ms[2], "idft_ms": ms[3],
+            "sens_launches": nl.value}

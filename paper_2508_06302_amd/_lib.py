@@ -1,0 +1,72 @@
+"""ctypes declarations of include/fse.h.  Loading fails loudly if libfse.so is absent."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfse.so")
+
+FSE_STATUS = {0: "FSE_OK", 1: "FSE_E_INVAL", 2: "FSE_E_NOMEM", 3: "FSE_E_DEVICE",
+              4: "FSE_E_NOCONV", 5: "FSE_E_SINGULAR", 6: "FSE_E_NAN", 7: "FSE_E_UNSUPPORTED"}
+
+EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_batch",
+           "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
+           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_last_error",
+           "fse_destroy"]
+
+i32p = C.POINTER(C.c_int32)
+f64p = C.POINTER(C.c_double)
+
+
+class FseSystem(C.Structure):
+    _fields_ = [("n", C.c_int32),
+                ("M_ptr", i32p), ("M_idx", i32p), ("M_val", f64p),
+                ("D_ptr", i32p), ("D_idx", i32p), ("D_val", f64p),
+                ("K_ptr", i32p), ("K_idx", i32p), ("K_val", f64p),
+                ("nnz2", C.c_int64), ("t2_idx", i32p), ("t2_val", f64p),
+                ("nnz3", C.c_int64), ("t3_idx", i32p), ("t3_val", f64p),
+                ("e", C.c_int32), ("F", f64p)]
+
+
+class FseTorusDesc(C.Structure):
+    _fields_ = [("d", C.c_int32), ("e", C.c_int32), ("K_len", i32p), ("K_list", i32p),
+                ("S", i32p), ("S1", C.c_int32), ("step_tol", C.c_double),
+                ("step_maxit", C.c_int32), ("max_batch", C.c_int32), ("precision", C.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfse.so and declare every C-ABI signature.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with paper_2508_06302_amd.build.build()")
+    # torch bundles its own HIP runtime (SONAME libamdhip64.so.7).  Importing torch first
+    # makes libfse.so bind to that already-loaded runtime, so the process holds one HIP
+    # runtime and torch's device pointers and streams are valid in the library.
+    import torch  # noqa: F401
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.fse_init_torus.argtypes = [C.POINTER(FseSystem), C.POINTER(FseTorusDesc), C.POINTER(vp)]
+    lib.fse_get_layout.argtypes = [vp, i32p, i32p, i32p, i32p]
+    lib.fse_set_stream.argtypes = [vp, vp]
+    lib.fse_integrate_batch.argtypes = [vp, C.c_int32, f64p, vp, vp, vp]
+    lib.fse_step_stats.argtypes = [vp, i32p, C.POINTER(C.c_int64)]
+    lib.fse_shooting_residual_jacobian.argtypes = [vp, C.c_int32, f64p, vp, vp, f64p, vp, vp]
+    lib.fse_newton_step.argtypes = [vp, f64p, vp, f64p]
+    lib.fse_newton_solve.argtypes = [vp, f64p, vp, C.c_double, C.c_int32, i32p, f64p]
+    lib.fse_lyapunov.argtypes = [vp, f64p, vp, C.c_int32, vp, f64p]
+    lib.fse_last_timing.argtypes = [vp, f64p, i32p]
+    lib.fse_last_error.argtypes = [vp]
+    lib.fse_last_error.restype = C.c_char_p
+    lib.fse_destroy.argtypes = [vp]
+    lib.fse_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("fse_last_error", "fse_destroy"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib

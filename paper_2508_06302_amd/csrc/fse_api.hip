@@ -1,0 +1,650 @@
+// C-ABI entry points of the FSE-Shooting library: context set-up on the host
+// (torus tables of App. B / App. D, banded device storage of the system) and the
+// orchestration of the device kernels for Sec. 3.3 steps 2-6 and App. F.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <random>
+
+#include "fse_internal.h"
+
+namespace {
+
+// Harmonic table of App. B (Eqs. B1-B2).  d = 2: [k_2; 0].  d > 2 from K~^{d-1}:
+// g-block rows [r, -k] for k in k_d (outer) and r in the nonzero rows (inner);
+// b-block rows [r, k] for k in [k_d; 0] (outer) and r in all rows (inner).
+std::vector<std::vector<int>> harmonic_table(const std::vector<std::vector<int>> &k) {
+  std::vector<std::vector<int>> T;
+  if (k.empty()) {
+    T.push_back({});
+    return T;
+  }
+  for (int v : k[0]) T.push_back({v});
+  T.push_back({0});
+  for (size_t j = 1; j < k.size(); ++j) {
+    std::vector<std::vector<int>> nt;
+    const size_t nz = T.size() - 1;
+    for (int kd : k[j])
+      for (size_t r = 0; r < nz; ++r) {
+        auto row = T[r];
+        row.push_back(-kd);
+        nt.push_back(row);
+      }
+    std::vector<int> kd0 = k[j];
+    kd0.push_back(0);
+    for (int kv : kd0)
+      for (size_t r = 0; r < T.size(); ++r) {
+        auto row = T[r];
+        row.push_back(kv);
+        nt.push_back(row);
+      }
+    T.swap(nt);
+  }
+  return T;
+}
+
+struct Csr {
+  const int32_t *ptr, *idx;
+  const double *val;
+};
+
+fse_status csr_to_band(fse_ctx *ctx, const char *name, Csr a, int n, int bw,
+                       std::vector<double> &band) {
+  const int w = 2 * bw + 1;
+  band.assign((size_t)n * w, 0.0);
+  if (!a.ptr || !a.idx || !a.val) {
+    ctx->err = std::string("matrix ") + name + ": null CSR array";
+    return FSE_E_INVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) {
+      const int j = a.idx[p];
+      if (j < 0 || j >= n || std::abs(j - i) > bw) {
+        ctx->err = std::string("matrix ") + name + ": column index out of range";
+        return FSE_E_INVAL;
+      }
+      band[(size_t)i * w + (j - i + bw)] += a.val[p];
+    }
+  }
+  double mx = 0.0;
+  for (double v : band) mx = std::max(mx, std::abs(v));
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t < w; ++t) {
+      const int j = i - bw + t;
+      if (j < 0 || j >= n) continue;
+      const double aij = band[(size_t)i * w + t];
+      const double aji = band[(size_t)j * w + (i - j + bw)];
+      if (std::abs(aij - aji) > 1e-12 * mx) {
+        ctx->err = std::string("matrix ") + name + " is not symmetric";
+        return FSE_E_INVAL;
+      }
+    }
+  return FSE_OK;
+}
+
+int csr_halfband(Csr a, int n) {
+  int b = 0;
+  if (!a.ptr) return 0;
+  for (int i = 0; i < n; ++i)
+    for (int32_t p = a.ptr[i]; p < a.ptr[i + 1]; ++p) b = std::max(b, std::abs(a.idx[p] - i));
+  return b;
+}
+
+template <typename T>
+fse_status upload(fse_ctx *ctx, T **dst, const std::vector<T> &src) {
+  const size_t bytes = std::max<size_t>(src.size(), 1) * sizeof(T);
+  if (hipMalloc((void **)dst, bytes) != hipSuccess) {
+    ctx->err = "hipMalloc failed (" + std::to_string(bytes) + " bytes)";
+    return FSE_E_NOMEM;
+  }
+  if (!src.empty()) FSE_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FSE_OK;
+}
+
+fse_status alloc(fse_ctx *ctx, void **dst, size_t bytes) {
+  if (hipMalloc(dst, std::max<size_t>(bytes, 8)) != hipSuccess) {
+    ctx->err = "hipMalloc failed (" + std::to_string(bytes) + " bytes)";
+    return FSE_E_NOMEM;
+  }
+  return FSE_OK;
+}
+
+fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx *ctx) {
+  if (!sys || !desc) {
+    ctx->err = "null system or torus descriptor";
+    return FSE_E_INVAL;
+  }
+  const int n = sys->n;
+  if (n <= 0 || sys->e < 1 || desc->d < 1 || desc->d > 4 || desc->e != sys->e || desc->e > desc->d ||
+      desc->S1 < 1 || desc->max_batch < 1) {
+    ctx->err = "invalid sizes: need n > 0, 1 <= e <= d <= 4, e == system e, S1 >= 1, max_batch >= 1";
+    return FSE_E_INVAL;
+  }
+  if (desc->precision != FSE_PREC_FP64 && desc->precision != FSE_PREC_MIXED_FP32) {
+    ctx->err = "unknown precision";
+    return FSE_E_INVAL;
+  }
+  if (desc->e < desc->d) {
+    ctx->err = "unknown base frequencies (d > e) are not handled by this build";
+    return FSE_E_UNSUPPORTED;
+  }
+  ctx->n = n;
+  ctx->e = sys->e;
+  ctx->d = desc->d;
+  ctx->S1 = desc->S1;
+  ctx->Bmax = desc->max_batch;
+  ctx->prec = desc->precision;
+  ctx->tol = desc->step_tol > 0 ? desc->step_tol : 1e-12;
+  ctx->maxit = desc->step_maxit > 0 ? desc->step_maxit : 30;
+  // FSE_KERNELS=fused|generic selects the trajectory kernels (tests cover both paths)
+  if (const char *kv = std::getenv("FSE_KERNELS")) ctx->use_fused = std::strcmp(kv, "fused") == 0;
+  if (const char *nc = std::getenv("FSE_FUSED_NCW")) ctx->fused_ncw = std::max(1, std::atoi(nc));
+  FSE_HIP(hipGetDevice(&ctx->device));
+
+  // ---- torus tables (App. B, App. D)
+  std::vector<std::vector<int>> klists;
+  int off = 0;
+  for (int j = 0; j < ctx->d - 1; ++j) {
+    const int Lj = desc->K_len ? desc->K_len[j] : 0;
+    if (Lj < 1 || !desc->K_list || !desc->S) {
+      ctx->err = "every torus direction needs at least one positive harmonic";
+      return FSE_E_INVAL;
+    }
+    std::vector<int> kj(desc->K_list + off, desc->K_list + off + Lj);
+    off += Lj;
+    for (int a = 0; a < Lj; ++a)
+      if (kj[a] <= 0 || (a > 0 && kj[a] <= kj[a - 1])) {
+        ctx->err = "harmonic orders must be positive and strictly ascending";
+        return FSE_E_INVAL;
+      }
+    const int Sj = desc->S[j];
+    if (Sj < 2 * kj.back() + 1) {
+      ctx->err = "Nyquist condition S_j >= 2 H_j + 1 violated (Sec. 3.1)";
+      return FSE_E_INVAL;
+    }
+    klists.push_back(kj);
+    ctx->Sdim.push_back(Sj);
+  }
+  auto T = harmonic_table(klists);
+  ctx->L = (int)T.size() - 1;
+  ctx->U = 2 * ctx->L + 1;
+  const int dm1 = ctx->d - 1;
+  ctx->ktable.assign((size_t)(ctx->L + 1) * std::max(dm1, 1), 0);
+  for (int r = 0; r <= ctx->L; ++r)
+    for (int j = 0; j < dm1; ++j) ctx->ktable[(size_t)r * dm1 + j] = T[r][j];
+  int64_t St = 1;
+  for (int s : ctx->Sdim) St *= s;
+  ctx->St = (int)St;
+  // sample coordinates, phi_2 fastest (Eq. D1)
+  ctx->sidx.assign((size_t)std::max(dm1, 1) * St, 0);
+  {
+    int64_t inner = 1;
+    for (int j = 0; j < dm1; ++j) {
+      for (int64_t s = 0; s < St; ++s) ctx->sidx[(size_t)j * St + s] = (int)((s / inner) % ctx->Sdim[j]);
+      inner *= ctx->Sdim[j];
+    }
+  }
+  // Gamma / Gamma^-1 (Eqs. D2-D3) with angles reduced in integers over prod S_j
+  ctx->G.assign((size_t)St * ctx->U, 0.0);
+  ctx->Gi.assign((size_t)ctx->U * St, 0.0);
+  const double twopi = 2.0 * M_PI;
+  for (int64_t s = 0; s < St; ++s) {
+    ctx->G[(size_t)s * ctx->U] = 1.0;
+    ctx->Gi[(size_t)s] = 1.0 / (double)St;
+    for (int l = 0; l < ctx->L; ++l) {
+      int64_t num = 0;
+      for (int j = 0; j < dm1; ++j) {
+        const int64_t Sj = ctx->Sdim[j];
+        int64_t m = ((int64_t)T[l][j] * ctx->sidx[(size_t)j * St + s]) % Sj;
+        if (m < 0) m += Sj;
+        num = (num + m * (St / Sj)) % St;
+      }
+      const double th = twopi * (double)num / (double)St;
+      const double c = std::cos(th), sn = std::sin(th);
+      ctx->G[(size_t)s * ctx->U + 2 * l + 1] = c;
+      ctx->G[(size_t)s * ctx->U + 2 * l + 2] = sn;
+      ctx->Gi[(size_t)(2 * l + 1) * St + s] = 2.0 * c / (double)St;
+      ctx->Gi[(size_t)(2 * l + 2) * St + s] = 2.0 * sn / (double)St;
+    }
+  }
+
+  // ---- system: band width from matrices and from the tensor index pairs
+  Csr M{sys->M_ptr, sys->M_idx, sys->M_val}, D{sys->D_ptr, sys->D_idx, sys->D_val},
+      K{sys->K_ptr, sys->K_idx, sys->K_val};
+  int bw = std::max({csr_halfband(M, n), csr_halfband(D, n), csr_halfband(K, n)});
+  if (sys->nnz2 < 0 || sys->nnz3 < 0 || (sys->nnz2 > 0 && (!sys->t2_idx || !sys->t2_val)) ||
+      (sys->nnz3 > 0 && (!sys->t3_idx || !sys->t3_val)) || !sys->F) {
+    ctx->err = "invalid tensor or load arrays";
+    return FSE_E_INVAL;
+  }
+  for (int64_t p = 0; p < sys->nnz2; ++p) {
+    const int32_t *ix = sys->t2_idx + 3 * p;
+    for (int a = 0; a < 3; ++a)
+      if (ix[a] < 0 || ix[a] >= n) {
+        ctx->err = "t2 index out of range";
+        return FSE_E_INVAL;
+      }
+    bw = std::max({bw, std::abs(ix[1] - ix[0]), std::abs(ix[2] - ix[0])});
+  }
+  for (int64_t p = 0; p < sys->nnz3; ++p) {
+    const int32_t *ix = sys->t3_idx + 4 * p;
+    for (int a = 0; a < 4; ++a)
+      if (ix[a] < 0 || ix[a] >= n) {
+        ctx->err = "t3 index out of range";
+        return FSE_E_INVAL;
+      }
+    bw = std::max({bw, std::abs(ix[1] - ix[0]), std::abs(ix[2] - ix[0]), std::abs(ix[3] - ix[0])});
+  }
+  ctx->bw = bw;
+  std::vector<double> Mb, Db, Kb;
+  FSE_TRY(csr_to_band(ctx, "M", M, n, bw, Mb));
+  FSE_TRY(csr_to_band(ctx, "D", D, n, bw, Db));
+  FSE_TRY(csr_to_band(ctx, "K", K, n, bw, Kb));
+
+  // f_nl rows (CSR by output index)
+  ctx->nnz2 = (int)sys->nnz2;
+  ctx->nnz3 = (int)sys->nnz3;
+  std::vector<int32_t> p2(n + 1, 0), p3(n + 1, 0);
+  for (int64_t p = 0; p < sys->nnz2; ++p) p2[sys->t2_idx[3 * p] + 1]++;
+  for (int64_t p = 0; p < sys->nnz3; ++p) p3[sys->t3_idx[4 * p] + 1]++;
+  for (int i = 0; i < n; ++i) {
+    p2[i + 1] += p2[i];
+    p3[i + 1] += p3[i];
+  }
+  std::vector<int32_t> jk((size_t)2 * sys->nnz2), jkl((size_t)3 * sys->nnz3);
+  std::vector<double> v2(sys->nnz2), v3(sys->nnz3);
+  {
+    std::vector<int32_t> c2(p2.begin(), p2.end() - 1), c3(p3.begin(), p3.end() - 1);
+    for (int64_t p = 0; p < sys->nnz2; ++p) {
+      const int32_t *ix = sys->t2_idx + 3 * p;
+      const int q = c2[ix[0]]++;
+      jk[2 * q] = ix[1];
+      jk[2 * q + 1] = ix[2];
+      v2[q] = sys->t2_val[p];
+    }
+    for (int64_t p = 0; p < sys->nnz3; ++p) {
+      const int32_t *ix = sys->t3_idx + 4 * p;
+      const int q = c3[ix[0]]++;
+      jkl[3 * q] = ix[1];
+      jkl[3 * q + 1] = ix[2];
+      jkl[3 * q + 2] = ix[3];
+      v3[q] = sys->t3_val[p];
+    }
+  }
+  // tangent contributions to the lower band, position p = m*(bw+1) + (i-m)
+  const int bp = bw + 1;
+  std::vector<std::vector<std::pair<double, std::pair<int, int>>>> con((size_t)n * bp);
+  auto add = [&](int i, int m, double c, int a, int b) {
+    if (i >= m) con[(size_t)m * bp + (i - m)].push_back({c, {a, b}});
+  };
+  for (int64_t p = 0; p < sys->nnz2; ++p) {
+    const int32_t *ix = sys->t2_idx + 3 * p;
+    const double v = sys->t2_val[p];
+    add(ix[0], ix[1], v, ix[2], -1);
+    add(ix[0], ix[2], v, ix[1], -1);
+  }
+  for (int64_t p = 0; p < sys->nnz3; ++p) {
+    const int32_t *ix = sys->t3_idx + 4 * p;
+    const double v = sys->t3_val[p];
+    add(ix[0], ix[1], v, ix[2], ix[3]);
+    add(ix[0], ix[2], v, ix[1], ix[3]);
+    add(ix[0], ix[3], v, ix[1], ix[2]);
+  }
+  std::vector<int32_t> ktp((size_t)n * bp + 1, 0), kti;
+  std::vector<double> ktc;
+  for (size_t q = 0; q < con.size(); ++q) {
+    ktp[q + 1] = ktp[q] + (int32_t)con[q].size();
+    for (auto &c : con[q]) {
+      ktc.push_back(c.first);
+      kti.push_back(c.second.first);
+      kti.push_back(c.second.second);
+    }
+  }
+  // the tangent must be symmetric (potential forces): check at a random state
+  if (sys->nnz2 + sys->nnz3 > 0) {
+    std::mt19937_64 rng(12345);
+    std::uniform_real_distribution<double> uni(-1.0, 1.0);
+    std::vector<double> q(n);
+    for (auto &v : q) v = uni(rng);
+    std::map<std::pair<int, int>, double> kt;
+    for (int64_t p = 0; p < sys->nnz2; ++p) {
+      const int32_t *ix = sys->t2_idx + 3 * p;
+      const double v = sys->t2_val[p];
+      kt[{ix[0], ix[1]}] += v * q[ix[2]];
+      kt[{ix[0], ix[2]}] += v * q[ix[1]];
+    }
+    for (int64_t p = 0; p < sys->nnz3; ++p) {
+      const int32_t *ix = sys->t3_idx + 4 * p;
+      const double v = sys->t3_val[p];
+      kt[{ix[0], ix[1]}] += v * q[ix[2]] * q[ix[3]];
+      kt[{ix[0], ix[2]}] += v * q[ix[1]] * q[ix[3]];
+      kt[{ix[0], ix[3]}] += v * q[ix[1]] * q[ix[2]];
+    }
+    double mx = 0.0;
+    for (auto &kv : kt) mx = std::max(mx, std::abs(kv.second));
+    for (auto &kv : kt) {
+      auto it = kt.find({kv.first.second, kv.first.first});
+      const double other = it == kt.end() ? 0.0 : it->second;
+      if (std::abs(kv.second - other) > 1e-9 * mx) {
+        ctx->err = "tangent of f_nl is not symmetric (forces must derive from a potential)";
+        return FSE_E_UNSUPPORTED;
+      }
+    }
+  }
+
+  // ---- uploads
+  FSE_TRY(upload(ctx, &ctx->Mb, Mb));
+  FSE_TRY(upload(ctx, &ctx->Db, Db));
+  FSE_TRY(upload(ctx, &ctx->Kb, Kb));
+  FSE_TRY(upload(ctx, &ctx->F, std::vector<double>(sys->F, sys->F + (size_t)sys->e * n)));
+  FSE_TRY(upload(ctx, &ctx->f2_ptr, p2));
+  FSE_TRY(upload(ctx, &ctx->f2_jk, jk));
+  FSE_TRY(upload(ctx, &ctx->f2_v, v2));
+  FSE_TRY(upload(ctx, &ctx->f3_ptr, p3));
+  FSE_TRY(upload(ctx, &ctx->f3_jkl, jkl));
+  FSE_TRY(upload(ctx, &ctx->f3_v, v3));
+  FSE_TRY(upload(ctx, &ctx->kt_ptr, ktp));
+  FSE_TRY(upload(ctx, &ctx->kt_idx, kti));
+  FSE_TRY(upload(ctx, &ctx->kt_c, ktc));
+  FSE_TRY(upload(ctx, &ctx->G_d, ctx->G));
+  FSE_TRY(upload(ctx, &ctx->Gi_d, ctx->Gi));
+  FSE_TRY(upload(ctx, &ctx->sidx_d, ctx->sidx));
+  FSE_TRY(upload(ctx, &ctx->Sdim_d, ctx->Sdim.empty() ? std::vector<int32_t>{1} : ctx->Sdim));
+  FSE_TRY(upload(ctx, &ctx->ktable_d, ctx->ktable));
+
+  // ---- work buffers
+  ctx->Wmax = ctx->Bmax * ctx->St;
+  const size_t W = ctx->Wmax;
+  FSE_TRY(alloc(ctx, (void **)&ctx->omega_d, sizeof(double) * ctx->Bmax * ctx->d));
+  FSE_TRY(alloc(ctx, (void **)&ctx->qhist, sizeof(double) * (size_t)(ctx->S1 + 1) * n * W));
+  FSE_TRY(alloc(ctx, (void **)&ctx->u0, sizeof(double) * (size_t)n * W));
+  FSE_TRY(alloc(ctx, (void **)&ctx->zTw, sizeof(double) * (size_t)2 * n * W));
+  FSE_TRY(alloc(ctx, (void **)&ctx->status_d, sizeof(DevStatus)));
+  FSE_TRY(alloc(ctx, (void **)&ctx->rot_d, sizeof(double) * ctx->Bmax * std::max(ctx->L, 1)));
+  FSE_TRY(alloc(ctx, (void **)&ctx->work_R, sizeof(double) * ctx->Bmax * 2 * n * ctx->U));
+  FSE_TRY(alloc(ctx, (void **)&ctx->Zwork, sizeof(double) * std::max(ctx->Bmax, 2) * 2 * n * ctx->U));
+  FSE_TRY(alloc(ctx, (void **)&ctx->norm_d, sizeof(double) * ctx->Bmax));
+  for (auto &e : ctx->ev) FSE_HIP(hipEventCreate(&e));
+  return FSE_OK;
+}
+
+void free_all(fse_ctx *ctx) {
+  void *ptrs[] = {ctx->Mb, ctx->Db, ctx->Kb, ctx->F, ctx->f2_ptr, ctx->f2_jk, ctx->f2_v,
+                  ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v, ctx->kt_ptr, ctx->kt_idx, ctx->kt_c,
+                  ctx->G_d, ctx->Gi_d, ctx->sidx_d, ctx->Sdim_d, ctx->ktable_d, ctx->omega_d,
+                  ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
+                  ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
+                  ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
+                  ctx->Sp, ctx->Mwp, ctx->Dwp};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto &e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+}
+
+fse_status check_status(fse_ctx *ctx) {
+  DevStatus st;
+  FSE_HIP(hipMemcpyAsync(&st, ctx->status_d, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->last_max_iters = st.max_iters;
+  ctx->last_total_iters = st.total_iters;
+  if (st.flags & DEV_SINGULAR) {
+    ctx->err = "zero or non-finite pivot in a banded factorisation";
+    return FSE_E_SINGULAR;
+  }
+  if (st.flags & DEV_NOCONV) {
+    ctx->err = "per-step Newton did not converge (first failing step " + std::to_string(st.first_step) + ")";
+    return FSE_E_NOCONV;
+  }
+  if (st.flags & DEV_NAN) {
+    ctx->err = "non-finite state during integration";
+    return FSE_E_NAN;
+  }
+  return FSE_OK;
+}
+
+fse_status upload_omega(fse_ctx *ctx, int B, const double *omega) {
+  if (!omega) {
+    ctx->err = "omega is null";
+    return FSE_E_INVAL;
+  }
+  for (int b = 0; b < B * ctx->d; ++b)
+    if (!(omega[b] > 0.0) || !std::isfinite(omega[b])) {
+      ctx->err = "omega must be finite and positive";
+      return FSE_E_INVAL;
+    }
+  FSE_HIP(hipMemcpyAsync(ctx->omega_d, omega, sizeof(double) * B * ctx->d, hipMemcpyHostToDevice,
+                         ctx->stream));
+  // rotation angles alpha_l = 2 pi k~_l . rho (Eq. 14), rho_j = omega_j / omega_1
+  std::vector<double> rot((size_t)B * std::max(ctx->L, 1), 0.0);
+  const int dm1 = ctx->d - 1;
+  for (int b = 0; b < B; ++b)
+    for (int l = 0; l < ctx->L; ++l) {
+      double a = 0.0;
+      for (int j = 0; j < dm1; ++j)
+        a += (double)ctx->ktable[(size_t)l * dm1 + j] * (omega[b * ctx->d + 1 + j] / omega[b * ctx->d]);
+      rot[(size_t)b * std::max(ctx->L, 1) + l] = 2.0 * M_PI * a;
+    }
+  FSE_HIP(hipMemcpyAsync(ctx->rot_d, rot.data(), sizeof(double) * rot.size(), hipMemcpyHostToDevice,
+                         ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double *Z0, double *zT,
+                          double *Phi) {
+  if (B < 1 || B > ctx->Bmax || !Z0) {
+    ctx->err = "B out of range [1, max_batch] or Z0 null";
+    return FSE_E_INVAL;
+  }
+  FSE_TRY(upload_omega(ctx, B, omega));
+  FSE_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+  FSE_TRY(launch_idft(ctx, B, Z0));
+  FSE_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+  const bool fused = ctx->use_fused && fused_supported(ctx);
+  if (fused) {
+    FSE_TRY(launch_fused(ctx, B, Phi));
+    FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
+  } else {
+    FSE_TRY(launch_state(ctx, B));
+    FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
+    if (Phi) FSE_TRY(launch_sens(ctx, B, Phi));
+  }
+  FSE_HIP(hipEventRecord(ctx->ev[3], ctx->stream));
+  if (zT) {
+    // zTw is [2n][Wmax]; caller layout [B][2n][S~]
+    const int n2 = 2 * ctx->n;
+    for (int b = 0; b < B; ++b)
+      FSE_HIP(hipMemcpy2DAsync(zT + (size_t)b * n2 * ctx->St, sizeof(double) * ctx->St,
+                               ctx->zTw + (size_t)b * ctx->St, sizeof(double) * ctx->Wmax,
+                               sizeof(double) * ctx->St, n2, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  FSE_HIP(hipEventRecord(ctx->ev[4], ctx->stream));
+  FSE_HIP(hipEventSynchronize(ctx->ev[4]));
+  float t_all = 0, t_idft = 0, t_state = 0, t_sens = 0;
+  FSE_HIP(hipEventElapsedTime(&t_all, ctx->ev[0], ctx->ev[4]));
+  FSE_HIP(hipEventElapsedTime(&t_idft, ctx->ev[0], ctx->ev[1]));
+  FSE_HIP(hipEventElapsedTime(&t_state, ctx->ev[1], ctx->ev[2]));
+  FSE_HIP(hipEventElapsedTime(&t_sens, ctx->ev[2], ctx->ev[3]));
+  ctx->last_ms[0] = t_all;
+  ctx->last_ms[1] = t_state;
+  ctx->last_ms[2] = t_sens;
+  ctx->last_ms[3] = t_idft;
+  return check_status(ctx);
+}
+
+fse_status ensure_phi(fse_ctx *ctx) {
+  if (!ctx->PhiQU) {
+    const size_t W = ctx->Wmax, n = ctx->n;
+    FSE_TRY(alloc(ctx, (void **)&ctx->PhiQU, sizeof(double) * W * 4 * n * n));
+  }
+  return FSE_OK;
+}
+
+}  // namespace
+
+// ============================================================================= C-ABI
+extern "C" {
+
+fse_status fse_init_torus(const fse_system *sys, const fse_torus_desc *desc, fse_ctx **out) {
+  if (!out) return FSE_E_INVAL;
+  *out = nullptr;
+  fse_ctx *ctx = new (std::nothrow) fse_ctx();
+  if (!ctx) return FSE_E_NOMEM;
+  fse_status s = init_impl(sys, desc, ctx);
+  if (s != FSE_OK) {
+    // keep the context alive so that fse_last_error can report; caller destroys it
+    *out = ctx;
+    return s;
+  }
+  *out = ctx;
+  return FSE_OK;
+}
+
+fse_status fse_get_layout(const fse_ctx *ctx, int32_t *U, int32_t *Stilde, int32_t *half_band,
+                          int32_t *ktable) {
+  if (!ctx) return FSE_E_INVAL;
+  if (U) *U = ctx->U;
+  if (Stilde) *Stilde = ctx->St;
+  if (half_band) *half_band = ctx->bw;
+  if (ktable && ctx->d > 1) std::memcpy(ktable, ctx->ktable.data(), sizeof(int32_t) * ctx->ktable.size());
+  return FSE_OK;
+}
+
+fse_status fse_set_stream(fse_ctx *ctx, void *hip_stream) {
+  if (!ctx) return FSE_E_INVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return FSE_OK;
+}
+
+fse_status fse_integrate_batch(fse_ctx *ctx, int32_t B, const double *omega, const double *Z0,
+                               double *zT, double *Phi) {
+  if (!ctx) return FSE_E_INVAL;
+  return integrate_impl(ctx, B, omega, Z0, zT, Phi);
+}
+
+fse_status fse_step_stats(const fse_ctx *ctx, int32_t *max_iters, int64_t *total_iters) {
+  if (!ctx) return FSE_E_INVAL;
+  if (max_iters) *max_iters = ctx->last_max_iters;
+  if (total_iters) *total_iters = (int64_t)ctx->last_total_iters;
+  return FSE_OK;
+}
+
+fse_status fse_shooting_residual_jacobian(fse_ctx *ctx, int32_t B, const double *omega,
+                                          const double *Z0, double *R, double *rnorm, double *J,
+                                          double *dRdw) {
+  if (!ctx) return FSE_E_INVAL;
+  if (!R) {
+    ctx->err = "R must not be null";
+    return FSE_E_INVAL;
+  }
+  if (dRdw) {
+    ctx->err = "dR/domega is not available in this build (pass NULL)";
+    return FSE_E_UNSUPPORTED;
+  }
+  double *phi = nullptr;
+  if (J) {
+    FSE_TRY(ensure_phi(ctx));
+    phi = ctx->PhiQU;
+  }
+  FSE_TRY(integrate_impl(ctx, B, omega, Z0, nullptr, phi));
+  FSE_TRY(launch_dft_residual(ctx, B, Z0, R));
+  if (rnorm) FSE_TRY(launch_norms(ctx, B, R, rnorm));
+  if (J) FSE_TRY(launch_jacobian(ctx, B, phi, J));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status fse_newton_step(fse_ctx *ctx, const double *omega, double *Z0, double *res_norm) {
+  if (!ctx || !Z0) return FSE_E_INVAL;
+  const size_t N = (size_t)2 * ctx->n * ctx->U;
+  if (!ctx->Jw) {
+    FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * N * N));
+    ctx->Jw_elems = N * N;
+  }
+  double rn = 0.0;
+  FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &rn, ctx->Jw, nullptr));
+  if (res_norm) *res_norm = rn;
+  // J dZ = -R  ->  solve J x = R in place, then Z0 -= x
+  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, (int)N, ctx->work_R));
+  FSE_TRY(launch_axpy(ctx, (int)N, -1.0, ctx->work_R, Z0));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, double tol, int32_t maxit,
+                            int32_t *iters, double *res_norm) {
+  if (!ctx || !Z0) return FSE_E_INVAL;
+  const int N = 2 * ctx->n * ctx->U;
+  double rn = INFINITY;
+  FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &rn, nullptr, nullptr));
+  int it = 0;
+  for (; it < maxit && !(rn < tol); ++it) {
+    // full Newton direction dZ = -J^-1 R at Z0 (work_R holds J^-1 R after the solve)
+    if (!ctx->Jw) {
+      FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * (size_t)N * N));
+      ctx->Jw_elems = (size_t)N * N;
+    }
+    double r0 = 0.0;
+    FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &r0, ctx->Jw, nullptr));
+    FSE_TRY(dense_lu_solve(ctx, ctx->Jw, N, ctx->work_R));
+    // backtracking on ||R||: accept Z - lambda J^-1 R once the residual decreases
+    double lam = 1.0;
+    bool accepted = false;
+    for (int ls = 0; ls < 8 && !accepted; ++ls, lam *= 0.5) {
+      FSE_TRY(launch_lincomb(ctx, N, Z0, -lam, ctx->work_R, ctx->Zwork));
+      double rt = INFINITY;
+      const fse_status st = fse_shooting_residual_jacobian(ctx, 1, omega, ctx->Zwork, ctx->Zwork + N, &rt,
+                                                           nullptr, nullptr);
+      if (st != FSE_OK && st != FSE_E_NOCONV && st != FSE_E_NAN && st != FSE_E_SINGULAR) return st;
+      if (st == FSE_OK && rt < (1.0 - 1e-4 * lam) * rn) {
+        FSE_HIP(hipMemcpyAsync(Z0, ctx->Zwork, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+        FSE_HIP(hipStreamSynchronize(ctx->stream));
+        rn = rt;
+        accepted = true;
+      }
+    }
+    if (!accepted) {
+      if (iters) *iters = it;
+      if (res_norm) *res_norm = rn;
+      ctx->err = "Newton line search failed to reduce the residual";
+      return FSE_E_NOCONV;
+    }
+  }
+  if (iters) *iters = it;
+  if (res_norm) *res_norm = rn;
+  if (!(rn < tol)) {
+    ctx->err = "Newton did not reach the residual tolerance";
+    return FSE_E_NOCONV;
+  }
+  return FSE_OK;
+}
+
+fse_status fse_lyapunov(fse_ctx *ctx, const double *omega, const double *Z0, int32_t N_Ly,
+                        const double *Q0, double *sigma) {
+  if (!ctx || !Z0 || !sigma || N_Ly < 1) return FSE_E_INVAL;
+  FSE_TRY(ensure_phi(ctx));
+  FSE_TRY(integrate_impl(ctx, 1, omega, Z0, nullptr, ctx->PhiQU));
+  return lyapunov_qr(ctx, ctx->PhiQU, omega, N_Ly, Q0, sigma);
+}
+
+fse_status fse_last_timing(const fse_ctx *ctx, double *ms4, int32_t *launches_out) {
+  if (!ctx) return FSE_E_INVAL;
+  if (ms4)
+    for (int i = 0; i < 4; ++i) ms4[i] = ctx->last_ms[i];
+  if (launches_out) *launches_out = ctx->last_sens_launches;
+  return FSE_OK;
+}
+
+const char *fse_last_error(const fse_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void fse_destroy(fse_ctx *ctx) {
+  if (!ctx) return;
+  free_all(ctx);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations of the FSE-Shooting HIP library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fse.h"
+
+// ----------------------------------------------------------------------------- errors
+#define FSE_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ctx->err = std::string("HIP error ") + hipGetErrorString(e_) + " at " +       \
+                 __FILE__ + ":" + std::to_string(__LINE__);                        \
+      return FSE_E_DEVICE;                                                         \
+    }                                                                              \
+  } while (0)
+
+#define FSE_TRY(expr)                  \
+  do {                                 \
+    fse_status s_ = (expr);            \
+    if (s_ != FSE_OK) return s_;       \
+  } while (0)
+
+// Device status word bits written by kernels (host reads after the stream syncs).
+enum : int {
+  DEV_OK = 0,
+  DEV_NOCONV = 1,      // per-step Newton exceeded maxit
+  DEV_SINGULAR = 2,    // zero or non-finite pivot
+  DEV_NAN = 4,         // non-finite state
+};
+
+struct DevStatus {
+  int flags;           // OR of DEV_* bits
+  int first_step;      // smallest step index that raised DEV_NOCONV (or INT_MAX)
+  int max_iters;       // largest per-step Newton iteration count
+  int pad;
+  unsigned long long total_iters;
+};
+
+// Per-call problem parameters passed to the trajectory kernels by value.
+struct TrajParams {
+  int n, bw, S1, e, d, St, W;   // sizes; W = B * St trajectories
+  int maxit;
+  double tol;
+  double h, c0, c1, c2;
+};
+
+struct fse_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // sizes
+  int n = 0, e = 0, d = 0, S1 = 0, U = 0, L = 0, St = 0, bw = 0;
+  int Bmax = 1, prec = 0, maxit = 30;
+  double tol = 1e-12;
+  int Wmax = 0;
+  int nnz2 = 0, nnz3 = 0;
+
+  // host tables
+  std::vector<int32_t> ktable;      // [(L+1)][d-1]
+  std::vector<int32_t> sidx;        // [d-1][St]
+  std::vector<int32_t> Sdim;        // [d-1]
+  std::vector<double> G, Gi;        // [St][U], [U][St]
+
+  // device: system (banded full rows [n][2bw+1])
+  double *Mb = nullptr, *Db = nullptr, *Kb = nullptr;
+  double *F = nullptr;              // [e][n]
+  // f_nl by output row: CSR over t2 (j,k,v) and t3 (j,k,l,v)
+  int32_t *f2_ptr = nullptr, *f2_jk = nullptr;  double *f2_v = nullptr;
+  int32_t *f3_ptr = nullptr, *f3_jkl = nullptr; double *f3_v = nullptr;
+  // tangent lower band: contributions per entry p = m*(bw+1) + (i-m)
+  int32_t *kt_ptr = nullptr, *kt_idx = nullptr;  double *kt_c = nullptr;  // idx pairs (p, r or -1)
+  // torus
+  double *G_d = nullptr, *Gi_d = nullptr;
+  int32_t *sidx_d = nullptr, *Sdim_d = nullptr, *ktable_d = nullptr;
+
+  // device work buffers (sized for Bmax points)
+  double *omega_d = nullptr;        // [Bmax][d]
+  double *qhist = nullptr;          // [S1+1][n][Wmax]
+  double *u0 = nullptr;             // [n][Wmax]
+  double *zTw = nullptr;            // [2n][Wmax]
+  double *state_scr = nullptr;      // per trajectory scratch for large systems
+  double *PhiA = nullptr;           // [Wmax][n][2n]
+  double *PhiQU = nullptr;          // [Wmax][2n][2n] internal when caller passes none
+  double *sens_scr = nullptr;       // per block factor + per column y
+  size_t sens_scr_elems = 0;
+  DevStatus *status_d = nullptr;
+  double *rot_d = nullptr;          // [Bmax][L] rotation angles alpha_l
+  double *work_R = nullptr;         // [Bmax][2n][U]
+  double *Zwork = nullptr;          // [Bmax][2n][U]
+  double *Jw = nullptr;             // dense Jacobian / LU workspace [2nU][2nU]
+  int32_t *piv_d = nullptr;
+  double *lu_scr = nullptr;
+  double *norm_d = nullptr;         // [Bmax] squared residual norms
+  double *jacP = nullptr;           // [S~][U][U] Jacobian right factor
+  double *sens_gscr = nullptr;      // factor scratch when it does not fit in LDS
+  size_t sens_gscr_elems = 0;
+  size_t Jw_elems = 0;
+
+  // fused trajectory kernel: padded per-point bands [Bmax][n][2BW+1]
+  double *Sp = nullptr, *Mwp = nullptr, *Dwp = nullptr;
+  size_t fused_band_elems = 0;
+  bool use_fused = false;
+
+  // tuning
+  int sens_cols = 64;               // columns per sensitivity work-group (generic kernel)
+  int fused_ncw = 1;                // column waves per fused work-group
+
+  // timing of the last integration
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double last_ms[4] = {0, 0, 0, 0};
+  int last_sens_launches = 0;
+  int last_max_iters = 0;
+  unsigned long long last_total_iters = 0;
+};
+
+// ----------------------------------------------------------------------------- launches
+// Trajectory integration (k_traj.hip)
+fse_status reset_status(fse_ctx *ctx);
+fse_status launch_idft(fse_ctx *ctx, int B, const double *Z0);
+fse_status launch_state(fse_ctx *ctx, int B);
+fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU);
+fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R);
+fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J);
+fse_status launch_dRdw(fse_ctx *ctx, int B, const double *Z0, double *dRdw);
+fse_status launch_norms(fse_ctx *ctx, int B, const double *R, double *out_host);
+// Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16
+bool fused_supported(const fse_ctx *ctx);
+fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);
+// Dense linear algebra (k_linalg.hip)
+fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
+fse_status launch_axpy(fse_ctx *ctx, int N, double alpha, const double *x, double *y);
+fse_status launch_lincomb(fse_ctx *ctx, int N, const double *x, double alpha, const double *d, double *y);
+fse_status lyapunov_qr(fse_ctx *ctx, const double *PhiQU, const double *omega_h, int N_Ly,
+                       const double *Q0, double *sigma_h);

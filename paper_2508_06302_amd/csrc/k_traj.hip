@@ -1,0 +1,742 @@
+// Trajectory kernels of FSE-Shooting on gfx950 (Sec. 3.3 steps 2-5, App. E).
+//
+// Layouts (W = B * S~ trajectories, trajectory index w = b * S~ + s, arrays
+// strided by Wmax so that consecutive trajectories are contiguous):
+//   qhist [S1+1][n][Wmax]   displacement history written by the state kernel
+//   u0    [n][Wmax]         initial velocities u = dq/dphi_1
+//   zTw   [2n][Wmax]        terminal samples [q; u](2 pi)
+//   Phi   [W][2n][2n]       [Q; U] sensitivities (rows), columns fastest
+//   PhiA  [W][n][2n]        A = dQ''/dz0 (Newmark acceleration sensitivities)
+// Banded matrices are stored as full rows [n][2bw+1] (entry (i,j) at
+// [i][j-i+bw]); a banded LDL^T factor is stored by columns [n][bw+1] with
+// entry (j+r, j) at [j][r] (r = 0 holds the pivot d_j).
+#include <climits>
+#include <cmath>
+
+#include "fse_internal.h"
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+__device__ inline double warp_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// max over the block; red must hold blockDim.x / 64 doubles; all threads get the result
+__device__ double block_max(double v, double *red) {
+  v = warp_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double r = red[0];
+  for (int i = 1; i < nw; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+__device__ inline void pair_rc(int p, int &r, int &c) {
+  int rr = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+  while (rr * (rr - 1) / 2 > p) --rr;
+  while ((rr + 1) * rr / 2 <= p) ++rr;
+  r = rr;
+  c = p - rr * (rr - 1) / 2 + 1;
+}
+
+// In-place banded LDL^T of the lower band Lf (column storage, see file header),
+// cooperative over the block; right-looking, one barrier per column.
+__device__ void band_ldlt(double *Lf, int n, int bw, DevStatus *st) {
+  const int bp = bw + 1;
+  const int npairs = bw * (bw + 1) / 2;
+  bool bad = false;
+  for (int j = 0; j < n; ++j) {
+    const double dj = Lf[j * bp];
+    if (!(dj != 0.0) || !isfinite(dj)) bad = true;
+    const double inv = 1.0 / dj;
+    for (int p = threadIdx.x; p < npairs; p += blockDim.x) {
+      int r, c;
+      pair_rc(p, r, c);
+      if (j + r < n) Lf[(j + c) * bp + (r - c)] -= Lf[j * bp + r] * Lf[j * bp + c] * inv;
+    }
+    __syncthreads();
+    for (int r = 1 + threadIdx.x; r <= bw; r += blockDim.x)
+      if (j + r < n) Lf[j * bp + r] *= inv;
+  }
+  __syncthreads();
+  if (bad && threadIdx.x == 0) atomicOr(&st->flags, (int)DEV_SINGULAR);
+}
+
+// Solve L D L^T x = r for one right-hand side held in x (in place), executed by
+// thread 0 (band factor and x in block-shared memory).
+__device__ void band_solve_serial(const double *Lf, int n, int bw, double *x) {
+  const int bp = bw + 1;
+  for (int i = 0; i < n; ++i) {
+    double y = x[i];
+    const int t0 = i < bw ? i : bw;
+    for (int t = t0; t >= 1; --t) y -= Lf[(i - t) * bp + t] * x[i - t];
+    x[i] = y;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double v = x[i] / Lf[i * bp];
+    const int t1 = (n - 1 - i) < bw ? (n - 1 - i) : bw;
+    for (int t = t1; t >= 1; --t) v -= Lf[i * bp + t] * x[i + t];
+    x[i] = v;
+  }
+}
+
+// Block-cooperative version for wide bands: every row's dot product is split over the block.
+__device__ void band_solve_block(const double *Lf, int n, int bw, double *x, double *red) {
+  const int bp = bw + 1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < n; ++i) {
+    double part = 0.0;
+    const int t0 = i < bw ? i : bw;
+    for (int t = 1 + threadIdx.x; t <= t0; t += blockDim.x) part += Lf[(i - t) * bp + t] * x[i - t];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) red[wid] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < nw; ++k) s += red[k];
+      x[i] -= s;
+    }
+    __syncthreads();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double part = 0.0;
+    const int t1 = (n - 1 - i) < bw ? (n - 1 - i) : bw;
+    for (int t = 1 + threadIdx.x; t <= t1; t += blockDim.x) part += Lf[i * bp + t] * x[i + t];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) red[wid] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int k = 0; k < nw; ++k) s += red[k];
+      x[i] = x[i] / Lf[i * bp] - s;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline void band_solve(const double *Lf, int n, int bw, double *x, double *red) {
+  if (bw <= 24) {
+    if (threadIdx.x == 0) band_solve_serial(Lf, n, bw, x);
+    __syncthreads();
+  } else {
+    band_solve_block(Lf, n, bw, x, red);
+  }
+}
+
+struct SysDev {
+  const double *Mb, *Db, *Kb, *F;
+  const int32_t *f2_ptr, *f2_jk;
+  const double *f2_v;
+  const int32_t *f3_ptr, *f3_jkl;
+  const double *f3_v;
+  const int32_t *kt_ptr, *kt_idx;
+  const double *kt_c;
+};
+
+// f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l (row i of the CSR-by-output tensors)
+__device__ inline double fnl_row(const SysDev &sy, const double *q, int i) {
+  double f = 0.0;
+  for (int p = sy.f2_ptr[i]; p < sy.f2_ptr[i + 1]; ++p)
+    f += sy.f2_v[p] * q[sy.f2_jk[2 * p]] * q[sy.f2_jk[2 * p + 1]];
+  for (int p = sy.f3_ptr[i]; p < sy.f3_ptr[i + 1]; ++p)
+    f += sy.f3_v[p] * q[sy.f3_jkl[3 * p]] * q[sy.f3_jkl[3 * p + 1]] * q[sy.f3_jkl[3 * p + 2]];
+  return f;
+}
+
+// K_t(q) at lower-band position pos = m*(bw+1) + (i-m)
+__device__ inline double kt_entry(const SysDev &sy, const double *q, int pos) {
+  double v = 0.0;
+  for (int p = sy.kt_ptr[pos]; p < sy.kt_ptr[pos + 1]; ++p) {
+    const int a = sy.kt_idx[2 * p], b = sy.kt_idx[2 * p + 1];
+    v += sy.kt_c[p] * q[a] * (b >= 0 ? q[b] : 1.0);
+  }
+  return v;
+}
+
+// Forcing cosines at phi_1 for sample s (Eq. E1): forcing 0 has argument phi_1,
+// forcing f >= 1 has phi_{f+1,s} + rho_{f+1} phi_1.
+__device__ inline double forcing_cos(int f, double phi1, const double *om, const int32_t *sidx,
+                                     const int32_t *Sdim, int St, int s) {
+  if (f == 0) return cos(phi1);
+  const double ph = kTwoPi * (double)sidx[(f - 1) * St + s] / (double)Sdim[f - 1];
+  return cos(ph + om[f] / om[0] * phi1);
+}
+
+__global__ void k_reset_status(DevStatus *st, int first_step) {
+  if (threadIdx.x == 0) {
+    st->flags = 0;
+    st->first_step = first_step;
+    st->max_iters = 0;
+    st->pad = 0;
+    st->total_iters = 0ull;
+  }
+}
+
+// ------------------------------------------------------------------------ inverse DFT (Eq. 20)
+__global__ void k_idft(const double *__restrict__ Z0, const double *__restrict__ G, int n, int U,
+                       int St, int W, int ldw, double *__restrict__ q0, double *__restrict__ u0) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;  // state row 0..2n-1
+  if (w >= W) return;
+  const int b = w / St, s = w - (w / St) * St;
+  const double *z = Z0 + ((size_t)b * 2 * n + i) * U;
+  const double *g = G + (size_t)s * U;
+  double v = 0.0;
+  for (int l = 0; l < U; ++l) v += g[l] * z[l];
+  if (i < n)
+    q0[(size_t)i * ldw + w] = v;
+  else
+    u0[(size_t)(i - n) * ldw + w] = v;
+}
+
+// ------------------------------------------------------------------------ state integration
+// One block per trajectory: average-acceleration Newmark (Eqs. E4-E7) with full-tangent
+// Newton on Eq. (E6) at every step.  Writes the displacement history for the
+// sensitivity kernel and the terminal state.
+template <bool LDS>
+__global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omega,
+                        const int32_t *__restrict__ sidx, const int32_t *__restrict__ Sdim,
+                        double *__restrict__ qhist, const double *__restrict__ u0,
+                        double *__restrict__ zT, int ldw, double *__restrict__ gscr,
+                        DevStatus *st) {
+  extern __shared__ double smem[];
+  const int n = P.n, bw = P.bw, bp = bw + 1, w = blockIdx.x;
+  const size_t stride = (size_t)n * bp + 8 * (size_t)n + 80;
+  double *base = LDS ? smem : gscr + (size_t)w * stride;
+  double *Lf = base;
+  double *q = Lf + (size_t)n * bp;
+  double *u = q + n;
+  double *a = u + n;
+  double *qn = a + n;
+  double *bv = qn + n;
+  double *r = bv + n;
+  double *cs = r + 2 * n;        // e cosines (<= 8)
+  double *red = cs + 8;          // block reduction scratch (<= 64)
+  const int b = w / P.St, s = w - b * P.St;
+  const double *om = omega + b * P.d;
+  const double w1 = om[0];
+  const double w1s = w1 * w1;
+  const int W2 = 2 * bw + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  for (int i = tid; i < n; i += nt) {
+    q[i] = qhist[(size_t)i * ldw + w];
+    u[i] = u0[(size_t)i * ldw + w];
+  }
+  if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s);
+  __syncthreads();
+  // consistent initial acceleration: (w1^2 M) a0 = e0 - w1 D u0 - K q0 - f_nl(q0)
+  for (int i = tid; i < n; i += nt) {
+    double v = 0.0;
+    for (int f = 0; f < P.e; ++f) v += sy.F[(size_t)f * n + i] * cs[f];
+    const int j0 = i - bw;
+    for (int t = 0; t < W2; ++t) {
+      const int j = j0 + t;
+      if (j < 0 || j >= n) continue;
+      v -= w1 * sy.Db[(size_t)i * W2 + t] * u[j] + sy.Kb[(size_t)i * W2 + t] * q[j];
+    }
+    a[i] = v - fnl_row(sy, q, i);
+  }
+  for (int pos = tid; pos < n * bp; pos += nt) {
+    const int m = pos / bp, t = pos - m * bp, i = m + t;
+    Lf[pos] = i < n ? w1s * sy.Mb[(size_t)i * W2 + (bw - t)] : 0.0;
+  }
+  __syncthreads();
+  band_ldlt(Lf, n, bw, st);
+  band_solve(Lf, n, bw, a, red);
+
+  int max_it = 0;
+  unsigned long long tot_it = 0;
+  bool failed = false;
+  for (int k = 0; k < P.S1; ++k) {
+    const double phi1 = (double)(k + 1) * P.h;
+    if (tid < P.e) cs[tid] = forcing_cos(tid, phi1, om, sidx, Sdim, P.St, s);
+    __syncthreads();
+    // b_k (Eq. E7) and the predictor
+    for (int i = tid; i < n; i += nt) {
+      double v = 0.0;
+      for (int f = 0; f < P.e; ++f) v += sy.F[(size_t)f * n + i] * cs[f];
+      const int j0 = i - bw;
+      for (int t = 0; t < W2; ++t) {
+        const int j = j0 + t;
+        if (j < 0 || j >= n) continue;
+        v += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * q[j] + P.c1 * u[j] + a[j]) +
+             w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * q[j] + u[j]);
+      }
+      bv[i] = v;
+      qn[i] = q[i] + P.h * u[i] + 0.5 * P.h * P.h * a[i];
+    }
+    __syncthreads();
+    double prev = INFINITY;
+    bool conv = false;
+    int it = 0;
+    for (; it < P.maxit && !conv; ++it) {
+      // residual r = S qn + f_nl(qn) - b and tangent band S + K_t(qn)
+      for (int i = tid; i < n; i += nt) {
+        double v = -bv[i] + fnl_row(sy, qn, i);
+        const int j0 = i - bw;
+        for (int t = 0; t < W2; ++t) {
+          const int j = j0 + t;
+          if (j < 0 || j >= n) continue;
+          const double sij = w1s * P.c0 * sy.Mb[(size_t)i * W2 + t] +
+                             w1 * P.c2 * sy.Db[(size_t)i * W2 + t] + sy.Kb[(size_t)i * W2 + t];
+          v += sij * qn[j];
+        }
+        r[i] = v;
+      }
+      for (int pos = tid; pos < n * bp; pos += nt) {
+        const int m = pos / bp, t = pos - m * bp, i = m + t;
+        double v = 0.0;
+        if (i < n) {
+          const size_t e = (size_t)i * W2 + (bw - t);
+          v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, pos);
+        }
+        Lf[pos] = v;
+      }
+      __syncthreads();
+      band_ldlt(Lf, n, bw, st);
+      band_solve(Lf, n, bw, r, red);
+      double nd = 0.0, nq = 0.0;
+      for (int i = tid; i < n; i += nt) {
+        const double dq = r[i];
+        const double v = qn[i] - dq;
+        qn[i] = v;
+        nd = fmax(nd, fabs(dq));
+        nq = fmax(nq, fabs(v));
+      }
+      nd = block_max(nd, red);
+      nq = block_max(nq, red);
+      if (!(nd == nd) || !(nq == nq)) break;
+      if (nd <= P.tol * nq || (nd <= 1e3 * P.tol * nq && nd > 0.5 * prev)) conv = true;
+      prev = nd;
+    }
+    if (!conv && !failed) {
+      failed = true;
+      if (tid == 0) {
+        atomicOr(&st->flags, (int)DEV_NOCONV);
+        atomicMin(&st->first_step, k);
+      }
+    }
+    max_it = it > max_it ? it : max_it;
+    tot_it += it;
+    // Eq. (E5) and the history for the sensitivity pass
+    for (int i = tid; i < n; i += nt) {
+      const double dqk = qn[i] - q[i];
+      const double un = P.c2 * dqk - u[i];
+      const double an = P.c0 * dqk - P.c1 * u[i] - a[i];
+      u[i] = un;
+      a[i] = an;
+      q[i] = qn[i];
+      qhist[((size_t)(k + 1) * n + i) * ldw + w] = qn[i];
+    }
+    __syncthreads();
+  }
+  bool nan = false;
+  for (int i = tid; i < n; i += nt) {
+    zT[(size_t)i * ldw + w] = q[i];
+    zT[(size_t)(n + i) * ldw + w] = u[i];
+    if (!isfinite(q[i]) || !isfinite(u[i])) nan = true;
+  }
+  if (nan) atomicOr(&st->flags, (int)DEV_NAN);
+  if (tid == 0) {
+    atomicMax(&st->max_iters, max_it);
+    atomicAdd(&st->total_iters, tot_it);
+  }
+}
+
+// ------------------------------------------------------------------------ sensitivities
+// Exact derivative of the converged discrete map (Eqs. E8-E9): with T = S + K_t(q_{k+1})
+//   T Q_{k+1} = w1^2 M (c0 Q_k + c1 U_k + A_k) + w1 D (c2 Q_k + U_k)
+//   U_{k+1} = c2 (Q_{k+1} - Q_k) - U_k,  A_{k+1} = c0 (Q_{k+1} - Q_k) - c1 U_k - A_k
+// Q_0 = [I 0], U_0 = [0 I], A_0 = -(w1^2 M)^-1 [K + K_t(q_0), w1 D].
+// Block (p, w): columns p*blockDim.x + tid of trajectory w; the band factor of T
+// is computed once per step per block, every thread sweeps its column.
+template <bool LDS>
+__global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega,
+                       const double *__restrict__ qhist, int ldw, double *__restrict__ PhiQU,
+                       double *__restrict__ PhiA, double *__restrict__ Ysc,
+                       double *__restrict__ gscr, DevStatus *st) {
+  extern __shared__ double smem[];
+  const int n = P.n, bw = P.bw, bp = bw + 1, n2 = 2 * n, W2 = 2 * bw + 1;
+  const int w = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = c < n2;
+  const size_t stride = (size_t)2 * n * bp + n + 8;
+  double *base = LDS ? smem : gscr + ((size_t)w * gridDim.x + blockIdx.x) * stride;
+  double *Lf = base;
+  double *Kt = Lf + (size_t)n * bp;
+  double *qv = Kt + (size_t)n * bp;
+  const int b = w / P.St;
+  const double w1 = omega[b * P.d];
+  const double w1s = w1 * w1;
+  double *Qc = PhiQU + (size_t)w * n2 * n2 + c;
+  double *Uc = Qc + (size_t)n * n2;
+  double *Ac = PhiA + (size_t)w * n * n2 + c;
+  double *Yc = Ysc + (size_t)w * n * n2 + c;
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  // ---- initial sensitivities
+  for (int i = tid; i < n; i += nt) qv[i] = qhist[(size_t)i * ldw + w];
+  __syncthreads();
+  for (int pos = tid; pos < n * bp; pos += nt) {
+    const int m = pos / bp, t = pos - m * bp, i = m + t;
+    Lf[pos] = i < n ? w1s * sy.Mb[(size_t)i * W2 + (bw - t)] : 0.0;
+    Kt[pos] = i < n ? kt_entry(sy, qv, pos) : 0.0;
+  }
+  __syncthreads();
+  band_ldlt(Lf, n, bw, st);
+  if (active) {
+    // right-hand side column: -(K + K_t(q0)) e_c or -w1 D e_{c-n}
+    for (int i = 0; i < n; ++i) {
+      double v = 0.0;
+      if (c < n) {
+        if (abs(i - c) <= bw) {
+          v = -sy.Kb[(size_t)i * W2 + (c - i + bw)];
+          v -= i >= c ? Kt[c * bp + (i - c)] : Kt[i * bp + (c - i)];
+        }
+      } else {
+        const int cc = c - n;
+        if (abs(i - cc) <= bw) v = -w1 * sy.Db[(size_t)i * W2 + (cc - i + bw)];
+      }
+      Yc[(size_t)i * n2] = v;
+    }
+    for (int i = 0; i < n; ++i) {
+      double y = Yc[(size_t)i * n2];
+      const int t0 = i < bw ? i : bw;
+      for (int t = 1; t <= t0; ++t) y -= Lf[(i - t) * bp + t] * Yc[(size_t)(i - t) * n2];
+      Yc[(size_t)i * n2] = y;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double x = Yc[(size_t)i * n2] / Lf[i * bp];
+      const int t1 = (n - 1 - i) < bw ? (n - 1 - i) : bw;
+      for (int t = 1; t <= t1; ++t) x -= Lf[i * bp + t] * Ac[(size_t)(i + t) * n2];
+      Ac[(size_t)i * n2] = x;
+      Qc[(size_t)i * n2] = (c == i) ? 1.0 : 0.0;
+      Uc[(size_t)i * n2] = (c == n + i) ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+
+  // ---- steps
+  for (int k = 0; k < P.S1; ++k) {
+    for (int i = tid; i < n; i += nt) qv[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
+    __syncthreads();
+    for (int pos = tid; pos < n * bp; pos += nt) {
+      const int m = pos / bp, t = pos - m * bp, i = m + t;
+      double v = 0.0;
+      if (i < n) {
+        const size_t e = (size_t)i * W2 + (bw - t);
+        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qv, pos);
+      }
+      Lf[pos] = v;
+    }
+    __syncthreads();
+    band_ldlt(Lf, n, bw, st);
+    if (active) {
+      for (int i = 0; i < n; ++i) {
+        double rhs = 0.0;
+        const int j0 = i - bw;
+        for (int t = 0; t < W2; ++t) {
+          const int j = j0 + t;
+          if (j < 0 || j >= n) continue;
+          const double Qj = Qc[(size_t)j * n2], Uj = Uc[(size_t)j * n2], Aj = Ac[(size_t)j * n2];
+          rhs += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * Qj + P.c1 * Uj + Aj) +
+                 w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * Qj + Uj);
+        }
+        const int t0 = i < bw ? i : bw;
+        for (int t = 1; t <= t0; ++t) rhs -= Lf[(i - t) * bp + t] * Yc[(size_t)(i - t) * n2];
+        Yc[(size_t)i * n2] = rhs;
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double x = Yc[(size_t)i * n2] / Lf[i * bp];
+        const int t1 = (n - 1 - i) < bw ? (n - 1 - i) : bw;
+        for (int t = 1; t <= t1; ++t) x -= Lf[i * bp + t] * Yc[(size_t)(i + t) * n2];
+        Yc[(size_t)i * n2] = x;
+        const double Qo = Qc[(size_t)i * n2], Uo = Uc[(size_t)i * n2], Ao = Ac[(size_t)i * n2];
+        const double dQ = x - Qo;
+        Uc[(size_t)i * n2] = P.c2 * dQ - Uo;
+        Ac[(size_t)i * n2] = P.c0 * dQ - P.c1 * Uo - Ao;
+        Qc[(size_t)i * n2] = x;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------ DFT, rotation, residual
+// R = (I (x) R(rho)) (I (x) Gamma^-1) zbar(2 pi) - Z(0)   (Eqs. 15, 16, 21)
+__global__ void k_dft_residual(const double *__restrict__ zT, int ldw, const double *__restrict__ Gi,
+                               const double *__restrict__ rot, const double *__restrict__ Z0, int n,
+                               int U, int L, int St, int B, double *__restrict__ R) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = B * 2 * n * (L + 1);
+  if (idx >= total) return;
+  const int l = idx % (L + 1);
+  const int bi = idx / (L + 1);
+  const int i = bi % (2 * n), b = bi / (2 * n);
+  const double *z = zT + (size_t)i * ldw + (size_t)b * St;
+  const double *z0 = Z0 + ((size_t)b * 2 * n + i) * U;
+  double *r = R + ((size_t)b * 2 * n + i) * U;
+  if (l == L) {
+    double v = 0.0;
+    for (int s = 0; s < St; ++s) v += Gi[s] * z[s];
+    r[0] = v - z0[0];
+    return;
+  }
+  const double *gc = Gi + (size_t)(2 * l + 1) * St;
+  const double *gs = Gi + (size_t)(2 * l + 2) * St;
+  double cc = 0.0, ss = 0.0;
+  for (int s = 0; s < St; ++s) {
+    cc += gc[s] * z[s];
+    ss += gs[s] * z[s];
+  }
+  const double al = rot[(size_t)b * (L > 0 ? L : 1) + l];
+  const double ca = cos(al), sa = sin(al);
+  r[2 * l + 1] = ca * cc - sa * ss - z0[2 * l + 1];
+  r[2 * l + 2] = sa * cc + ca * ss - z0[2 * l + 2];
+}
+
+__global__ void k_sumsq(const double *__restrict__ R, size_t len, double *__restrict__ out) {
+  __shared__ double red[16];
+  const double *r = R + (size_t)blockIdx.x * len;
+  double v = 0.0;
+  for (size_t i = threadIdx.x; i < len; i += blockDim.x) v += r[i] * r[i];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
+    out[blockIdx.x] = s;
+  }
+}
+
+// ------------------------------------------------------------------------ Jacobian (Eq. 22)
+// P[s][l][m] = (R Gamma^-1)[l][s] Gamma[s][m]
+__global__ void k_jac_P(const double *__restrict__ Gi, const double *__restrict__ G,
+                        const double *__restrict__ rot, int U, int L, int St,
+                        double *__restrict__ Pm) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)St * U * U;
+  if (idx >= total) return;
+  const int m = idx % U;
+  const int l = (idx / U) % U;
+  const int s = idx / ((size_t)U * U);
+  double a;
+  if (l == 0) {
+    a = Gi[s];
+  } else {
+    const int pr = (l - 1) / 2;
+    const double al = rot[pr], ca = cos(al), sa = sin(al);
+    const double gc = Gi[(size_t)(2 * pr + 1) * St + s], gs = Gi[(size_t)(2 * pr + 2) * St + s];
+    a = (l & 1) ? (ca * gc - sa * gs) : (sa * gc + ca * gs);
+  }
+  Pm[idx] = a * G[(size_t)s * U + m];
+}
+
+// J[(i,l),(j,m)] = sum_s Phi_s[i][j] P[s][l][m] - delta: GEMM over s with
+// 64 (ij) x 64 (lm) tiles, 4 x 4 outputs per thread.
+__global__ __launch_bounds__(256) void k_jac_gemm(const double *__restrict__ Phi,
+                                                  const double *__restrict__ Pm, int n2, int U,
+                                                  int St, double *__restrict__ J) {
+  __shared__ double As[16][64 + 1];
+  __shared__ double Bs[16][64 + 1];
+  const size_t NIJ = (size_t)n2 * n2;
+  const int NLM = U * U;
+  const size_t ij0 = (size_t)blockIdx.x * 64;
+  const int lm0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4] = {};
+  for (int s0 = 0; s0 < St; s0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int ks = e / 64, col = e % 64;
+      const int s = s0 + ks;
+      const size_t ij = ij0 + col;
+      As[ks][col] = (s < St && ij < NIJ) ? Phi[(size_t)s * NIJ + ij] : 0.0;
+      const int lm = lm0 + col;
+      Bs[ks][col] = (s < St && lm < NLM) ? Pm[(size_t)s * NLM + lm] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[ks][ty * 4 + a];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bv[c] = Bs[ks][tx * 4 + c];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] += av[a] * bv[c];
+    }
+    __syncthreads();
+  }
+  const size_t N = (size_t)n2 * U;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const size_t ij = ij0 + ty * 4 + a;
+    if (ij >= NIJ) continue;
+    const int i = (int)(ij / n2), j = (int)(ij % n2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int lm = lm0 + tx * 4 + c;
+      if (lm >= NLM) continue;
+      const int l = lm / U, m = lm % U;
+      const size_t row = (size_t)i * U + l, col = (size_t)j * U + m;
+      J[row * N + col] = acc[a][c] - ((row == col) ? 1.0 : 0.0);
+    }
+  }
+}
+
+SysDev sysdev(const fse_ctx *ctx) {
+  return SysDev{ctx->Mb,   ctx->Db,     ctx->Kb,   ctx->F,      ctx->f2_ptr, ctx->f2_jk, ctx->f2_v,
+                ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v, ctx->kt_ptr, ctx->kt_idx, ctx->kt_c};
+}
+
+TrajParams params(const fse_ctx *ctx, int B) {
+  TrajParams P;
+  P.n = ctx->n;
+  P.bw = ctx->bw;
+  P.S1 = ctx->S1;
+  P.e = ctx->e;
+  P.d = ctx->d;
+  P.St = ctx->St;
+  P.W = B * ctx->St;
+  P.maxit = ctx->maxit;
+  P.tol = ctx->tol;
+  P.h = 2.0 * M_PI / ctx->S1;
+  P.c0 = 4.0 / (P.h * P.h);
+  P.c1 = 4.0 / P.h;
+  P.c2 = 2.0 / P.h;
+  return P;
+}
+
+constexpr size_t kLdsLimit = 64 * 1024;
+
+}  // namespace
+
+fse_status reset_status(fse_ctx *ctx) {
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, ctx->stream, ctx->status_d, INT_MAX);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_idft(fse_ctx *ctx, int B, const double *Z0) {
+  const int W = B * ctx->St;
+  dim3 grid((W + 127) / 128, 2 * ctx->n);
+  hipLaunchKernelGGL(k_idft, grid, dim3(128), 0, ctx->stream, Z0, ctx->G_d, ctx->n, ctx->U, ctx->St, W,
+                     ctx->Wmax, ctx->qhist, ctx->u0);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_state(fse_ctx *ctx, int B) {
+  const TrajParams P = params(ctx, B);
+  const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 8 * (size_t)ctx->n + 80;
+  const size_t bytes = elems * sizeof(double);
+  // reset the status word; the first failing step starts at "none"
+  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, ctx->stream, ctx->status_d, INT_MAX);
+  const int threads = ctx->bw > 24 ? 256 : 64;
+  if (bytes <= kLdsLimit) {
+    hipLaunchKernelGGL(k_state<true>, dim3(P.W), dim3(threads), bytes, ctx->stream, P, sysdev(ctx),
+                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->zTw,
+                       ctx->Wmax, nullptr, ctx->status_d);
+  } else {
+    if (!ctx->state_scr) {
+      if (hipMalloc((void **)&ctx->state_scr, sizeof(double) * elems * ctx->Wmax) != hipSuccess) {
+        ctx->err = "hipMalloc failed for the state scratch";
+        return FSE_E_NOMEM;
+      }
+    }
+    hipLaunchKernelGGL(k_state<false>, dim3(P.W), dim3(threads), 0, ctx->stream, P, sysdev(ctx),
+                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->zTw,
+                       ctx->Wmax, ctx->state_scr, ctx->status_d);
+  }
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU) {
+  const TrajParams P = params(ctx, B);
+  const size_t n = ctx->n, n2 = 2 * n;
+  if (!ctx->PhiA) {
+    if (hipMalloc((void **)&ctx->PhiA, sizeof(double) * ctx->Wmax * n * n2) != hipSuccess ||
+        hipMalloc((void **)&ctx->sens_scr, sizeof(double) * ctx->Wmax * n * n2) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the sensitivity buffers";
+      return FSE_E_NOMEM;
+    }
+  }
+  const int C = ctx->sens_cols;
+  const int nblk = (int)((n2 + C - 1) / C);
+  const size_t elems = 2 * n * (ctx->bw + 1) + n + 8;
+  const size_t bytes = elems * sizeof(double);
+  dim3 grid(nblk, P.W);
+  if (bytes <= kLdsLimit) {
+    hipLaunchKernelGGL(k_sens<true>, grid, dim3(C), bytes, ctx->stream, P, sysdev(ctx), ctx->omega_d,
+                       ctx->qhist, ctx->Wmax, PhiQU, ctx->PhiA, ctx->sens_scr, nullptr, ctx->status_d);
+  } else {
+    const size_t need = elems * nblk * (size_t)ctx->Wmax;
+    if (ctx->sens_gscr_elems < need) {
+      if (ctx->sens_gscr) (void)hipFree(ctx->sens_gscr);
+      ctx->sens_gscr = nullptr;
+      ctx->sens_gscr_elems = 0;
+      if (hipMalloc((void **)&ctx->sens_gscr, sizeof(double) * need) != hipSuccess) {
+        ctx->err = "hipMalloc failed for the sensitivity factor scratch";
+        return FSE_E_NOMEM;
+      }
+      ctx->sens_gscr_elems = need;
+    }
+    hipLaunchKernelGGL(k_sens<false>, grid, dim3(C), 0, ctx->stream, P, sysdev(ctx), ctx->omega_d,
+                       ctx->qhist, ctx->Wmax, PhiQU, ctx->PhiA, ctx->sens_scr, ctx->sens_gscr,
+                       ctx->status_d);
+  }
+  ctx->last_sens_launches = 1;
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R) {
+  const int total = B * 2 * ctx->n * (ctx->L + 1);
+  hipLaunchKernelGGL(k_dft_residual, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, ctx->zTw,
+                     ctx->Wmax, ctx->Gi_d, ctx->rot_d, Z0, ctx->n, ctx->U, ctx->L, ctx->St, B, R);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_norms(fse_ctx *ctx, int B, const double *R, double *out_host) {
+  hipLaunchKernelGGL(k_sumsq, dim3(B), dim3(256), 0, ctx->stream, R, (size_t)2 * ctx->n * ctx->U,
+                     ctx->norm_d);
+  FSE_HIP(hipGetLastError());
+  std::vector<double> h(B);
+  FSE_HIP(hipMemcpyAsync(h.data(), ctx->norm_d, sizeof(double) * B, hipMemcpyDeviceToHost, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  for (int b = 0; b < B; ++b) out_host[b] = std::sqrt(h[b]);
+  return FSE_OK;
+}
+
+fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J) {
+  const int U = ctx->U, St = ctx->St, n2 = 2 * ctx->n;
+  const size_t Pn = (size_t)St * U * U;
+  if (!ctx->jacP && hipMalloc((void **)&ctx->jacP, sizeof(double) * Pn) != hipSuccess) {
+    ctx->err = "hipMalloc failed for the Jacobian factor";
+    return FSE_E_NOMEM;
+  }
+  double *Pm = ctx->jacP;
+  const size_t N = (size_t)n2 * U;
+  for (int b = 0; b < B; ++b) {
+    hipLaunchKernelGGL(k_jac_P, dim3((unsigned)((Pn + 255) / 256)), dim3(256), 0, ctx->stream, ctx->Gi_d,
+                       ctx->G_d, ctx->rot_d + (size_t)b * (ctx->L > 0 ? ctx->L : 1), U, ctx->L, St, Pm);
+    const size_t NIJ = (size_t)n2 * n2;
+    dim3 grid((unsigned)((NIJ + 63) / 64), (unsigned)((U * U + 63) / 64));
+    hipLaunchKernelGGL(k_jac_gemm, grid, dim3(256), 0, ctx->stream,
+                       PhiQU + (size_t)b * St * NIJ, Pm, n2, U, St, J + (size_t)b * N * N);
+  }
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}

@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+
+Bar: bit-exact for the harmonic table; normwise relative <= 1e-10 for FP64
+states, sensitivities and residuals; ||R|| < 1e-8 on converged tori with the
+oracle re-evaluating R at the GPU's Z(0); Lyapunov exponents within 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from fse_inputs import Torus, tiny_system, workload
+from fse_inputs.systems import System
+from oracle import lyapunov as olyap
+from oracle import shooting as osh
+from oracle import torus as otor
+
+pytestmark = pytest.mark.gpu
+GOLDEN = (1 + 5 ** 0.5) / 2
+RTOL = 1e-10
+
+
+def fse():
+    import paper_2508_06302_amd as m
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("K,S", [([np.arange(1, 6)], [16]), ([np.arange(1, 9)] * 2, [32, 32]),
+                                 ([[1, 3], [1, 2], [2]], [7, 5, 5])])
+def test_layout_bit_exact(K, S):
+    d = len(K) + 1
+    s = tiny_system(n=2, seed=1, e=d)
+    tr = Torus(d=d, e=d, K=K, S=S, S1=8)
+    ctx = fse().fse_init_torus(s, tr)
+    U, St, bw, kt = fse().fse_get_layout(ctx)
+    ref = otor.harmonic_table(K)
+    assert U == otor.n_coefficients(K) and St == int(np.prod(S))
+    assert np.array_equal(kt, ref)
+
+
+def _tiny_case(d=2, n=3, S1=64, seed=2):
+    s = tiny_system(n=n, seed=seed, cubic=1.0, quad=0.3, e=d)
+    om = np.array([0.8, 0.8 * GOLDEN, 0.8 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=d, K=[np.arange(1, 4)] * (d - 1), S=[8] * (d - 1), S1=S1)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(seed).normal(size=(2 * n, tb.U))
+    return s, tr, tb, om, Z0
+
+
+@pytest.mark.parametrize("kernels", ["generic"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_integrate_state_and_sensitivities_tiny(d, kernels, monkeypatch):
+    monkeypatch.setenv("FSE_KERNELS", kernels)
+    s, tr, tb, om, Z0 = _tiny_case(d=d)
+    log(f"tiny d={d} kernels={kernels}")
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    zT, phi = fse().fse_integrate_batch(ctx, om[None], Z0[None], want_phi=True)
+    assert rel(zT[0].cpu().numpy(), ref["zbarT"]) < RTOL
+    assert rel(phi[0].cpu().numpy(), ref["Phi"]) < RTOL
+
+
+def test_residual_and_jacobian_tiny():
+    s, tr, tb, om, Z0 = _tiny_case()
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    Jref = osh.jacobian(ref)
+    ctx = fse().fse_init_torus(s, tr)
+    R, rn, J = fse().fse_shooting_residual_jacobian(ctx, om[None], Z0[None], want_J=True)
+    assert rel(R[0].cpu().numpy(), ref["R"]) < RTOL
+    assert abs(rn[0] - np.linalg.norm(ref["R"])) < RTOL * np.linalg.norm(ref["R"])
+    assert rel(J[0].cpu().numpy(), Jref) < RTOL
+
+
+def test_batch_of_points_matches_single_calls():
+    """B = 3 continuation points with different omega in one launch."""
+    s, tr, tb, om, Z0 = _tiny_case()
+    oms = np.stack([om, om * 1.01, om * 0.97])
+    Zs = np.stack([Z0, 0.5 * Z0, -Z0])
+    ctx = fse().fse_init_torus(s, tr, max_batch=3)
+    zT, phi = fse().fse_integrate_batch(ctx, oms, Zs, want_phi=True)
+    for b in range(3):
+        ref = osh.evaluate(s, tr, oms[b], Zs[b], sens=True, tables=tb)
+        assert rel(zT[b].cpu().numpy(), ref["zbarT"]) < RTOL
+        assert rel(phi[b].cpu().numpy(), ref["Phi"]) < RTOL
+
+
+def test_c1_full_newton_solve():
+    """C1: GPU Newton to ||R|| < 1e-8 from the seeded start; the oracle re-evaluates R at
+    the GPU's Z(0) and its own converged torus agrees."""
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    import torch
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    it, rn = fse().fse_newton_solve(ctx, wl.omega, Zg, tol=1e-8, maxit=10)
+    log(f"C1 gpu newton iterations {it} |R| {rn:.3e}")
+    assert rn < 1e-8
+    Zgpu = Zg.cpu().numpy()
+    ref = osh.evaluate(wl.system, wl.torus, wl.omega, Zgpu, tables=tb)
+    assert np.linalg.norm(ref["R"]) < 1e-8
+    Zo, _, hist = osh.solve(wl.system, wl.torus, wl.omega, Z0, tol_R=1e-10, tables=tb)
+    assert rel(Zgpu, Zo) < 1e-8
+
+
+@pytest.mark.parametrize("kernels", ["generic"])
+def test_c1_integrate_all_trajectories(kernels, monkeypatch):
+    monkeypatch.setenv("FSE_KERNELS", kernels)
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    ref = osh.evaluate(wl.system, wl.torus, wl.omega, Z0, sens=True, tables=tb)
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    zT, phi = fse().fse_integrate_batch(ctx, wl.omega[None], Z0[None], want_phi=True)
+    assert rel(zT[0].cpu().numpy(), ref["zbarT"]) < RTOL
+    assert rel(phi[0].cpu().numpy(), ref["Phi"]) < RTOL
+
+
+def test_c2_full_size_sampled_trajectories():
+    """C2 at full size (147 DOF, 64 trajectories, S1 = 512): all trajectories on the
+    GPU, three sampled ones (first, a middle one, the last) by the oracle."""
+    wl = workload("C2")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    log("C2 gpu integrate with sensitivities")
+    zT, phi = fse().fse_integrate_batch(ctx, wl.omega[None], Z0[None], want_phi=True)
+    zT = zT[0].cpu().numpy()
+    samples = [0, 37, 63]
+    log("C2 oracle sampled trajectories")
+    ref = osh.evaluate(wl.system, wl.torus, wl.omega, Z0, sens=True, tables=tb, samples=samples)
+    for s in samples:
+        assert rel(zT[:, s], ref["zbarT"][:, s]) < RTOL, s
+        assert rel(phi[0, s].cpu().numpy(), ref["Phi"][s]) < 1e-9, s
+
+
+def test_lyapunov_tiny_matches_oracle():
+    s, tr, tb, om, Z0 = _tiny_case()
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    Q0, _ = np.linalg.qr(np.random.default_rng(5).normal(size=(6, 6)))
+    sig_o, _, _ = olyap.exponents(ref["Phi"], om, tb, N_Ly=200, Q0=Q0)
+    ctx = fse().fse_init_torus(s, tr)
+    sig_g = fse().fse_lyapunov(ctx, om, Z0, N_Ly=200, Q0=Q0)
+    assert np.abs(sig_g - sig_o).max() < 1e-6
+
+
+def test_d1_periodic_shooting():
+    """d = 1 (classical shooting, Sec. 3.1): forced Duffing periodic orbit."""
+    s = System("duffing", np.eye(1), np.array([[0.1]]), np.eye(1), np.zeros((0, 3), np.int32),
+               np.zeros(0), np.array([[0, 0, 0, 0]], np.int32), np.array([0.5]), np.array([[0.4]]))
+    tr = Torus(d=1, e=1, K=[], S=[], S1=128)
+    om = np.array([0.7])
+    tb = osh.TorusTables(tr)
+    Zo, _, _ = osh.solve(s, tr, om, np.zeros((2, 1)), tol_R=1e-12, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    import torch
+    Zg = torch.zeros((2, 1), dtype=torch.float64, device="cuda")
+    it, rn = fse().fse_newton_solve(ctx, om, Zg, tol=1e-12, maxit=20)
+    assert rn < 1e-12
+    assert rel(Zg.cpu().numpy(), Zo) < 1e-10
+
+
+def test_error_paths():
+    m = fse()
+    s, tr, tb, om, Z0 = _tiny_case()
+    bad = Torus(d=2, e=2, K=[np.arange(1, 6)], S=[9], S1=16)     # S_2 < 2 H + 1
+    with pytest.raises(m.FseError, match="FSE_E_INVAL"):
+        m.fse_init_torus(s, bad)
+    ctx = m.fse_init_torus(s, tr, max_batch=1)
+    with pytest.raises(m.FseError, match="FSE_E_INVAL"):
+        m.fse_integrate_batch(ctx, np.stack([om, om]), np.stack([Z0, Z0]))
+    ctx1 = m.fse_init_torus(s, tr, step_maxit=1)
+    with pytest.raises(m.FseError, match="FSE_E_NOCONV"):
+        m.fse_integrate_batch(ctx1, om[None], Z0[None])
+    ns = tiny_system(n=3, seed=2, e=2)
+    ns.t2_idx = np.array([[0, 1, 2]], np.int32)                   # f_0 = q1 q2: not a gradient
+    ns.t2_val = np.array([1.0])
+    ns.t3_idx = np.zeros((0, 4), np.int32)
+    ns.t3_val = np.zeros(0)
+    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
+        m.fse_init_torus(ns, tr)
