@@ -140,7 +140,7 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   ctx->tol = desc->step_tol > 0 ? desc->step_tol : 1e-12;
   ctx->maxit = desc->step_maxit > 0 ? desc->step_maxit : 30;
   // FSE_KERNELS=fused|generic selects the trajectory kernels (tests cover both paths)
-  if (const char *kv = std::getenv("FSE_KERNELS")) ctx->use_fused = std::strcmp(kv, "fused") == 0;
+  if (const char *kv = std::getenv("FSE_KERNELS")) ctx->use_fused = std::strcmp(kv, "generic") != 0;
   if (const char *nc = std::getenv("FSE_FUSED_NCW")) ctx->fused_ncw = std::max(1, std::atoi(nc));
   FSE_HIP(hipGetDevice(&ctx->device));
 
@@ -346,6 +346,16 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   FSE_TRY(upload(ctx, &ctx->f3_ptr, p3));
   FSE_TRY(upload(ctx, &ctx->f3_jkl, jkl));
   FSE_TRY(upload(ctx, &ctx->f3_v, v3));
+  if (n < 65536) {
+    std::vector<uint32_t> pk2((size_t)sys->nnz2), pk3((size_t)2 * sys->nnz3);
+    for (int64_t q = 0; q < sys->nnz2; ++q) pk2[q] = (uint32_t)jk[2 * q] | ((uint32_t)jk[2 * q + 1] << 16);
+    for (int64_t q = 0; q < sys->nnz3; ++q) {
+      pk3[2 * q] = (uint32_t)jkl[3 * q] | ((uint32_t)jkl[3 * q + 1] << 16);
+      pk3[2 * q + 1] = (uint32_t)jkl[3 * q + 2];
+    }
+    FSE_TRY(upload(ctx, &ctx->f2_pk, pk2));
+    FSE_TRY(upload(ctx, &ctx->f3_pk, pk3));
+  }
   FSE_TRY(upload(ctx, &ctx->kt_ptr, ktp));
   FSE_TRY(upload(ctx, &ctx->kt_idx, kti));
   FSE_TRY(upload(ctx, &ctx->kt_c, ktc));
@@ -378,7 +388,9 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp};
+  if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
+  if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &e : ctx->ev)

@@ -103,14 +103,16 @@ struct fse_ctx {
   size_t sens_gscr_elems = 0;
   size_t Jw_elems = 0;
 
+  // packed tensors for LDS staging: t2 (j | k << 16), t3 (j | k << 16, l)
+  uint32_t *f2_pk = nullptr, *f3_pk = nullptr;
   // fused trajectory kernel: padded per-point bands [Bmax][n][2BW+1]
-  double *Sp = nullptr, *Mwp = nullptr, *Dwp = nullptr;
+  double *Sp = nullptr, *Mwp = nullptr, *Dwp = nullptr, *Kp = nullptr;
   size_t fused_band_elems = 0;
-  bool use_fused = false;
+  bool use_fused = true;
 
   // tuning
   int sens_cols = 64;               // columns per sensitivity work-group (generic kernel)
-  int fused_ncw = 1;                // column waves per fused work-group
+  int fused_ncw = 2;                // column waves per fused work-group
 
   // timing of the last integration
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

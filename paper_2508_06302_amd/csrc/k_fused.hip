@@ -2,20 +2,29 @@
 // trajectory in one work-group (App. E), for half bandwidths up to 16.
 //
 // Work-group (p, w): trajectory w, sensitivity columns [p*64*NCW, (p+1)*64*NCW).
-//   wave 0      state: average-acceleration Newmark (Eqs. E4-E7); the step
-//               equation (E6) is solved by a chord Newton whose matrix is the
-//               factor of T(q_k) = S + K_t(q_k) from the end of the previous
-//               step; after convergence T(q_{k+1}) is assembled and factored
-//               (banded LDL^T with a register window) into the other buffer.
-//   waves 1..   sensitivities, one step behind the state: in iteration k they
-//               advance [Q; U; A] from step k-1 to k with the factor of T(q_k)
-//               that wave 0 produced in iteration k-1 (exact derivative of the
-//               converged discrete map, Eqs. E8-E9).
-// One barrier per step separates producer and consumers (double-buffered factor).
+// A three-stage pipeline, one barrier per stage step:
+//   wave 0  state      step k: q_k -> q_{k+1} (Eqs. E4-E7).  Eq. (E6) is solved by a
+//                      chord Newton whose matrix is the exact tangent T(q_{k-1}) =
+//                      S + K_t(q_{k-1}) factored by wave 1 (contraction ~1e-3 for
+//                      smooth responses); if the contraction is poor the wave
+//                      assembles and factors T at the current iterate itself.
+//   wave 1  factor     step k: assemble T(q_k) and factor it (banded LDL^T).
+//   waves 2.. columns  step k: advance [Q; U; A] from step k-2 to k-1 with the factor
+//                      of T(q_{k-1}) (exact derivative of the converged discrete map,
+//                      Eqs. E8-E9); in step 0 they form Q_0, U_0, A_0.
+// The chord stops once ||dq||_inf <= 1e-3 tol ||q||_inf, or once the linear-convergence
+// bound rho/(1-rho) ||dq|| on the remaining error (rho the observed contraction) is below
+// 1e-2 tol ||q||: the flow amplifies per-step errors over a period, so the chord must
+// leave no more error than a full Newton step that stops at tol.  An update that stops
+// shrinking below tol ||q|| is the FP64 noise floor of the residual and ends the step.
+// On poor contraction (rho >= 1/4) above tol the state wave refactors T at the current
+// iterate once and continues; if that fails too it restarts from the predictor with full
+// Newton, which stops on ||dq||_inf <= tol ||q||_inf or stagnation below 1e3 tol.
 //
 // Banded data are padded to the compile-time half bandwidth BW >= bw with zeros:
-//   full rows  [n][2BW+1]  entry (i, j) at [i][j - i + BW]   (global, per point)
-//   LDL^T      [n][BW+1]   entry (j + r, j) at [j][r]; [j][0] holds 1 / d_j (LDS)
+//   full rows  [n][2BW+1]   entry (i, j) at [i][j - i + BW]      (global, per point)
+//   LDL^T      [n+BW][BW+1] entry (j + r, j) at [BW + j][r]; [BW + j][0] = 1 / d_j;
+//                           the BW leading columns are zero so sweeps need no guards.
 #include <climits>
 #include <cmath>
 
@@ -40,17 +49,16 @@ __device__ inline double wave_max(double v) {
 
 struct FusedArgs {
   TrajParams P;
-  const double *Mb0, *Db0, *Kb0;           // unpadded full rows [n][2bw+1]
+  const double *Kb0;                       // unpadded full rows [n][2bw+1]
   const double *F;                         // loads [e][n]
   const int32_t *f2_ptr, *f2_jk;
   const double *f2_v;
   const int32_t *f3_ptr, *f3_jkl;
   const double *f3_v;
-  const int32_t *kt_ptr, *kt_idx;
-  const double *kt_c;
+  const uint32_t *f2_pk, *f3_pk;           // packed indices (see fse_ctx)
+  int nnz2, nnz3;
   const double *omega;                     // [B][d]
   const int32_t *sidx, *Sdim;
-  const double *Sp, *Mwp, *Dwp;            // padded full rows [B][n][2BW+1]
   const double *q0, *u0;                   // [n][ldw]
   int ldw;
   double *zT;                              // [2n][ldw]
@@ -60,32 +68,84 @@ struct FusedArgs {
   DevStatus *st;
 };
 
-__device__ inline double fnl_row(const FusedArgs &a, const double *q, int i) {
-  double f = 0.0;
-  for (int p = a.f2_ptr[i]; p < a.f2_ptr[i + 1]; ++p)
-    f += a.f2_v[p] * q[a.f2_jk[2 * p]] * q[a.f2_jk[2 * p + 1]];
-  for (int p = a.f3_ptr[i]; p < a.f3_ptr[i + 1]; ++p)
-    f += a.f3_v[p] * q[a.f3_jkl[3 * p]] * q[a.f3_jkl[3 * p + 1]] * q[a.f3_jkl[3 * p + 2]];
-  return f;
-}
+// Polynomial forces staged in LDS: row pointers, packed indices and values.
+struct TensLds {
+  const int *p2, *p3;
+  const uint32_t *i2, *i3;
+  const double *v2, *v3;
+};
 
-// K_t(q)(i, m) for i >= m, i - m <= bw (lower band, runtime positions)
-__device__ inline double kt_lower(const FusedArgs &a, const double *q, int m, int r) {
-  const int pos = m * (a.P.bw + 1) + r;
-  double v = 0.0;
-  for (int p = a.kt_ptr[pos]; p < a.kt_ptr[pos + 1]; ++p) {
-    const int x = a.kt_idx[2 * p], y = a.kt_idx[2 * p + 1];
-    v += a.kt_c[p] * q[x] * (y >= 0 ? q[y] : 1.0);
+// f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l over row i (four partial sums)
+__device__ inline double fnl_row(const TensLds &t, const double *q, int i) {
+  double f[4] = {0.0, 0.0, 0.0, 0.0};
+  const int a0 = t.p2[i], a1 = t.p2[i + 1];
+  int p = a0;
+  for (; p + 3 < a1; p += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t x = t.i2[p + u];
+      f[u] += t.v2[p + u] * q[x & 0xffff] * q[x >> 16];
+    }
   }
-  return v;
+  for (; p < a1; ++p) {
+    const uint32_t x = t.i2[p];
+    f[0] += t.v2[p] * q[x & 0xffff] * q[x >> 16];
+  }
+  const int b0 = t.p3[i], b1 = t.p3[i + 1];
+  p = b0;
+  for (; p + 3 < b1; p += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t x = t.i3[2 * (p + u)], xl = t.i3[2 * (p + u) + 1];
+      f[u] += t.v3[p + u] * q[x & 0xffff] * q[x >> 16] * q[xl];
+    }
+  }
+  for (; p < b1; ++p) {
+    const uint32_t x = t.i3[2 * p], xl = t.i3[2 * p + 1];
+    f[1] += t.v3[p] * q[x & 0xffff] * q[x >> 16] * q[xl];
+  }
+  return (f[0] + f[1]) + (f[2] + f[3]);
 }
 
-// In-place banded LDL^T by one lane with a register window.  On entry F holds the
-// lower band of a symmetric matrix ([m][r] = A(m+r, m)); on exit [j][0] = 1/d_j and
-// [j][r] = l_{j+r, j}.  Returns false on a zero / non-finite pivot.
+// Lower band of T = S + K_t(q) into F (padded column storage), lanes of one wave over
+// rows: the lane of row i owns the entries (i, i - r), so no two lanes write the same
+// word.  K_t(i, m) = d f_i / d q_m collects the terms of row i whose index set holds m
+// (entries with m > i are the transposes of lower entries of a symmetric tangent).
 template <int BW>
-__device__ bool ldlt_serial(double *F, int n) {
+__device__ void assemble_T(const TensLds &t, int n, const double *__restrict__ Sp, const double *q,
+                           double *Fp, int lane) {
+  constexpr int bp = BW + 1, W2 = 2 * BW + 1;
+  double *F = Fp + BW * bp;
+  for (int i = lane; i < n; i += 64) {
+#pragma unroll
+    for (int r = 0; r <= BW; ++r) {
+      const int m = i - r;
+      if (m >= 0) F[m * bp + r] = Sp[(size_t)i * W2 + (BW - r)];
+    }
+    for (int p = t.p2[i]; p < t.p2[i + 1]; ++p) {
+      const uint32_t x = t.i2[p];
+      const int j = x & 0xffff, k = x >> 16;
+      const double v = t.v2[p];
+      if (j <= i) F[j * bp + (i - j)] += v * q[k];
+      if (k <= i) F[k * bp + (i - k)] += v * q[j];
+    }
+    for (int p = t.p3[i]; p < t.p3[i + 1]; ++p) {
+      const uint32_t x = t.i3[2 * p];
+      const int j = x & 0xffff, k = x >> 16, l = t.i3[2 * p + 1];
+      const double v = t.v3[p];
+      if (j <= i) F[j * bp + (i - j)] += v * q[k] * q[l];
+      if (k <= i) F[k * bp + (i - k)] += v * q[j] * q[l];
+      if (l <= i) F[l * bp + (i - l)] += v * q[j] * q[k];
+    }
+  }
+}
+
+// In-place banded LDL^T by one lane with a register window (padded storage, see
+// file header).  Returns false on a zero or non-finite pivot.
+template <int BW>
+__device__ bool ldlt_serial(double *Fp, int n) {
   constexpr int bp = BW + 1;
+  double *F = Fp + BW * bp;
   double Wn[BW + 1][BW + 1];
 #pragma unroll
   for (int r = 0; r <= BW; ++r)
@@ -95,14 +155,15 @@ __device__ bool ldlt_serial(double *F, int n) {
   for (int j = 0; j < n; ++j) {
     const double d = Wn[0][0];
     ok = ok && (d != 0.0) && isfinite(d);
-    const double inv = 1.0 / d;
+    // reciprocal: hardware estimate refined by one Newton step (relative error ~1 ulp)
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
     double l[BW + 1];
 #pragma unroll
     for (int r = 1; r <= BW; ++r) l[r] = Wn[r][0] * inv;
     F[j * bp] = inv;
 #pragma unroll
-    for (int r = 1; r <= BW; ++r)
-      if (j + r < n) F[j * bp + r] = l[r];
+    for (int r = 1; r <= BW; ++r) F[j * bp + r] = (j + r < n) ? l[r] : 0.0;
 #pragma unroll
     for (int r = 1; r <= BW; ++r)
 #pragma unroll
@@ -111,49 +172,84 @@ __device__ bool ldlt_serial(double *F, int n) {
     for (int r = 0; r < BW; ++r)
 #pragma unroll
       for (int c = 0; c <= r; ++c) Wn[r][c] = Wn[r + 1][c + 1];
-    const int nr = j + 1 + BW;  // new bottom row of the window
+    const bool in = j + 1 + BW < n;
 #pragma unroll
-    for (int c = 0; c <= BW; ++c) Wn[BW][c] = (nr < n) ? F[(j + 1 + c) * bp + (BW - c)] : 0.0;
+    for (int c = 0; c <= BW; ++c) Wn[BW][c] = in ? F[(j + 1 + c) * bp + (BW - c)] : 0.0;
   }
   return ok;
 }
 
-// Solve (L D L^T) x = x in place by one lane; the term with the most recent unknown
-// is applied last so each row adds one dependent FMA to the critical path.
+// Solve (L D L^T) x = x in place by one lane.  The coefficients of the next row
+// are loaded while the current row is reduced, and the term with the most recent
+// unknown is applied last, so each row adds one dependent FMA to the critical path.
 template <int BW>
-__device__ void ldlt_solve_serial(const double *F, int n, double *x) {
+__device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
   constexpr int bp = BW + 1;
-  double yw[BW];
+  const double *F = Fp + BW * bp;
+  double yw[BW], cf[BW + 1], cn[BW + 1];
 #pragma unroll
   for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-  for (int i = 0; i < n; ++i) {
-    double acc = x[i];
 #pragma unroll
-    for (int t = BW; t >= 1; --t)
-      if (i >= t) acc -= F[(i - t) * bp + t] * yw[t - 1];
+  for (int t = 1; t <= BW; ++t) cf[t] = F[(0 - t) * bp + t];
+  double xn = x[0];
+  for (int i = 0; i < n; ++i) {
+    const double xi = xn;
+    const int i1 = i + 1 < n ? i + 1 : i;
+#pragma unroll
+    for (int t = 1; t <= BW; ++t) cn[t] = F[(i1 - t) * bp + t];
+    xn = x[i1];
+    // older terms in two independent partial sums, off the critical path
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = BW; t >= 2; --t) {
+      if ((t & 1) == 0)
+        s0 += cf[t] * yw[t - 1];
+      else
+        s1 += cf[t] * yw[t - 1];
+    }
+    const double acc = (xi - (s0 + s1)) - cf[1] * yw[0];
 #pragma unroll
     for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
     yw[0] = acc;
     x[i] = acc;
+#pragma unroll
+    for (int t = 1; t <= BW; ++t) cf[t] = cn[t];
   }
 #pragma unroll
   for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    double acc = x[i] * F[i * bp];
 #pragma unroll
-    for (int t = BW; t >= 1; --t) acc -= F[i * bp + t] * yw[t - 1];
+  for (int t = 0; t <= BW; ++t) cf[t] = F[(n - 1) * bp + t];
+  xn = x[n - 1];
+  for (int i = n - 1; i >= 0; --i) {
+    const double xi = xn;
+    const int i1 = i > 0 ? i - 1 : 0;
+#pragma unroll
+    for (int t = 0; t <= BW; ++t) cn[t] = F[i1 * bp + t];
+    xn = x[i1];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = BW; t >= 2; --t) {
+      if ((t & 1) == 0)
+        s0 += cf[t] * yw[t - 1];
+      else
+        s1 += cf[t] * yw[t - 1];
+    }
+    const double acc = (xi * cf[0] - (s0 + s1)) - cf[1] * yw[0];
 #pragma unroll
     for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
     yw[0] = acc;
     x[i] = acc;
+#pragma unroll
+    for (int t = 0; t <= BW; ++t) cf[t] = cn[t];
   }
 }
 
-// Per-point padded bands: S = w1^2 c0 M + w1 c2 D + K, w1^2 M, w1 D.
+// Per-point padded bands: S = w1^2 c0 M + w1 c2 D + K, w1^2 M, w1 D; and K itself.
 template <int BW>
 __global__ void k_point_bands(TrajParams P, const double *__restrict__ Mb, const double *__restrict__ Db,
                               const double *__restrict__ Kb, const double *__restrict__ omega, int B,
-                              double *__restrict__ Sp, double *__restrict__ Mwp, double *__restrict__ Dwp) {
+                              double *__restrict__ Sp, double *__restrict__ Mwp, double *__restrict__ Dwp,
+                              double *__restrict__ Kp) {
   constexpr int W2 = 2 * BW + 1;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = B * P.n * W2;
@@ -174,12 +270,126 @@ __global__ void k_point_bands(TrajParams P, const double *__restrict__ Mb, const
   Mwp[idx] = w1 * w1 * m;
   Dwp[idx] = w1 * dd;
   Sp[idx] = w1 * w1 * P.c0 * m + w1 * P.c2 * dd + k;
+  if (b == 0) Kp[idx] = k;
+}
+
+__device__ inline double forcing_cos(const FusedArgs &a, int f, double phi1, const double *om, int s) {
+  if (f == 0) return cos(phi1);
+  const double ph = kTwoPi * (double)a.sidx[(f - 1) * a.P.St + s] / (double)a.Sdim[f - 1];
+  return cos(ph + om[f] / om[0] * phi1);
+}
+
+constexpr int kRB = 8;   // rows per block in the sensitivity sweeps
+// Chord stop: an update below kChordFloor tol |q| ends the step; otherwise the linear
+// error bound must fall below kChordBound tol |q|.
+constexpr double kChordFloor = 1e-3;
+constexpr double kChordBound = 1e-2;
+
+// One sensitivity step for the column owned by this lane (Eqs. E8-E9): RHS formation as
+// an independent pass over row blocks, then the forward and backward substitutions
+// whose per-block loads are all issued before the dependent chain.
+template <int BW>
+__device__ void sens_step(const double *F, const double *__restrict__ Mwp, const double *__restrict__ Dwp,
+                          int n, int n2, double c0, double c1, double c2, double *__restrict__ Qc,
+                          double *__restrict__ Uc, double *__restrict__ Ac, double *__restrict__ Yc) {
+  constexpr int bp = BW + 1, W2 = 2 * BW + 1;
+  // pass 1: Y_i = w1^2 M (c0 Q + c1 U + A)_i + w1 D (c2 Q + U)_i
+  for (int i0 = 0; i0 < n; i0 += kRB) {
+    constexpr int NR = kRB + 2 * BW;
+    double v1[NR], v2[NR];
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+      const int j = i0 - BW + t;
+      double Qj = 0.0, Uj = 0.0, Aj = 0.0;
+      if (j >= 0 && j < n) {
+        Qj = Qc[(size_t)j * n2];
+        Uj = Uc[(size_t)j * n2];
+        Aj = Ac[(size_t)j * n2];
+      }
+      v1[t] = c0 * Qj + c1 * Uj + Aj;
+      v2[t] = c2 * Qj + Uj;
+    }
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      const int i = i0 + d;
+      if (i < n) {
+        const double *mr = Mwp + (size_t)i * W2;
+        const double *dr = Dwp + (size_t)i * W2;
+        double rhs = 0.0;
+#pragma unroll
+        for (int t = 0; t < W2; ++t) rhs += mr[t] * v1[d + t] + dr[t] * v2[d + t];
+        Yc[(size_t)i * n2] = rhs;
+      }
+    }
+  }
+  // pass 2: forward substitution with the unit lower factor
+  double yw[BW];
+#pragma unroll
+  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+  for (int i0 = 0; i0 < n; i0 += kRB) {
+    double yb[kRB];
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) yb[d] = (i0 + d < n) ? Yc[(size_t)(i0 + d) * n2] : 0.0;
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      const int i = i0 + d;
+      double acc = yb[d];
+#pragma unroll
+      for (int t = BW; t >= 1; --t) acc -= F[(i - t) * bp + t] * yw[t - 1];
+#pragma unroll
+      for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
+      yw[0] = acc;
+      yb[d] = acc;
+    }
+#pragma unroll
+    for (int d = 0; d < kRB; ++d)
+      if (i0 + d < n) Yc[(size_t)(i0 + d) * n2] = yb[d];
+  }
+  // pass 3: backward substitution and the Newmark update of [Q; U; A]
+#pragma unroll
+  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+  const int nb = (n + kRB - 1) / kRB;
+  for (int blk = nb - 1; blk >= 0; --blk) {
+    const int i0 = blk * kRB;
+    double yb[kRB], qb[kRB], ub[kRB], ab[kRB];
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      const int i = i0 + d;
+      const bool in = i < n;
+      yb[d] = in ? Yc[(size_t)i * n2] : 0.0;
+      qb[d] = in ? Qc[(size_t)i * n2] : 0.0;
+      ub[d] = in ? Uc[(size_t)i * n2] : 0.0;
+      ab[d] = in ? Ac[(size_t)i * n2] : 0.0;
+    }
+#pragma unroll
+    for (int d = kRB - 1; d >= 0; --d) {
+      const int i = i0 + d;
+      if (i >= n) continue;
+      double x = yb[d] * F[i * bp];
+#pragma unroll
+      for (int t = BW; t >= 1; --t) x -= F[i * bp + t] * yw[t - 1];
+#pragma unroll
+      for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
+      yw[0] = x;
+      yb[d] = x;
+    }
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      const int i = i0 + d;
+      if (i >= n) continue;
+      const double dQ = yb[d] - qb[d];
+      Uc[(size_t)i * n2] = c2 * dQ - ub[d];
+      Ac[(size_t)i * n2] = c0 * dQ - c1 * ub[d] - ab[d];
+      Qc[(size_t)i * n2] = yb[d];
+    }
+  }
 }
 
 template <int BW>
 __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__restrict__ Sp_all,
                                                const double *__restrict__ Mwp_all,
-                                               const double *__restrict__ Dwp_all) {
+                                               const double *__restrict__ Dwp_all,
+                                               const double *__restrict__ Kp) {
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
   extern __shared__ double smem[];
   const TrajParams &P = a.P;
@@ -187,50 +397,89 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
   const int w = blockIdx.y;
   const int b = w / P.St, s = w - b * P.St;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ncw = (blockDim.x >> 6) - 1;
+  const int ncw = (blockDim.x >> 6) - 2;
   const double *om = a.omega + b * P.d;
-  const double w1 = om[0];
   // read-only per-point bands; __restrict__ lets uniform row reads use the scalar path
   const double *__restrict__ Sp = Sp_all + (size_t)b * n * W2;
   const double *__restrict__ Mwp = Mwp_all + (size_t)b * n * W2;
   const double *__restrict__ Dwp = Dwp_all + (size_t)b * n * W2;
 
-  double *FM = smem;                     // factor of w1^2 M
-  double *FT0 = FM + (size_t)n * bp;     // factors of T, double buffered
-  double *FT1 = FT0 + (size_t)n * bp;
-  double *KtB = FT1 + (size_t)n * bp;    // lower band of K + K_t(q0)
-  double *q = KtB + (size_t)n * bp;
+  const size_t fb = (size_t)(n + BW) * bp;   // one padded factor buffer
+  double *FM = smem;                         // factor of w1^2 M
+  double *KtB = FM + fb;                     // lower band of K + K_t(q0) (same padding)
+  double *FT0 = KtB + fb;                    // factors of T, double buffered
+  double *FT1 = FT0 + fb;
+  double *FR = FT1 + fb;                     // state-wave refresh factor
+  double *q = FR + fb;
   double *u = q + n;
   double *acc = u + n;
   double *qn = acc + n;
   double *bv = qn + n;
   double *r = bv + n;
-  double *cs = r + n;                    // forcing cosines [8]
+  double *qs0 = r + n;                       // q_k handed to the factor wave
+  double *qs1 = qs0 + n;
+  double *cs = qs1 + n;                      // forcing cosines [8]
+  double *tv2 = cs + 8;                      // staged polynomial forces
+  double *tv3 = tv2 + a.nnz2;
+  int *tp2 = reinterpret_cast<int *>(tv3 + a.nnz3);
+  int *tp3 = tp2 + (n + 1);
+  uint32_t *ti2 = reinterpret_cast<uint32_t *>(tp3 + (n + 1));
+  uint32_t *ti3 = ti2 + a.nnz2;
+  const TensLds tl{tp2, tp3, ti2, ti3, tv2, tv3};
   __shared__ int s_fail_step;
   __shared__ int s_flags;
 
-  // ============================================================ prologue (wave 0)
-  if (wave == 0) {
-    if (lane == 0) {
-      s_fail_step = INT_MAX;
-      s_flags = 0;
-    }
+  // ============================================================ prologue
+  for (int e = threadIdx.x; e < (int)(5 * fb); e += blockDim.x) smem[e] = 0.0;
+  for (int e = threadIdx.x; e <= n; e += blockDim.x) {
+    tp2[e] = a.f2_ptr[e];
+    tp3[e] = a.f3_ptr[e];
+  }
+  for (int e = threadIdx.x; e < a.nnz2; e += blockDim.x) {
+    tv2[e] = a.f2_v[e];
+    ti2[e] = a.f2_pk[e];
+  }
+  for (int e = threadIdx.x; e < a.nnz3; e += blockDim.x) {
+    tv3[e] = a.f3_v[e];
+    ti3[2 * e] = a.f3_pk[2 * e];
+    ti3[2 * e + 1] = a.f3_pk[2 * e + 1];
+  }
+  if (threadIdx.x == 0) {
+    s_fail_step = INT_MAX;
+    s_flags = 0;
+  }
+  __syncthreads();
+  if (wave == 0 || wave == 1) {
     for (int i = lane; i < n; i += 64) {
-      q[i] = a.q0[(size_t)i * a.ldw + w];
-      u[i] = a.u0[(size_t)i * a.ldw + w];
-    }
-    if (lane < P.e) {
-      double c;
-      if (lane == 0) {
-        c = 1.0;
+      const double qi = a.q0[(size_t)i * a.ldw + w];
+      if (wave == 0) {
+        q[i] = qi;
+        u[i] = a.u0[(size_t)i * a.ldw + w];
       } else {
-        const double ph = kTwoPi * (double)a.sidx[(lane - 1) * P.St + s] / (double)a.Sdim[lane - 1];
-        c = cos(ph);
+        qs0[i] = qi;
       }
-      cs[lane] = c;
+    }
+  }
+  __syncthreads();
+  if (wave == 1) {
+    // w1^2 M, K + K_t(q0) and T(q0) = S + K_t(q0) lower bands; factor w1^2 M and T(q0)
+    assemble_T<BW>(tl, n, Sp, qs0, FT0, lane);
+    assemble_T<BW>(tl, n, Kp, qs0, KtB, lane);
+    for (int pos = lane; pos < n * bp; pos += 64) {
+      const int m = pos / bp, rr = pos - m * bp, i = m + rr;
+      FM[BW * bp + pos] = i < n ? Mwp[(size_t)i * W2 + (BW - rr)] : 0.0;
     }
     wave_sync();
-    // a0 right-hand side: e0 - w1 D u0 - K q0 - f_nl(q0); lower bands of w1^2 M, K + K_t(q0), T(q0)
+    if (lane == 0) {
+      bool ok = ldlt_serial<BW>(FM, n);
+      ok = ldlt_serial<BW>(FT0, n) && ok;
+      if (!ok) s_flags |= DEV_SINGULAR;
+    }
+  }
+  if (wave == 0) {
+    if (lane < P.e) cs[lane] = forcing_cos(a, lane, 0.0, om, s);
+    wave_sync();
+    // a0 right-hand side: e0 - w1 D u0 - K q0 - f_nl(q0)
     for (int i = lane; i < n; i += 64) {
       double v = 0.0;
       for (int f = 0; f < P.e; ++f) v += a.F[(size_t)f * n + i] * cs[f];
@@ -242,60 +491,34 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
         const double k = (tb >= 0 && tb <= 2 * P.bw) ? a.Kb0[(size_t)i * (2 * P.bw + 1) + tb] : 0.0;
         v -= Dwp[(size_t)i * W2 + t] * u[j] + k * q[j];
       }
-      acc[i] = v - fnl_row(a, q, i);
+      acc[i] = v - fnl_row(tl, q, i);
     }
-    for (int pos = lane; pos < n * bp; pos += 64) {
-      const int m = pos / bp, rr = pos - m * bp, i = m + rr;
-      double vm = 0.0, vk = 0.0, vt = 0.0;
-      if (i < n) {
-        const size_t e = (size_t)i * W2 + (BW - rr);
-        const double kt = rr <= P.bw ? kt_lower(a, q, m, rr) : 0.0;
-        const double kk = rr <= P.bw ? a.Kb0[(size_t)i * (2 * P.bw + 1) + (P.bw - rr)] : 0.0;
-        vm = Mwp[e];
-        vk = kk + kt;
-        vt = Sp[e] + kt;
-      }
-      FM[pos] = vm;
-      KtB[pos] = vk;
-      FT0[pos] = vt;
-    }
-    wave_sync();
-    if (lane == 0) {
-      bool ok = ldlt_serial<BW>(FM, n);
-      ldlt_solve_serial<BW>(FM, n, acc);
-      ok = ldlt_serial<BW>(FT0, n) && ok;
-      if (!ok) s_flags |= DEV_SINGULAR;
-    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    if (lane == 0) ldlt_solve_serial<BW>(FM, n, acc);
     wave_sync();
   }
   __syncthreads();
 
-  // ============================================================ steps
-  const int c = blockIdx.x * (64 * ncw) + (wave - 1) * 64 + lane;
-  const bool colw = wave >= 1 && c < n2 && a.Phi != nullptr;
+  // ============================================================ pipeline
+  const int c = blockIdx.x * (64 * ncw) + (wave - 2) * 64 + lane;
+  const bool colw = wave >= 2 && c < n2 && a.Phi != nullptr;
   double *Qc = a.Phi ? a.Phi + (size_t)w * n2 * n2 + c : nullptr;
   double *Uc = a.Phi ? Qc + (size_t)n * n2 : nullptr;
   double *Ac = a.PhiA + (size_t)w * n * n2 + c;
   double *Yc = a.Ysc + (size_t)w * n * n2 + c;
   int max_it = 0;
   unsigned long long tot_it = 0;
+  const int last = a.Phi ? P.S1 + 1 : P.S1 - 1;
 
-  for (int k = 0; k <= P.S1; ++k) {
+  for (int k = 0; k <= last; ++k) {
     if (wave == 0 && k < P.S1) {
-      // ---------------- state step k: q_k -> q_{k+1}, chord matrix T(q_k) in FT[k%2]
-      const double *Fc = (k & 1) ? FT1 : FT0;
-      double *Fn = (k & 1) ? FT0 : FT1;
+      // ---------------- state step k: q_k -> q_{k+1}; chord T(q_{k-1}) = FT[(k-1)&1]
+      const double *Fc = (k == 0) ? FT0 : (((k - 1) & 1) ? FT1 : FT0);
+      double *qsn = ((k + 1) & 1) ? qs1 : qs0;
       const double phi1 = (double)(k + 1) * P.h;
-      if (lane < P.e) {
-        double cc;
-        if (lane == 0) {
-          cc = cos(phi1);
-        } else {
-          const double ph = kTwoPi * (double)a.sidx[(lane - 1) * P.St + s] / (double)a.Sdim[lane - 1];
-          cc = cos(ph + om[lane] / w1 * phi1);
-        }
-        cs[lane] = cc;
-      }
+      if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s);
       wave_sync();
       for (int i = lane; i < n; i += 64) {
         double v = 0.0;
@@ -312,11 +535,19 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
       }
       wave_sync();
       double prev = INFINITY;
-      bool conv = false;
+      bool conv = false, full = false, refreshed = false;
+      const double *Fcur = Fc;
       int it = 0;
       for (; it < P.maxit && !conv; ++it) {
+        if (full) {
+          // full Newton: exact tangent at the current iterate
+          assemble_T<BW>(tl, n, Sp, qn, FR, lane);
+          wave_sync();
+          if (lane == 0 && !ldlt_serial<BW>(FR, n)) s_flags |= DEV_SINGULAR;
+          wave_sync();
+        }
         for (int i = lane; i < n; i += 64) {
-          double v = fnl_row(a, qn, i) - bv[i];
+          double v = fnl_row(tl, qn, i) - bv[i];
 #pragma unroll
           for (int t = 0; t < W2; ++t) {
             const int j = i - BW + t;
@@ -326,7 +557,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
           r[i] = v;
         }
         wave_sync();
-        if (lane == 0) ldlt_solve_serial<BW>(Fc, n, r);
+        if (lane == 0) ldlt_solve_serial<BW>(full ? FR : Fcur, n, r);
         wave_sync();
         double nd = 0.0, nq = 0.0;
         for (int i = lane; i < n; i += 64) {
@@ -339,18 +570,44 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
         nd = wave_max(nd);
         nq = wave_max(nq);
         wave_sync();
-        if (!(nd == nd) || !(nq == nq)) {
-          it = P.maxit;
-          break;
-        }
+        const bool finite = (nd == nd) && (nq == nq) && nd < INFINITY;
         const double tolq = P.tol * nq;
-        // converged: update below tolerance; or the noise floor (update stops shrinking
-        // while below 1e3 tol); or the linear-convergence bound rho/(1-rho)|dq| <= tol
-        const double rho = it > 0 ? nd / prev : 1.0;
-        if (nd <= tolq || (nd <= 1e3 * tolq && nd > 0.5 * prev) ||
-            (rho < 0.5 && rho / (1.0 - rho) * nd <= tolq))
+        const double rho = prev < INFINITY ? nd / prev : 1.0;
+        if (full) {
+          // quadratic convergence: same rule as a full Newton step (App. E reading)
+          if (!finite) {
+            it = P.maxit;
+            break;
+          }
+          if (nd <= tolq || (nd <= 1e3 * tolq && nd > 0.5 * prev)) conv = true;
+          prev = nd;
+        } else if (finite && nd <= kChordFloor * tolq) {
           conv = true;
-        prev = nd;
+        } else if (finite && prev < INFINITY && rho < 0.25) {
+          // linear convergence: stop once the remaining error bound rho/(1-rho) |dq| is
+          // two decades below tol; the flow amplifies per-step errors over a period
+          if (rho / (1.0 - rho) * nd <= kChordBound * tolq) conv = true;
+          prev = nd;
+        } else if (finite && prev == INFINITY) {
+          prev = nd;
+        } else if (finite && nd <= tolq) {
+          conv = true;  // no further contraction below tol: FP64 noise floor of the residual
+        } else if (finite && !refreshed) {
+          // poor contraction: refresh the chord matrix at the current iterate and go on
+          assemble_T<BW>(tl, n, Sp, qn, FR, lane);
+          wave_sync();
+          if (lane == 0 && !ldlt_serial<BW>(FR, n)) s_flags |= DEV_SINGULAR;
+          wave_sync();
+          Fcur = FR;
+          refreshed = true;
+          prev = INFINITY;
+        } else {
+          // poor contraction or divergence: restart from the predictor with full Newton
+          for (int i = lane; i < n; i += 64) qn[i] = q[i] + P.h * u[i] + 0.5 * P.h * P.h * acc[i];
+          wave_sync();
+          full = true;
+          prev = INFINITY;
+        }
       }
       if (!conv && lane == 0) {
         s_flags |= DEV_NOCONV;
@@ -365,149 +622,88 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
         u[i] = un;
         acc[i] = an;
         q[i] = qn[i];
+        qsn[i] = qn[i];
       }
       wave_sync();
-      // T(q_{k+1}) for the sensitivity step k and the chord of step k+1
-      for (int pos = lane; pos < n * bp; pos += 64) {
-        const int m = pos / bp, rr = pos - m * bp, i = m + rr;
-        double vt = 0.0;
-        if (i < n) vt = Sp[(size_t)i * W2 + (BW - rr)] + (rr <= P.bw ? kt_lower(a, q, m, rr) : 0.0);
-        Fn[pos] = vt;
-      }
+    } else if (wave == 1 && k >= 1 && k <= P.S1) {
+      // ---------------- factor step k: T(q_k) -> FT[k&1]
+      double *Fn = (k & 1) ? FT1 : FT0;
+      const double *qk = (k & 1) ? qs1 : qs0;
+      assemble_T<BW>(tl, n, Sp, qk, Fn, lane);
       wave_sync();
-      if (lane == 0) {
-        if (!ldlt_serial<BW>(Fn, n)) s_flags |= DEV_SINGULAR;
-      }
+      if (lane == 0 && !ldlt_serial<BW>(Fn, n)) s_flags |= DEV_SINGULAR;
       wave_sync();
-    }
-    if (colw) {
-      if (k == 0) {
-        // ---------------- Q_0 = [I 0], U_0 = [0 I], w1^2 M A_0 = -[K + K_t(q0), w1 D]
-        for (int i = 0; i < n; ++i) {
-          double v = 0.0;
-          if (c < n) {
-            const int dlt = i - c;
-            if (dlt >= 0 && dlt <= BW)
-              v = -KtB[c * bp + dlt];
-            else if (dlt < 0 && -dlt <= BW)
-              v = -KtB[i * bp + (-dlt)];
-          } else {
-            const int cc = c - n, t = cc - i + BW;
-            if (t >= 0 && t < W2) v = -Dwp[(size_t)i * W2 + t];
-          }
-          Yc[(size_t)i * n2] = v;
-        }
-        double yw[BW];
+    } else if (colw && k == 0) {
+      // ---------------- Q_0 = [I 0], U_0 = [0 I], w1^2 M A_0 = -[K + K_t(q0), w1 D]
+      const double *F = FM + BW * bp;
+      const double *Kl = KtB + BW * bp;
+      double yw[BW];
 #pragma unroll
-        for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-        for (int i = 0; i < n; ++i) {
-          double v = Yc[(size_t)i * n2];
-#pragma unroll
-          for (int t = BW; t >= 1; --t)
-            if (i >= t) v -= FM[(i - t) * bp + t] * yw[t - 1];
-#pragma unroll
-          for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
-          yw[0] = v;
-          Yc[(size_t)i * n2] = v;
+      for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        if (c < n) {
+          const int dlt = i - c;
+          if (dlt >= 0 && dlt <= BW)
+            v = -Kl[c * bp + dlt];
+          else if (dlt < 0 && -dlt <= BW)
+            v = -Kl[i * bp + (-dlt)];
+        } else {
+          const int t = (c - n) - i + BW;
+          if (t >= 0 && t < W2) v = -Dwp[(size_t)i * W2 + t];
         }
 #pragma unroll
-        for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-          double v = Yc[(size_t)i * n2] * FM[i * bp];
+        for (int t = BW; t >= 1; --t) v -= F[(i - t) * bp + t] * yw[t - 1];
 #pragma unroll
-          for (int t = BW; t >= 1; --t) v -= FM[i * bp + t] * yw[t - 1];
-#pragma unroll
-          for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
-          yw[0] = v;
-          Ac[(size_t)i * n2] = v;
-          Qc[(size_t)i * n2] = (c == i) ? 1.0 : 0.0;
-          Uc[(size_t)i * n2] = (c == n + i) ? 1.0 : 0.0;
-        }
-      } else {
-        // ---------------- sensitivity step k-1 with the factor of T(q_k) in FT[k%2]
-        const double *Fk = (k & 1) ? FT1 : FT0;
-        double v1w[W2], v2w[W2], yw[BW];
-#pragma unroll
-        for (int t = 0; t < W2; ++t) {
-          const int j = t - BW;
-          double Qj = 0.0, Uj = 0.0, Aj = 0.0;
-          if (j >= 0 && j < n) {
-            Qj = Qc[(size_t)j * n2];
-            Uj = Uc[(size_t)j * n2];
-            Aj = Ac[(size_t)j * n2];
-          }
-          v1w[t] = P.c0 * Qj + P.c1 * Uj + Aj;
-          v2w[t] = P.c2 * Qj + Uj;
-        }
-#pragma unroll
-        for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-        for (int i = 0; i < n; ++i) {
-          const double *mr = Mwp + (size_t)i * W2;
-          const double *dr = Dwp + (size_t)i * W2;
-          double rhs = 0.0;
-#pragma unroll
-          for (int t = 0; t < W2; ++t) rhs += mr[t] * v1w[t] + dr[t] * v2w[t];
-#pragma unroll
-          for (int t = BW; t >= 1; --t)
-            if (i >= t) rhs -= Fk[(i - t) * bp + t] * yw[t - 1];
-#pragma unroll
-          for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
-          yw[0] = rhs;
-          Yc[(size_t)i * n2] = rhs;
-          // slide the windows to rows i-BW+1 .. i+BW+1
-#pragma unroll
-          for (int t = 0; t < W2 - 1; ++t) {
-            v1w[t] = v1w[t + 1];
-            v2w[t] = v2w[t + 1];
-          }
-          const int jn = i + BW + 1;
-          double Qj = 0.0, Uj = 0.0, Aj = 0.0;
-          if (jn < n) {
-            Qj = Qc[(size_t)jn * n2];
-            Uj = Uc[(size_t)jn * n2];
-            Aj = Ac[(size_t)jn * n2];
-          }
-          v1w[W2 - 1] = P.c0 * Qj + P.c1 * Uj + Aj;
-          v2w[W2 - 1] = P.c2 * Qj + Uj;
-        }
-#pragma unroll
-        for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-        for (int i = n - 1; i >= 0; --i) {
-          double x = Yc[(size_t)i * n2] * Fk[i * bp];
-#pragma unroll
-          for (int t = BW; t >= 1; --t) x -= Fk[i * bp + t] * yw[t - 1];
-#pragma unroll
-          for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
-          yw[0] = x;
-          const double Qo = Qc[(size_t)i * n2], Uo = Uc[(size_t)i * n2], Ao = Ac[(size_t)i * n2];
-          const double dQ = x - Qo;
-          Uc[(size_t)i * n2] = P.c2 * dQ - Uo;
-          Ac[(size_t)i * n2] = P.c0 * dQ - P.c1 * Uo - Ao;
-          Qc[(size_t)i * n2] = x;
-        }
+        for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
+        yw[0] = v;
+        Yc[(size_t)i * n2] = v;
       }
+#pragma unroll
+      for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        double v = Yc[(size_t)i * n2] * F[i * bp];
+#pragma unroll
+        for (int t = BW; t >= 1; --t) v -= F[i * bp + t] * yw[t - 1];
+#pragma unroll
+        for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
+        yw[0] = v;
+        Ac[(size_t)i * n2] = v;
+        Qc[(size_t)i * n2] = (c == i) ? 1.0 : 0.0;
+        Uc[(size_t)i * n2] = (c == n + i) ? 1.0 : 0.0;
+      }
+    } else if (colw && k >= 2) {
+      // ---------------- sensitivity step k-2 -> k-1 with the factor of T(q_{k-1})
+      const double *F = (((k - 1) & 1) ? FT1 : FT0) + BW * bp;
+      sens_step<BW>(F, Mwp, Dwp, n, n2, P.c0, P.c1, P.c2, Qc, Uc, Ac, Yc);
     }
     __syncthreads();
   }
 
   // ============================================================ epilogue
-  if (wave == 0) {
+  if (wave == 0 && blockIdx.x == 0) {
     bool nan = false;
-    if (blockIdx.x == 0) {
-      for (int i = lane; i < n; i += 64) {
-        a.zT[(size_t)i * a.ldw + w] = q[i];
-        a.zT[(size_t)(n + i) * a.ldw + w] = u[i];
-        if (!isfinite(q[i]) || !isfinite(u[i])) nan = true;
-      }
+    for (int i = lane; i < n; i += 64) {
+      a.zT[(size_t)i * a.ldw + w] = q[i];
+      a.zT[(size_t)(n + i) * a.ldw + w] = u[i];
+      if (!isfinite(q[i]) || !isfinite(u[i])) nan = true;
     }
     if (nan) atomicOr(&a.st->flags, (int)DEV_NAN);
-    if (lane == 0 && blockIdx.x == 0) {
-      if (s_flags) atomicOr(&a.st->flags, s_flags);
-      if (s_fail_step != INT_MAX) atomicMin(&a.st->first_step, s_fail_step);
+    if (lane == 0) {
       atomicMax(&a.st->max_iters, max_it);
       atomicAdd(&a.st->total_iters, tot_it);
     }
   }
+  if (threadIdx.x == 0) {
+    if (s_flags) atomicOr(&a.st->flags, s_flags);
+    if (s_fail_step != INT_MAX) atomicMin(&a.st->first_step, s_fail_step);
+  }
+}
+
+template <int BW>
+size_t fused_lds_bytes(int n, int nnz2, int nnz3) {
+  return sizeof(double) * ((size_t)5 * (n + BW) * (BW + 1) + 8 * (size_t)n + 8 + nnz2 + nnz3) +
+         sizeof(int) * (2 * ((size_t)n + 1) + nnz2 + 2 * (size_t)nnz3);
 }
 
 template <int BW>
@@ -516,12 +712,14 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   const size_t n = ctx->n;
   const size_t band = (size_t)ctx->Bmax * n * W2;
   if (ctx->fused_band_elems < band) {
-    for (double *p : {ctx->Sp, ctx->Mwp, ctx->Dwp})
+    for (double *p : {ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp})
       if (p) (void)hipFree(p);
-    ctx->Sp = ctx->Mwp = ctx->Dwp = nullptr;
+    ctx->Sp = ctx->Mwp = ctx->Dwp = ctx->Kp = nullptr;
+    ctx->fused_band_elems = 0;
     if (hipMalloc((void **)&ctx->Sp, sizeof(double) * band) != hipSuccess ||
         hipMalloc((void **)&ctx->Mwp, sizeof(double) * band) != hipSuccess ||
-        hipMalloc((void **)&ctx->Dwp, sizeof(double) * band) != hipSuccess) {
+        hipMalloc((void **)&ctx->Dwp, sizeof(double) * band) != hipSuccess ||
+        hipMalloc((void **)&ctx->Kp, sizeof(double) * n * W2) != hipSuccess) {
       ctx->err = "hipMalloc failed for the per-point bands";
       return FSE_E_NOMEM;
     }
@@ -529,11 +727,9 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   }
   const int total = B * (int)n * W2;
   hipLaunchKernelGGL(k_point_bands<BW>, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, P, ctx->Mb,
-                     ctx->Db, ctx->Kb, ctx->omega_d, B, ctx->Sp, ctx->Mwp, ctx->Dwp);
+                     ctx->Db, ctx->Kb, ctx->omega_d, B, ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp);
   FusedArgs a;
   a.P = P;
-  a.Mb0 = ctx->Mb;
-  a.Db0 = ctx->Db;
   a.Kb0 = ctx->Kb;
   a.F = ctx->F;
   a.f2_ptr = ctx->f2_ptr;
@@ -542,15 +738,13 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   a.f3_ptr = ctx->f3_ptr;
   a.f3_jkl = ctx->f3_jkl;
   a.f3_v = ctx->f3_v;
-  a.kt_ptr = ctx->kt_ptr;
-  a.kt_idx = ctx->kt_idx;
-  a.kt_c = ctx->kt_c;
+  a.f2_pk = ctx->f2_pk;
+  a.f3_pk = ctx->f3_pk;
+  a.nnz2 = ctx->nnz2;
+  a.nnz3 = ctx->nnz3;
   a.omega = ctx->omega_d;
   a.sidx = ctx->sidx_d;
   a.Sdim = ctx->Sdim_d;
-  a.Sp = ctx->Sp;
-  a.Mwp = ctx->Mwp;
-  a.Dwp = ctx->Dwp;
   a.q0 = ctx->qhist;
   a.u0 = ctx->u0;
   a.ldw = ctx->Wmax;
@@ -559,49 +753,54 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   a.PhiA = ctx->PhiA;
   a.Ysc = ctx->sens_scr;
   a.st = ctx->status_d;
-  int ncw = 0, nblk = 1;
-  if (Phi) {
-    ncw = ctx->fused_ncw;
-    const int cols = 64 * ncw;
-    nblk = (int)((2 * n + cols - 1) / cols);
-  }
-  const size_t lds = sizeof(double) * ((size_t)4 * n * (BW + 1) + 7 * n + 8);
+  const int ncw = Phi ? ctx->fused_ncw : 0;
+  const int nblk = Phi ? (int)((2 * n + 64 * ncw - 1) / (64 * ncw)) : 1;
+  const size_t lds = fused_lds_bytes<BW>((int)n, ctx->nnz2, ctx->nnz3);
+  FSE_HIP(hipFuncSetAttribute((const void *)k_fused<BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
   dim3 grid(nblk, P.W);
-  hipLaunchKernelGGL(k_fused<BW>, grid, dim3(64 * (1 + ncw)), lds, ctx->stream, a, ctx->Sp, ctx->Mwp,
-                     ctx->Dwp);
+  hipLaunchKernelGGL(k_fused<BW>, grid, dim3(64 * (2 + ncw)), lds, ctx->stream, a, ctx->Sp, ctx->Mwp,
+                     ctx->Dwp, ctx->Kp);
   FSE_HIP(hipGetLastError());
   ctx->last_sens_launches = Phi ? 1 : 0;
   return FSE_OK;
 }
 
+int bw_bucket(int bw) { return bw <= 4 ? 4 : bw <= 6 ? 6 : bw <= 8 ? 8 : bw <= 12 ? 12 : 16; }
+
+size_t lds_for(const fse_ctx *ctx) {
+  const int n = ctx->n, a = ctx->nnz2, b = ctx->nnz3;
+  switch (bw_bucket(ctx->bw)) {
+    case 4: return fused_lds_bytes<4>(n, a, b);
+    case 6: return fused_lds_bytes<6>(n, a, b);
+    case 8: return fused_lds_bytes<8>(n, a, b);
+    case 12: return fused_lds_bytes<12>(n, a, b);
+    default: return fused_lds_bytes<16>(n, a, b);
+  }
+}
+
 }  // namespace
 
-static int bw_bucket(int bw) { return bw <= 4 ? 4 : bw <= 6 ? 6 : bw <= 8 ? 8 : bw <= 12 ? 12 : 16; }
-
 bool fused_supported(const fse_ctx *ctx) {
-  if (ctx->bw > 16) return false;
-  const size_t lds = sizeof(double) * ((size_t)4 * ctx->n * (bw_bucket(ctx->bw) + 1) + 7 * ctx->n + 8);
-  return lds <= 64 * 1024;
+  return ctx->bw <= 16 && ctx->n < 65536 && ctx->f2_pk && ctx->f3_pk && lds_for(ctx) <= 150 * 1024 &&
+         ctx->fused_ncw >= 1 && ctx->fused_ncw <= 2;
 }
 
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi) {
-  const TrajParams P = [&] {
-    TrajParams p;
-    p.n = ctx->n;
-    p.bw = ctx->bw;
-    p.S1 = ctx->S1;
-    p.e = ctx->e;
-    p.d = ctx->d;
-    p.St = ctx->St;
-    p.W = B * ctx->St;
-    p.maxit = ctx->maxit;
-    p.tol = ctx->tol;
-    p.h = 2.0 * M_PI / ctx->S1;
-    p.c0 = 4.0 / (p.h * p.h);
-    p.c1 = 4.0 / p.h;
-    p.c2 = 2.0 / p.h;
-    return p;
-  }();
+  TrajParams p;
+  p.n = ctx->n;
+  p.bw = ctx->bw;
+  p.S1 = ctx->S1;
+  p.e = ctx->e;
+  p.d = ctx->d;
+  p.St = ctx->St;
+  p.W = B * ctx->St;
+  p.maxit = ctx->maxit;
+  p.tol = ctx->tol;
+  p.h = 2.0 * M_PI / ctx->S1;
+  p.c0 = 4.0 / (p.h * p.h);
+  p.c1 = 4.0 / p.h;
+  p.c2 = 2.0 / p.h;
   if (Phi && !ctx->PhiA) {
     const size_t sz = sizeof(double) * ctx->Wmax * (size_t)ctx->n * 2 * ctx->n;
     if (hipMalloc((void **)&ctx->PhiA, sz) != hipSuccess || hipMalloc((void **)&ctx->sens_scr, sz) != hipSuccess) {
@@ -610,9 +809,11 @@ fse_status launch_fused(fse_ctx *ctx, int B, double *Phi) {
     }
   }
   FSE_TRY(reset_status(ctx));
-  if (ctx->bw <= 4) return launch_bw<4>(ctx, B, Phi, P);
-  if (ctx->bw <= 6) return launch_bw<6>(ctx, B, Phi, P);
-  if (ctx->bw <= 8) return launch_bw<8>(ctx, B, Phi, P);
-  if (ctx->bw <= 12) return launch_bw<12>(ctx, B, Phi, P);
-  return launch_bw<16>(ctx, B, Phi, P);
+  switch (bw_bucket(ctx->bw)) {
+    case 4: return launch_bw<4>(ctx, B, Phi, p);
+    case 6: return launch_bw<6>(ctx, B, Phi, p);
+    case 8: return launch_bw<8>(ctx, B, Phi, p);
+    case 12: return launch_bw<12>(ctx, B, Phi, p);
+    default: return launch_bw<16>(ctx, B, Phi, p);
+  }
 }

@@ -57,7 +57,7 @@ def _tiny_case(d=2, n=3, S1=64, seed=2):
     return s, tr, tb, om, Z0
 
 
-@pytest.mark.parametrize("kernels", ["generic"])
+@pytest.mark.parametrize("kernels", ["fused", "generic"])
 @pytest.mark.parametrize("d", [2, 3])
 def test_integrate_state_and_sensitivities_tiny(d, kernels, monkeypatch):
     monkeypatch.setenv("FSE_KERNELS", kernels)
@@ -113,7 +113,7 @@ def test_c1_full_newton_solve():
     assert rel(Zgpu, Zo) < 1e-8
 
 
-@pytest.mark.parametrize("kernels", ["generic"])
+@pytest.mark.parametrize("kernels", ["fused", "generic"])
 def test_c1_integrate_all_trajectories(kernels, monkeypatch):
     monkeypatch.setenv("FSE_KERNELS", kernels)
     wl = workload("C1")
