@@ -49,7 +49,7 @@ typedef enum {
   FSE_E_NOCONV = 4,       /* per-step Newton did not converge (step index in message)    */
   FSE_E_SINGULAR = 5,     /* zero / non-finite pivot in a banded or dense factorisation  */
   FSE_E_NAN = 6,          /* non-finite state                                            */
-  FSE_E_UNSUPPORTED = 7   /* valid request this build does not handle (message says why) */
+  FSE_E_UNSUPPORTED = 7   /* valid request the library does not handle (message says why) */
 } fse_status;
 
 typedef enum {

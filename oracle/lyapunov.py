@@ -7,7 +7,7 @@ is a quasi-periodic function of phi~, interpolated by trigonometric polynomials
 on the torus grid; step i of the discrete Gram-Schmidt (Eq. F2) uses
 Psi(2 pi (i-1) rho) with the interval Delta t = T_1 = 2 pi / omega_1.
 
-Readings (listed in the design doc): the interpolation basis is the torus basis
+Readings: the interpolation basis is the torus basis
 H(k~, phi~) with coefficients Gamma^-1 Psi_s (the "(d-1)-dimensional FFT");
 the Gram-Schmidt is a Householder QR with a positive diagonal; the exponents
 are returned in QR column order and sorted.

@@ -7,7 +7,7 @@ Eq. (E6) S q_{k+1} + f_nl(q_{k+1}) = b_k (Eq. E7) by full-tangent Newton, and
 the sensitivities d[q;u](2pi)/d[q;u](0) (Eq. E8) are the exact derivative of
 the converged discrete map.
 
-Readings where the paper is silent (listed in the design doc as well):
+Readings where the paper is silent:
   * the state is [q; u] with u = dq/dphi_1 (App. E), not [q; qdot];
   * a_0 is the acceleration consistent with the equation of motion at phi_1 = 0;
   * Newton predictor q_k + D u_k + D^2/2 a_k; stop when ||dq||_inf <= tol *

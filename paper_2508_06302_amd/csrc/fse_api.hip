@@ -127,8 +127,12 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     ctx->err = "unknown precision";
     return FSE_E_INVAL;
   }
+  if (desc->precision == FSE_PREC_MIXED_FP32) {
+    ctx->err = "FP32 sensitivity propagation is not implemented";
+    return FSE_E_UNSUPPORTED;
+  }
   if (desc->e < desc->d) {
-    ctx->err = "unknown base frequencies (d > e) are not handled by this build";
+    ctx->err = "unknown base frequencies (d > e) are not implemented";
     return FSE_E_UNSUPPORTED;
   }
   ctx->n = n;
@@ -554,7 +558,7 @@ fse_status fse_shooting_residual_jacobian(fse_ctx *ctx, int32_t B, const double 
     return FSE_E_INVAL;
   }
   if (dRdw) {
-    ctx->err = "dR/domega is not available in this build (pass NULL)";
+    ctx->err = "dR/domega is not implemented (pass NULL)";
     return FSE_E_UNSUPPORTED;
   }
   double *phi = nullptr;
