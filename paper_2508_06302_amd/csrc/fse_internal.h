@@ -96,6 +96,7 @@ struct fse_ctx {
   double *Zwork = nullptr;          // [Bmax][2n][U]
   double *Jw = nullptr;             // dense Jacobian / LU workspace [2nU][2nU]
   int32_t *piv_d = nullptr;
+  int piv_n = 0;
   double *lu_scr = nullptr;
   double *norm_d = nullptr;         // [Bmax] squared residual norms
   double *jacP = nullptr;           // [S~][U][U] Jacobian right factor

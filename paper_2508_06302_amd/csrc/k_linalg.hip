@@ -8,19 +8,31 @@
 namespace {
 
 // ---------------------------------------------------------------- LU with partial pivoting
-// Row-major A (N x N).  Panel of kb columns starting at k0 factored by one block;
-// full-row swaps are applied to A and to the right-hand side immediately.
-__global__ __launch_bounds__(1024) void k_lu_panel(double *__restrict__ A, int N, int k0, int kb,
-                                                   double *__restrict__ rhs, DevStatus *st) {
+// The Jacobian arrives row-major (J[i][j] at i*N + j).  The factorisation works on
+// B = J^T read column-major (B(i, j) at j*N + i), so a column of B is contiguous and
+// pivot searches and rank-1 updates are coalesced:  Pi B = L U with unit lower L and
+// row interchanges Pi = S_{N-1} ... S_0 (S_k swaps k and piv[k]).  Then
+// J = U^T L^T Pi, and J x = r is solved as U^T v = r, L^T w = v, x = Pi^T w.
+// Right-looking blocked algorithm with recursively split panels.
+
+constexpr int kLuLeaf = 8;    // panel columns factored by one work-group
+constexpr int kLuBlock = 64;  // outer block (also the largest TRSM triangle)
+
+// Factor the leaf panel B[j0:N, j0:j0+nb] (nb <= kLuLeaf) with partial pivoting;
+// interchanges are applied inside the panel only.
+__global__ __launch_bounds__(1024) void k_lu_leaf(double *__restrict__ B, int N, int j0, int nb,
+                                                  int32_t *__restrict__ piv, DevStatus *st) {
   __shared__ double sv[16];
   __shared__ int si[16];
   __shared__ int piv_s;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
-  for (int j = k0; j < k0 + kb; ++j) {
+  for (int c = 0; c < nb; ++c) {
+    const int j = j0 + c;
+    const double *col = B + (size_t)j * N;
     double best = -1.0;
     int bi = j;
     for (int i = j + tid; i < N; i += nt) {
-      const double v = fabs(A[(size_t)i * N + j]);
+      const double v = fabs(col[i]);
       if (v > best) {
         best = v;
         bi = i;
@@ -48,112 +60,163 @@ __global__ __launch_bounds__(1024) void k_lu_panel(double *__restrict__ A, int N
           ix = si[w];
         }
       piv_s = ix;
+      piv[j] = ix;
       if (!(b > 0.0) || !isfinite(b)) atomicOr(&st->flags, (int)DEV_SINGULAR);
     }
     __syncthreads();
     const int p = piv_s;
-    if (p != j) {
-      for (int c = tid; c < N; c += nt) {
-        const double t = A[(size_t)j * N + c];
-        A[(size_t)j * N + c] = A[(size_t)p * N + c];
-        A[(size_t)p * N + c] = t;
-      }
-      if (tid == 0) {
-        const double t = rhs[j];
-        rhs[j] = rhs[p];
-        rhs[p] = t;
-      }
+    if (p != j && tid < nb) {
+      double *cc = B + (size_t)(j0 + tid) * N;
+      const double t = cc[j];
+      cc[j] = cc[p];
+      cc[p] = t;
     }
     __syncthreads();
-    const double inv = 1.0 / A[(size_t)j * N + j];
+    const double inv = 1.0 / col[j];
     for (int i = j + 1 + tid; i < N; i += nt) {
-      const double l = A[(size_t)i * N + j] * inv;
-      A[(size_t)i * N + j] = l;
-      for (int c = j + 1; c < k0 + kb; ++c) A[(size_t)i * N + c] -= l * A[(size_t)j * N + c];
+      const double l = col[i] * inv;
+      B[(size_t)j * N + i] = l;
+      for (int c2 = c + 1; c2 < nb; ++c2) {
+        double *cc = B + (size_t)(j0 + c2) * N;
+        cc[i] -= l * cc[j];
+      }
     }
     __syncthreads();
   }
 }
 
-// A12 <- L11^-1 A12 (unit lower L11 of the panel), one thread per column.
-__global__ void k_lu_trsm(double *__restrict__ A, int N, int k0, int kb) {
-  const int c = k0 + kb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  for (int r = k0 + 1; r < k0 + kb; ++r) {
-    double v = A[(size_t)r * N + c];
-    for (int t = k0; t < r; ++t) v -= A[(size_t)r * N + t] * A[(size_t)t * N + c];
-    A[(size_t)r * N + c] = v;
+// Interchanges piv[k0..k1) applied in order to the columns [c0, c1) of B.
+__global__ void k_lu_swap(double *__restrict__ B, int N, int c0, int c1, int k0, int k1,
+                          const int32_t *__restrict__ piv) {
+  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  double *cc = B + (size_t)c * N;
+  for (int k = k0; k < k1; ++k) {
+    const int p = piv[k];
+    if (p != k) {
+      const double t = cc[k];
+      cc[k] = cc[p];
+      cc[p] = t;
+    }
   }
 }
 
-// A22 -= A21 A12, 64 x 64 tiles, kb <= 64 inner.
-__global__ __launch_bounds__(256) void k_lu_gemm(double *__restrict__ A, int N, int k0, int kb) {
-  __shared__ double As[64][65];
-  __shared__ double Bs[64][65];
-  const int r0 = k0 + kb + blockIdx.y * 64;
-  const int c0 = k0 + kb + blockIdx.x * 64;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int rr = e / 64, kk = e % 64;
-    As[rr][kk] = (r0 + rr < N && kk < kb) ? A[(size_t)(r0 + rr) * N + k0 + kk] : 0.0;
-    const int k2 = e / 64, cc = e % 64;
-    Bs[k2][cc] = (k2 < kb && c0 + cc < N) ? A[(size_t)(k0 + k2) * N + c0 + cc] : 0.0;
+// B[j0:j0+nb, c0:c0+nc] <- L11^-1 B[j0:j0+nb, c0:c0+nc], L11 the unit lower triangle of
+// B[j0:j0+nb, j0:j0+nb] (nb <= 64) staged in LDS.  One wave per column, lane r holds row r.
+__global__ __launch_bounds__(256) void k_lu_trsm(double *__restrict__ B, int N, int j0, int nb, int c0,
+                                                 int nc) {
+  __shared__ double L[kLuBlock][kLuBlock + 1];
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int r = e % nb, c = e / nb;
+    L[r][c] = B[(size_t)(j0 + c) * N + j0 + r];
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int col = c0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (col >= c0 + nc) return;
+  double *cc = B + (size_t)col * N + j0;
+  double x = lane < nb ? cc[lane] : 0.0;
+  for (int r = 0; r < nb - 1; ++r) {
+    const double xr = __shfl(x, r);
+    if (lane > r) x -= L[lane][r] * xr;
+  }
+  if (lane < nb) cc[lane] = x;
+}
+
+// C -= A Bm on column-major sub-blocks of B: C = B[r0:r0+m, c0:c0+n], A = B[r0:r0+m, k0:k0+kk],
+// Bm = B[k0:k0+kk, c0:c0+n].  64 x 64 tiles, 16-deep k slices staged in LDS.
+__global__ __launch_bounds__(256) void k_lu_gemm(double *__restrict__ B, int N, int r0, int m, int c0,
+                                                 int n, int k0, int kk) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int i0 = r0 + blockIdx.x * 64, jb = c0 + blockIdx.y * 64;
   double acc[4][4] = {};
-  for (int k = 0; k < kb; ++k) {
-    double a[4], b[4];
+  for (int ks = 0; ks < kk; ks += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int i = e & 63, k = e >> 6;
+      const int gi = i0 + i, gk = k0 + ks + k;
+      As[k][i] = (gi < r0 + m && ks + k < kk) ? B[(size_t)gk * N + gi] : 0.0;
+      const int k2 = e & 15, j = e >> 4;
+      const int gj = jb + j, gk2 = k0 + ks + k2;
+      Bs[k2][j] = (gj < c0 + n && ks + k2 < kk) ? B[(size_t)gj * N + gk2] : 0.0;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = As[ty * 4 + i][k];
+    for (int k = 0; k < 16; ++k) {
+      double a[4], b[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+      for (int u = 0; u < 4; ++u) a[u] = As[k][tr + 16 * u];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int v = 0; v < 4; ++v) b[v] = Bs[k][tc + 16 * v];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = r0 + ty * 4 + i;
-    if (r >= N) continue;
+  for (int v = 0; v < 4; ++v) {
+    const int gj = jb + tc + 16 * v;
+    if (gj >= c0 + n) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = c0 + tx * 4 + j;
-      if (c < N) A[(size_t)r * N + c] -= acc[i][j];
+    for (int u = 0; u < 4; ++u) {
+      const int gi = i0 + tr + 16 * u;
+      if (gi < r0 + m) B[(size_t)gj * N + gi] -= acc[u][v];
     }
   }
 }
 
-// Triangular solves with the packed LU (unit lower L, upper U), one block.
-__global__ __launch_bounds__(1024) void k_lu_substitute(const double *__restrict__ A, int N,
-                                                        double *__restrict__ x) {
-  __shared__ double red[16];
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
-  for (int i = 0; i < N; ++i) {
-    double s = 0.0;
-    for (int j = tid; j < i; j += nt) s += A[(size_t)i * N + j] * x[j];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[wid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (nt >> 6); ++w) t += red[w];
-      x[i] -= t;
+// Blocked triangular solves with the factors of B (row i of U^T and of L^T is contiguous:
+// memory row i).  y[r0:r0+nb] -= M[r0:r0+nb, cols] x[cols] for the already solved
+// columns, one wave per row.
+__global__ __launch_bounds__(256) void k_lu_gemv(const double *__restrict__ A, int N, int r0, int nb,
+                                                 int c0, int c1, const double *__restrict__ x,
+                                                 double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int r = r0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= r0 + nb) return;
+  const double *row = A + (size_t)r * N;
+  double s = 0.0;
+  for (int c = c0 + lane; c < c1; c += 64) s += row[c] * x[c];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) y[r] -= s;
+}
+
+// Diagonal block of the substitution, one wave: forward (upper = false: U^T with its
+// diagonal) or backward (upper = true: unit L^T) over rows [r0, r0+nb), nb <= 64.
+__global__ __launch_bounds__(64) void k_lu_diag(const double *__restrict__ A, int N, int r0, int nb,
+                                                bool upper, double *__restrict__ y) {
+  const int lane = threadIdx.x;
+  double x = lane < nb ? y[r0 + lane] : 0.0;
+  if (!upper) {
+    for (int r = 0; r < nb; ++r) {
+      const double d = A[(size_t)(r0 + r) * N + r0 + r];
+      const double xr = __shfl(x, r) / d;
+      if (lane == r) x = xr;
+      // rows below: memory row (r0+lane), column (r0+r)
+      if (lane > r && lane < nb) x -= A[(size_t)(r0 + lane) * N + r0 + r] * xr;
     }
-    __syncthreads();
+  } else {
+    for (int r = nb - 1; r >= 0; --r) {
+      const double xr = __shfl(x, r);
+      if (lane < r) x -= A[(size_t)(r0 + lane) * N + r0 + r] * xr;
+    }
   }
-  for (int i = N - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int j = i + 1 + tid; j < N; j += nt) s += A[(size_t)i * N + j] * x[j];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[wid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (nt >> 6); ++w) t += red[w];
-      x[i] = (x[i] - t) / A[(size_t)i * N + i];
+  if (lane < nb) y[r0 + lane] = x;
+}
+
+// x = Pi^T w: interchanges applied in reverse order (one thread).
+__global__ void k_lu_unpermute(double *__restrict__ x, int N, const int32_t *__restrict__ piv) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int k = N - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k) {
+      const double t = x[k];
+      x[k] = x[p];
+      x[p] = t;
     }
-    __syncthreads();
   }
 }
 
@@ -292,20 +355,82 @@ __global__ __launch_bounds__(1024) void k_householder(double *__restrict__ Y, in
 
 }  // namespace
 
+namespace {
+
+void lu_gemm(fse_ctx *ctx, double *B, int N, int r0, int m, int c0, int n, int k0, int kk) {
+  if (m <= 0 || n <= 0 || kk <= 0) return;
+  dim3 g((m + 63) / 64, (n + 63) / 64);
+  hipLaunchKernelGGL(k_lu_gemm, g, dim3(256), 0, ctx->stream, B, N, r0, m, c0, n, k0, kk);
+}
+
+void lu_swap(fse_ctx *ctx, double *B, int N, int c0, int c1, int k0, int k1) {
+  if (c1 <= c0 || k1 <= k0) return;
+  hipLaunchKernelGGL(k_lu_swap, dim3((c1 - c0 + 255) / 256), dim3(256), 0, ctx->stream, B, N, c0, c1, k0,
+                     k1, ctx->piv_d);
+}
+
+void lu_trsm(fse_ctx *ctx, double *B, int N, int j0, int nb, int c0, int nc) {
+  if (nc <= 0 || nb <= 1) return;
+  hipLaunchKernelGGL(k_lu_trsm, dim3((nc + 3) / 4), dim3(256), 0, ctx->stream, B, N, j0, nb, c0, nc);
+}
+
+// Recursive panel B[j0:N, j0:j0+nb], nb <= kLuBlock.
+void lu_panel(fse_ctx *ctx, double *B, int N, int j0, int nb) {
+  if (nb <= kLuLeaf) {
+    hipLaunchKernelGGL(k_lu_leaf, dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb, ctx->piv_d,
+                       ctx->status_d);
+    return;
+  }
+  const int n1 = ((nb / 2 + kLuLeaf - 1) / kLuLeaf) * kLuLeaf, n2 = nb - n1;
+  lu_panel(ctx, B, N, j0, n1);
+  lu_swap(ctx, B, N, j0 + n1, j0 + nb, j0, j0 + n1);
+  lu_trsm(ctx, B, N, j0, n1, j0 + n1, n2);
+  lu_gemm(ctx, B, N, j0 + n1, N - j0 - n1, j0 + n1, n2, j0, n1);
+  lu_panel(ctx, B, N, j0 + n1, n2);
+  lu_swap(ctx, B, N, j0, j0 + n1, j0 + n1, j0 + nb);
+}
+
+}  // namespace
+
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
   FSE_TRY(reset_status(ctx));
-  const int nb = 64;
-  for (int k0 = 0; k0 < N; k0 += nb) {
-    const int kb = (N - k0) < nb ? (N - k0) : nb;
-    hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), 0, ctx->stream, A, N, k0, kb, rhs, ctx->status_d);
-    const int rest = N - k0 - kb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_lu_trsm, dim3((rest + 127) / 128), dim3(128), 0, ctx->stream, A, N, k0, kb);
-      dim3 g((rest + 63) / 64, (rest + 63) / 64);
-      hipLaunchKernelGGL(k_lu_gemm, g, dim3(256), 0, ctx->stream, A, N, k0, kb);
+  if (ctx->piv_n < N) {
+    if (ctx->piv_d) (void)hipFree(ctx->piv_d);
+    ctx->piv_d = nullptr;
+    ctx->piv_n = 0;
+    if (hipMalloc((void **)&ctx->piv_d, sizeof(int32_t) * N) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the pivots";
+      return FSE_E_NOMEM;
     }
+    ctx->piv_n = N;
   }
-  hipLaunchKernelGGL(k_lu_substitute, dim3(1), dim3(1024), 0, ctx->stream, A, N, rhs);
+  double *B = A;  // B = J^T column-major
+  for (int j0 = 0; j0 < N; j0 += kLuBlock) {
+    const int nb = (N - j0) < kLuBlock ? (N - j0) : kLuBlock;
+    lu_panel(ctx, B, N, j0, nb);
+    const int c1 = j0 + nb;
+    lu_swap(ctx, B, N, c1, N, j0, c1);       // trailing columns
+    lu_swap(ctx, B, N, 0, j0, j0, c1);       // earlier L columns
+    lu_trsm(ctx, B, N, j0, nb, c1, N - c1);
+    lu_gemm(ctx, B, N, c1, N - c1, c1, N - c1, j0, nb);
+  }
+  // U^T v = r (forward, memory rows), then L^T w = v (backward), then x = Pi^T w
+  for (int r0 = 0; r0 < N; r0 += 64) {
+    const int nb = (N - r0) < 64 ? (N - r0) : 64;
+    if (r0 > 0)
+      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4), dim3(256), 0, ctx->stream, A, N, r0, nb, 0, r0,
+                         rhs, rhs);
+    hipLaunchKernelGGL(k_lu_diag, dim3(1), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs);
+  }
+  const int last = ((N - 1) / 64) * 64;
+  for (int r0 = last; r0 >= 0; r0 -= 64) {
+    const int nb = (N - r0) < 64 ? (N - r0) : 64;
+    if (r0 + nb < N)
+      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4), dim3(256), 0, ctx->stream, A, N, r0, nb, r0 + nb, N,
+                         rhs, rhs);
+    hipLaunchKernelGGL(k_lu_diag, dim3(1), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs);
+  }
+  hipLaunchKernelGGL(k_lu_unpermute, dim3(1), dim3(1), 0, ctx->stream, rhs, N, ctx->piv_d);
   FSE_HIP(hipGetLastError());
   DevStatus st;
   FSE_HIP(hipMemcpyAsync(&st, ctx->status_d, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));

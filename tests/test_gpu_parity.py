@@ -189,3 +189,19 @@ def test_error_paths():
     ns.t3_val = np.zeros(0)
     with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
         m.fse_init_torus(ns, tr)
+
+
+def test_newton_step_ragged_lu():
+    """One Newton step with N = 2 n U = 474 unknowns (7 full LU blocks and a ragged one)."""
+    s = tiny_system(n=3, seed=4, cubic=1.0, quad=0.3, e=2)
+    om = np.array([0.8, 0.8 * GOLDEN])
+    tr = Torus(d=2, e=2, K=[np.arange(1, 40)], S=[96], S1=64)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.1 * np.random.default_rng(7).normal(size=(6, tb.U)) / (1 + np.arange(tb.U))
+    Zo, _, rn_o = osh.newton_step(s, tr, om, Z0, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    import torch
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    rn = fse().fse_newton_step(ctx, om, Zg)
+    assert abs(rn - rn_o) < RTOL * rn_o
+    assert rel(Zg.cpu().numpy() - Z0, Zo - Z0) < 1e-9
