@@ -140,6 +140,32 @@ fse_status fse_newton_step(fse_ctx *ctx, const double *omega, double *Z0, double
 fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, double tol,
                             int32_t maxit, int32_t *iters, double *res_norm);
 
+/* Forcing amplitudes: the load vectors of Eq. (25) become amp_i F_i, with the F given
+ * to fse_init_torus as amplitude 1 (the paper's examples list the amplitudes f_i in
+ * Sec. 4, Tables 1-4).  amp: HOST [e].  Applies to every later call. */
+fse_status fse_set_forcing(fse_ctx *ctx, const double *amp);
+
+/* Secant predictor of a natural-parameter continuation (the zeroth-order form of the
+ * predictor of App. C): Z_next = Z_cur + tau (Z_cur - Z_prev) with
+ * tau = <p_next - p_cur, p_cur - p_prev> / ||p_cur - p_prev||^2.
+ * p_prev, p_cur, p_next: HOST [np] parameter vectors; Z_*: [2n][U] (Z_next may alias
+ * neither input).  FSE_E_INVAL if p_cur == p_prev. */
+fse_status fse_secant_predict(fse_ctx *ctx, int32_t np, const double *p_prev, const double *p_cur,
+                              const double *p_next, const double *Z_prev, const double *Z_cur,
+                              double *Z_next);
+
+/* Natural-parameter continuation over P points (App. C, secant predictor).
+ * params: HOST [P][d+e]; point j has omega = params[j][0:d] and forcing amplitudes
+ * params[j][d:d+e].  Point 0 starts from Z_init [2n][U], point 1 from the solution of
+ * point 0, every later point from the secant prediction of the two previous solutions.
+ * Each point is solved by fse_newton_solve(tol, maxit).  Z_out: [P][2n][U] solutions;
+ * iters, rnorm: HOST [P] Newton iterations and final ||R||_2.  On failure at point j the
+ * status of that point is returned with iters[j] = -1 and later points are not touched.
+ * The forcing amplitudes stay at those of the last point attempted. */
+fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const double *Z_init,
+                            double tol, int32_t maxit, double *Z_out, int32_t *iters,
+                            double *rnorm);
+
 /* Lyapunov exponents of App. F from the sensitivities at Z0: Psi_s of Eq. (F3),
  * trigonometric interpolation on the torus basis at phi~ = 2 pi (i-1) rho,
  * N_Ly steps of Gram-Schmidt as Householder QR with positive diagonal.

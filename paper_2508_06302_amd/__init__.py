@@ -15,8 +15,8 @@ from . import _lib
 
 __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
-           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "FSE_PREC_FP64",
-           "FSE_PREC_MIXED_FP32"]
+           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
+           "fse_secant_predict", "fse_continuation", "FSE_PREC_FP64", "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
 FSE_PREC_MIXED_FP32 = 1
@@ -116,6 +116,7 @@ def fse_init_torus(system, torus, max_batch=1, precision=FSE_PREC_FP64, step_tol
     kt = np.zeros(((U.value + 1) // 2, max(torus.d - 1, 1)), np.int32)
     lib.fse_get_layout(h, None, None, None, _p(kt, C.c_int32))
     ctx = Context(h, lib, n, torus.d, U.value, St.value, bw.value, kt[:, : torus.d - 1])
+    ctx.e = int(F.shape[0])
     ctx.bind_stream()
     return ctx
 
@@ -212,3 +213,45 @@ def fse_last_timing(ctx: Context):
     ctx.check(ctx.lib.fse_last_timing(ctx.h, _p(ms, C.c_double), C.byref(nl)))
     return {"total_ms": ms[0], "state_ms": ms[1], "sens_ms": ms[2], "idft_ms": ms[3],
             "sens_launches": nl.value}
+
+
+def fse_set_forcing(ctx: Context, amp):
+    """Forcing amplitudes (host [e]) multiplying the unit load vectors."""
+    a = np.ascontiguousarray(np.asarray(amp, dtype=np.float64).reshape(ctx.e))
+    ctx.bind_stream()
+    ctx.check(ctx.lib.fse_set_forcing(ctx.h, _p(a, C.c_double)))
+
+
+def fse_secant_predict(ctx: Context, p_prev, p_cur, p_next, Z_prev, Z_cur):
+    """-> Z_next [2n][U] (torch cuda) = Z_cur + tau (Z_cur - Z_prev)."""
+    torch = _torch()
+    ctx.bind_stream()
+    pp = [np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel()) for x in (p_prev, p_cur, p_next)]
+    zp = _dev(Z_prev, (2 * ctx.n, ctx.U))
+    zc = _dev(Z_cur, (2 * ctx.n, ctx.U))
+    zn = torch.empty_like(zc)
+    ctx.check(ctx.lib.fse_secant_predict(ctx.h, len(pp[0]), _p(pp[0], C.c_double), _p(pp[1], C.c_double),
+                                         _p(pp[2], C.c_double), C.c_void_p(zp.data_ptr()),
+                                         C.c_void_p(zc.data_ptr()), C.c_void_p(zn.data_ptr())))
+    return zn
+
+
+def fse_continuation(ctx: Context, params, Z_init, tol=1e-8, maxit=20):
+    """params host [P][d+e] (omega then forcing amplitudes) -> (Z [P][2n][U] torch cuda,
+    iterations [P], final ||R|| [P]).  Raises FseError on a failed point (its iteration
+    count is -1 in the error's .iters)."""
+    torch = _torch()
+    ctx.bind_stream()
+    pr = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, ctx.d + ctx.e))
+    P = pr.shape[0]
+    z0 = _dev(Z_init, (2 * ctx.n, ctx.U))
+    Z = torch.zeros((P, 2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+    it = np.zeros(P, np.int32)
+    rn = np.zeros(P)
+    st = ctx.lib.fse_continuation(ctx.h, P, _p(pr, C.c_double), C.c_void_p(z0.data_ptr()), float(tol),
+                                  int(maxit), C.c_void_p(Z.data_ptr()), _p(it, C.c_int32), _p(rn, C.c_double))
+    if st != 0:
+        err = FseError(st, ctx.lib.fse_last_error(ctx.h).decode())
+        err.iters, err.rnorm, err.Z = it, rn, Z
+        raise err
+    return Z, it, rn

@@ -12,8 +12,8 @@ FSE_STATUS = {0: "FSE_OK", 1: "FSE_E_INVAL", 2: "FSE_E_NOMEM", 3: "FSE_E_DEVICE"
 
 EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
-           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_last_error",
-           "fse_destroy"]
+           "fse_newton_solve", "fse_lyapunov", "fse_set_forcing", "fse_secant_predict",
+           "fse_continuation", "fse_last_timing", "fse_last_error", "fse_destroy"]
 
 i32p = C.POINTER(C.c_int32)
 f64p = C.POINTER(C.c_double)
@@ -60,6 +60,9 @@ def load(path: str = LIB_PATH):
     lib.fse_newton_step.argtypes = [vp, f64p, vp, f64p]
     lib.fse_newton_solve.argtypes = [vp, f64p, vp, C.c_double, C.c_int32, i32p, f64p]
     lib.fse_lyapunov.argtypes = [vp, f64p, vp, C.c_int32, vp, f64p]
+    lib.fse_set_forcing.argtypes = [vp, f64p]
+    lib.fse_secant_predict.argtypes = [vp, C.c_int32, f64p, f64p, f64p, vp, vp, vp]
+    lib.fse_continuation.argtypes = [vp, C.c_int32, f64p, vp, C.c_double, C.c_int32, vp, i32p, f64p]
     lib.fse_last_timing.argtypes = [vp, f64p, i32p]
     lib.fse_last_error.argtypes = [vp]
     lib.fse_last_error.restype = C.c_char_p

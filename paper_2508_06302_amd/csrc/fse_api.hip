@@ -343,7 +343,9 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   FSE_TRY(upload(ctx, &ctx->Mb, Mb));
   FSE_TRY(upload(ctx, &ctx->Db, Db));
   FSE_TRY(upload(ctx, &ctx->Kb, Kb));
-  FSE_TRY(upload(ctx, &ctx->F, std::vector<double>(sys->F, sys->F + (size_t)sys->e * n)));
+  ctx->F_host.assign(sys->F, sys->F + (size_t)sys->e * n);
+  ctx->amp.assign(sys->e, 1.0);
+  FSE_TRY(upload(ctx, &ctx->F, ctx->F_host));
   FSE_TRY(upload(ctx, &ctx->f2_ptr, p2));
   FSE_TRY(upload(ctx, &ctx->f2_jk, jk));
   FSE_TRY(upload(ctx, &ctx->f2_v, v2));
@@ -595,18 +597,24 @@ fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, doubl
                             int32_t *iters, double *res_norm) {
   if (!ctx || !Z0) return FSE_E_INVAL;
   const int N = 2 * ctx->n * ctx->U;
+  if (!ctx->Jw) {
+    FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * (size_t)N * N));
+    ctx->Jw_elems = (size_t)N * N;
+  }
+  // R and J at Z0; every accepted trial point below is evaluated with its Jacobian, so the
+  // next iteration starts from a valid (R, J) pair without integrating again
   double rn = INFINITY;
-  FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &rn, nullptr, nullptr));
+  FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &rn, ctx->Jw, nullptr));
+  bool have_J = true;
   int it = 0;
   for (; it < maxit && !(rn < tol); ++it) {
-    // full Newton direction dZ = -J^-1 R at Z0 (work_R holds J^-1 R after the solve)
-    if (!ctx->Jw) {
-      FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * (size_t)N * N));
-      ctx->Jw_elems = (size_t)N * N;
+    if (!have_J) {
+      double r0 = 0.0;
+      FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &r0, ctx->Jw, nullptr));
     }
-    double r0 = 0.0;
-    FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &r0, ctx->Jw, nullptr));
+    // work_R <- J^-1 R (the Newton direction is -work_R)
     FSE_TRY(dense_lu_solve(ctx, ctx->Jw, N, ctx->work_R));
+    have_J = false;
     // backtracking on ||R||: accept Z - lambda J^-1 R once the residual decreases
     double lam = 1.0;
     bool accepted = false;
@@ -614,13 +622,16 @@ fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, doubl
       FSE_TRY(launch_lincomb(ctx, N, Z0, -lam, ctx->work_R, ctx->Zwork));
       double rt = INFINITY;
       const fse_status st = fse_shooting_residual_jacobian(ctx, 1, omega, ctx->Zwork, ctx->Zwork + N, &rt,
-                                                           nullptr, nullptr);
+                                                           ctx->Jw, nullptr);
       if (st != FSE_OK && st != FSE_E_NOCONV && st != FSE_E_NAN && st != FSE_E_SINGULAR) return st;
       if (st == FSE_OK && rt < (1.0 - 1e-4 * lam) * rn) {
         FSE_HIP(hipMemcpyAsync(Z0, ctx->Zwork, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+        FSE_HIP(hipMemcpyAsync(ctx->work_R, ctx->Zwork + N, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                               ctx->stream));
         FSE_HIP(hipStreamSynchronize(ctx->stream));
         rn = rt;
         accepted = true;
+        have_J = true;
       }
     }
     if (!accepted) {
@@ -635,6 +646,70 @@ fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, doubl
   if (!(rn < tol)) {
     ctx->err = "Newton did not reach the residual tolerance";
     return FSE_E_NOCONV;
+  }
+  return FSE_OK;
+}
+
+fse_status fse_set_forcing(fse_ctx *ctx, const double *amp) {
+  if (!ctx || !amp) return FSE_E_INVAL;
+  const int n = ctx->n, e = ctx->e;
+  std::vector<double> Fs((size_t)e * n);
+  for (int f = 0; f < e; ++f) {
+    if (!std::isfinite(amp[f])) {
+      ctx->err = "non-finite forcing amplitude";
+      return FSE_E_INVAL;
+    }
+    ctx->amp[f] = amp[f];
+    for (int i = 0; i < n; ++i) Fs[(size_t)f * n + i] = amp[f] * ctx->F_host[(size_t)f * n + i];
+  }
+  FSE_HIP(hipMemcpyAsync(ctx->F, Fs.data(), sizeof(double) * Fs.size(), hipMemcpyHostToDevice, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status fse_secant_predict(fse_ctx *ctx, int32_t np, const double *p_prev, const double *p_cur,
+                              const double *p_next, const double *Z_prev, const double *Z_cur,
+                              double *Z_next) {
+  if (!ctx || np < 1 || !p_prev || !p_cur || !p_next || !Z_prev || !Z_cur || !Z_next) return FSE_E_INVAL;
+  double num = 0.0, den = 0.0;
+  for (int i = 0; i < np; ++i) {
+    const double dp = p_cur[i] - p_prev[i];
+    num += (p_next[i] - p_cur[i]) * dp;
+    den += dp * dp;
+  }
+  if (!(den > 0.0)) {
+    ctx->err = "secant predictor needs two distinct parameter points";
+    return FSE_E_INVAL;
+  }
+  const double tau = num / den;
+  const int N = 2 * ctx->n * ctx->U;
+  FSE_TRY(launch_axpby(ctx, N, 1.0 + tau, Z_cur, -tau, Z_prev, Z_next));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const double *Z_init,
+                            double tol, int32_t maxit, double *Z_out, int32_t *iters, double *rnorm) {
+  if (!ctx || P < 1 || !params || !Z_init || !Z_out || !iters || !rnorm) return FSE_E_INVAL;
+  const int np = ctx->d + ctx->e;
+  const size_t N = (size_t)2 * ctx->n * ctx->U;
+  for (int j = 0; j < P; ++j) {
+    const double *pj = params + (size_t)j * np;
+    FSE_TRY(fse_set_forcing(ctx, pj + ctx->d));
+    double *Zj = Z_out + j * N;
+    if (j == 0) {
+      FSE_HIP(hipMemcpyAsync(Zj, Z_init, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    } else if (j == 1) {
+      FSE_HIP(hipMemcpyAsync(Zj, Z_out, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+      FSE_TRY(fse_secant_predict(ctx, np, pj - 2 * np, pj - np, pj, Zj - 2 * N, Zj - N, Zj));
+    }
+    int32_t it = 0;
+    double rn = 0.0;
+    const fse_status st = fse_newton_solve(ctx, pj, Zj, tol, maxit, &it, &rn);
+    iters[j] = st == FSE_OK ? it : -1;
+    rnorm[j] = rn;
+    if (st != FSE_OK) return st;
   }
   return FSE_OK;
 }

@@ -95,6 +95,8 @@ struct fse_ctx {
   double *work_R = nullptr;         // [Bmax][2n][U]
   double *Zwork = nullptr;          // [Bmax][2n][U]
   double *Jw = nullptr;             // dense Jacobian / LU workspace [2nU][2nU]
+  std::vector<double> F_host;   // unit-amplitude load vectors [e][n]
+  std::vector<double> amp;      // forcing amplitudes [e]
   int32_t *piv_d = nullptr;
   int piv_n = 0;
   double *lu_scr = nullptr;
@@ -138,6 +140,7 @@ bool fused_supported(const fse_ctx *ctx);
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
+fse_status launch_axpby(fse_ctx *ctx, int N, double a, const double *x, double b, const double *z, double *y);
 fse_status launch_axpy(fse_ctx *ctx, int N, double alpha, const double *x, double *y);
 fse_status launch_lincomb(fse_ctx *ctx, int N, const double *x, double alpha, const double *d, double *y);
 fse_status lyapunov_qr(fse_ctx *ctx, const double *PhiQU, const double *omega_h, int N_Ly,

@@ -220,6 +220,12 @@ __global__ void k_lu_unpermute(double *__restrict__ x, int N, const int32_t *__r
   }
 }
 
+__global__ void k_axpby(int N, double a, const double *__restrict__ x, double b, const double *__restrict__ z,
+                        double *__restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) y[i] = a * x[i] + b * z[i];
+}
+
 __global__ void k_lincomb(int N, const double *__restrict__ x, double alpha, const double *__restrict__ d,
                           double *__restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -444,6 +450,12 @@ fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
 
 fse_status launch_lincomb(fse_ctx *ctx, int N, const double *x, double alpha, const double *d, double *y) {
   hipLaunchKernelGGL(k_lincomb, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, x, alpha, d, y);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_axpby(fse_ctx *ctx, int N, double a, const double *x, double b, const double *z, double *y) {
+  hipLaunchKernelGGL(k_axpby, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, N, a, x, b, z, y);
   FSE_HIP(hipGetLastError());
   return FSE_OK;
 }

@@ -205,3 +205,46 @@ def test_newton_step_ragged_lu():
     rn = fse().fse_newton_step(ctx, om, Zg)
     assert abs(rn - rn_o) < RTOL * rn_o
     assert rel(Zg.cpu().numpy() - Z0, Zo - Z0) < 1e-9
+
+
+def test_secant_predict_matches_oracle():
+    from oracle import learned as olearn
+    s, tr, tb, om, Z0 = _tiny_case()
+    rng = np.random.default_rng(11)
+    Zp, Zc = rng.normal(size=Z0.shape), rng.normal(size=Z0.shape)
+    pp, pc, pn = rng.normal(size=4), rng.normal(size=4), rng.normal(size=4)
+    ctx = fse().fse_init_torus(s, tr)
+    Zn = fse().fse_secant_predict(ctx, pp, pc, pn, Zp, Zc).cpu().numpy()
+    assert rel(Zn, olearn.secant_predict(pp, pc, pn, Zp, Zc)) < 1e-14
+    m = fse()
+    with pytest.raises(m.FseError, match="FSE_E_INVAL"):
+        m.fse_secant_predict(ctx, pc, pc, pn, Zp, Zc)
+
+
+def test_forcing_amplitude_continuation_c1():
+    """Natural-parameter continuation in the forcing amplitude (secant predictor):
+    every point converged, re-evaluated by the oracle with the scaled loads."""
+    import copy
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    amps = [0.25, 0.5, 0.75, 1.0]
+    params = np.array([[*wl.omega, a, a] for a in amps])
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    # ||R|| < 1e-12: the displacements are ~1e-4 m, so an absolute 1e-8 would leave the
+    # solution defined only to ~1e-6 relative
+    Z, it, rn = fse().fse_continuation(ctx, params, Z0, tol=1e-12, maxit=10)
+    log(f"continuation iterations {it.tolist()} residuals {rn.tolist()}")
+    assert np.all(it >= 0) and np.all(rn < 1e-12)
+    ro = []
+    for j, a in enumerate(amps):
+        sj = copy.copy(wl.system)
+        sj.F = wl.system.F * a
+        ref = osh.evaluate(sj, wl.torus, wl.omega, Z[j].cpu().numpy(), tables=tb)
+        fse().fse_set_forcing(ctx, [a, a])
+        _, rg, _ = fse().fse_shooting_residual_jacobian(ctx, wl.omega[None], Z[j][None])
+        ro.append((float(np.linalg.norm(ref["R"])), float(rg[0])))
+    log(f"oracle / gpu residual at the gpu solutions: {ro}")
+    assert all(r[0] < 1e-10 for r in ro)
+    Zo, _, _ = osh.solve(wl.system, wl.torus, wl.omega, Z0, tol_R=1e-12, tables=tb)
+    assert rel(Z[-1].cpu().numpy(), Zo) < 1e-8
