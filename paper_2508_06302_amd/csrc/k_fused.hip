@@ -143,7 +143,7 @@ __device__ void assemble_T(const TensLds &t, int n, const double *__restrict__ S
 // In-place banded LDL^T by one lane with a register window (padded storage, see
 // file header).  Returns false on a zero or non-finite pivot.
 template <int BW>
-__device__ bool ldlt_serial(double *Fp, int n) {
+__device__ bool ldlt_serial_shift(double *Fp, int n) {
   constexpr int bp = BW + 1;
   double *F = Fp + BW * bp;
   double Wn[BW + 1][BW + 1];
@@ -183,7 +183,7 @@ __device__ bool ldlt_serial(double *Fp, int n) {
 // are loaded while the current row is reduced, and the term with the most recent
 // unknown is applied last, so each row adds one dependent FMA to the critical path.
 template <int BW>
-__device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
+__device__ void ldlt_solve_shift(const double *Fp, int n, double *x) {
   constexpr int bp = BW + 1;
   const double *F = Fp + BW * bp;
   double yw[BW], cf[BW + 1], cn[BW + 1];
@@ -242,6 +242,144 @@ __device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
 #pragma unroll
     for (int t = 0; t <= BW; ++t) cf[t] = cn[t];
   }
+}
+
+// Register-ring variants for half bandwidths up to 6 (P = BW + 1 slots).
+// Factorisation: entry A(R, C) of the active window lives in G[R % P][C % P]; with the
+// column loop unrolled by P every slot index is a compile-time constant, so the window
+// never moves between registers.  The row entering the window after column j (row
+// j + P) is loaded at the end of column j, one column ahead of its first use.
+template <int BW>
+__device__ bool ldlt_serial_ring(double *Fp, int n) {
+  constexpr int P = BW + 1, bp = BW + 1;
+  double *F = Fp + BW * bp;
+  double G[P][P];
+#pragma unroll
+  for (int r = 0; r < P; ++r)
+#pragma unroll
+    for (int c = 0; c < P; ++c) G[r][c] = (c <= r && r < n) ? F[c * bp + (r - c)] : 0.0;
+  bool ok = true;
+  for (int j0 = 0; j0 < n; j0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int j = j0 + u;
+      if (j >= n) break;
+      const double d = G[u][u];
+      ok = ok && (d != 0.0) && isfinite(d);
+      // reciprocal: hardware estimate refined by one Newton step
+      double inv = __builtin_amdgcn_rcp(d);
+      inv = fma(inv, fma(-d, inv, 1.0), inv);
+      double l[P];
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) l[t] = G[(u + t) % P][u] * inv;
+      F[j * bp] = inv;
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) F[j * bp + t] = l[t];
+#pragma unroll
+      for (int r = 1; r <= BW; ++r)
+#pragma unroll
+        for (int c = 1; c <= r; ++c) G[(u + r) % P][(u + c) % P] -= G[(u + r) % P][u] * l[c];
+      // row R = j + P enters slot u: A(R, C) for C = j + 1 .. j + P
+      const int R = j + P;
+      const bool in = R < n;
+#pragma unroll
+      for (int c = 0; c <= BW; ++c) {
+        const int C = j + 1 + c;
+        G[u][(u + 1 + c) % P] = in ? F[C * bp + (R - C)] : 0.0;
+      }
+    }
+  }
+  return ok;
+}
+
+// Solve (L D L^T) x = x in place by one lane; step k of each sweep keeps its result in
+// slot k % P of a register ring and the coefficients of step k + P are loaded when step
+// k retires, P steps before they are needed.  The term of the newest unknown is
+// applied last, so each row adds one dependent FMA to the critical path.
+template <int BW>
+__device__ void ldlt_solve_ring(const double *Fp, int n, double *x) {
+  constexpr int P = BW + 1, bp = BW + 1;
+  const double *F = Fp + BW * bp;
+  double y[P], cf[P][P], xv[P];
+  // forward: row i = k, coefficients L(i, i - t) = F[(i - t) bp + t]
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int ir = u < n ? u : n - 1;
+    y[u] = 0.0;
+    xv[u] = x[ir];
+#pragma unroll
+    for (int t = 1; t <= BW; ++t) cf[u][t] = F[(ir - t) * bp + t];
+  }
+  for (int k0 = 0; k0 < n; k0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int i = k0 + u;
+      if (i >= n) break;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = BW; t >= 2; --t) {
+        if ((t & 1) == 0)
+          s0 += cf[u][t] * y[(u - t + P) % P];
+        else
+          s1 += cf[u][t] * y[(u - t + P) % P];
+      }
+      const double acc = (xv[u] - (s0 + s1)) - cf[u][1] * y[(u - 1 + P) % P];
+      y[u] = acc;
+      x[i] = acc;
+      const int ir = i + P < n ? i + P : n - 1;
+      xv[u] = x[ir];
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) cf[u][t] = F[(ir - t) * bp + t];
+    }
+  }
+  // backward: row i = n - 1 - k, coefficients D^-1 = F[i bp], L(i + t, i) = F[i bp + t]
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int ir = n - 1 - u >= 0 ? n - 1 - u : 0;
+    y[u] = 0.0;
+    xv[u] = x[ir];
+#pragma unroll
+    for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
+  }
+  for (int k0 = 0; k0 < n; k0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int k = k0 + u;
+      if (k >= n) break;
+      const int i = n - 1 - k;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = BW; t >= 2; --t) {
+        if ((t & 1) == 0)
+          s0 += cf[u][t] * y[(u - t + P) % P];
+        else
+          s1 += cf[u][t] * y[(u - t + P) % P];
+      }
+      const double acc = (xv[u] * cf[u][0] - (s0 + s1)) - cf[u][1] * y[(u - 1 + P) % P];
+      y[u] = acc;
+      x[i] = acc;
+      const int ir = i - P >= 0 ? i - P : 0;
+      xv[u] = x[ir];
+#pragma unroll
+      for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
+    }
+  }
+}
+
+template <int BW>
+__device__ bool ldlt_serial(double *Fp, int n) {
+  if constexpr (BW <= 6)
+    return ldlt_serial_ring<BW>(Fp, n);
+  else
+    return ldlt_serial_shift<BW>(Fp, n);
+}
+
+template <int BW>
+__device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
+  if constexpr (BW <= 6)
+    ldlt_solve_ring<BW>(Fp, n, x);
+  else
+    ldlt_solve_shift<BW>(Fp, n, x);
 }
 
 // Per-point padded bands: S = w1^2 c0 M + w1 c2 D + K, w1^2 M, w1 D; and K itself.
