@@ -2,14 +2,15 @@
 // trajectory in one work-group (App. E), for half bandwidths up to 16.
 //
 // Work-group (p, w): trajectory w, sensitivity columns [p*64*NCW, (p+1)*64*NCW).
-// A three-stage pipeline, one barrier per stage step:
+// A four-stage pipeline, one barrier per stage step:
 //   wave 0  state      step k: q_k -> q_{k+1} (Eqs. E4-E7).  Eq. (E6) is solved by a
-//                      chord Newton whose matrix is the exact tangent T(q_{k-1}) =
-//                      S + K_t(q_{k-1}) factored by wave 1 (contraction ~1e-3 for
-//                      smooth responses); if the contraction is poor the wave
-//                      assembles and factors T at the current iterate itself.
-//   wave 1  factor     step k: assemble T(q_k) and factor it (banded LDL^T).
-//   waves 2.. columns  step k: advance [Q; U; A] from step k-2 to k-1 with the factor
+//                      chord Newton whose matrix is the exact tangent at a two-step
+//                      prediction of q_{k+1}, factored one step ahead by wave 1; if the
+//                      contraction is poor the wave refactors T at its own iterate.
+//   wave 1  chord      step k: T(q^_{k+2}) with q^_{k+2} = q_k + 2h u_k,
+//                      assembled and factored (banded LDL^T) for state step k + 1.
+//   wave 2  tangent    step k: T(q_k) = S + K_t(q_k) at the converged state, factored.
+//   waves 3.. columns  step k: advance [Q; U; A] from step k-2 to k-1 with the factor
 //                      of T(q_{k-1}) (exact derivative of the converged discrete map,
 //                      Eqs. E8-E9); in step 0 they form Q_0, U_0, A_0.
 // The chord stops once ||dq||_inf <= 1e-3 tol ||q||_inf, or once the linear-convergence
@@ -18,8 +19,10 @@
 // leave no more error than a full Newton step that stops at tol.  An update that stops
 // shrinking below tol ||q|| is the FP64 noise floor of the residual and ends the step.
 // On poor contraction (rho >= 1/4) above tol the state wave refactors T at the current
-// iterate once and continues; if that fails too it restarts from the predictor with full
-// Newton, which stops on ||dq||_inf <= tol ||q||_inf or stagnation below 1e3 tol.
+// iterate once and continues (stagnation below 1e3 tol with that fresh tangent is the
+// noise floor); if that fails too, or the chord spends maxit iterations, it restarts
+// from the predictor with full Newton and a fresh budget of maxit iterations, which
+// stops on ||dq||_inf <= tol ||q||_inf or stagnation below 1e3 tol.
 //
 // Banded data are padded to the compile-time half bandwidth BW >= bw with zeros:
 //   full rows  [n][2BW+1]   entry (i, j) at [i][j - i + BW]      (global, per point)
@@ -524,7 +527,7 @@ __device__ void sens_step(const double *F, const double *__restrict__ Mwp, const
 }
 
 template <int BW>
-__global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__restrict__ Sp_all,
+__global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__restrict__ Sp_all,
                                                const double *__restrict__ Mwp_all,
                                                const double *__restrict__ Dwp_all,
                                                const double *__restrict__ Kp) {
@@ -535,7 +538,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
   const int w = blockIdx.y;
   const int b = w / P.St, s = w - b * P.St;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ncw = (blockDim.x >> 6) - 2;
+  const int ncw = (blockDim.x >> 6) - 3;
   const double *om = a.omega + b * P.d;
   // read-only per-point bands; __restrict__ lets uniform row reads use the scalar path
   const double *__restrict__ Sp = Sp_all + (size_t)b * n * W2;
@@ -545,9 +548,11 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
   const size_t fb = (size_t)(n + BW) * bp;   // one padded factor buffer
   double *FM = smem;                         // factor of w1^2 M
   double *KtB = FM + fb;                     // lower band of K + K_t(q0) (same padding)
-  double *FT0 = KtB + fb;                    // factors of T, double buffered
+  double *FT0 = KtB + fb;                    // factors of T(q_k), double buffered
   double *FT1 = FT0 + fb;
-  double *FR = FT1 + fb;                     // state-wave refresh factor
+  double *CB0 = FT1 + fb;                    // chord factors T(predicted q), double buffered
+  double *CB1 = CB0 + fb;
+  double *FR = CB1 + fb;                     // state-wave refresh factor
   double *q = FR + fb;
   double *u = q + n;
   double *acc = u + n;
@@ -556,7 +561,9 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
   double *r = bv + n;
   double *qs0 = r + n;                       // q_k handed to the factor wave
   double *qs1 = qs0 + n;
-  double *cs = qs1 + n;                      // forcing cosines [8]
+  double *pq0 = qs1 + n;                     // two-step predictions handed to the chord wave
+  double *pq1 = pq0 + n;
+  double *cs = pq1 + n;                      // forcing cosines [8]
   double *tv2 = cs + 8;                      // staged polynomial forces
   double *tv3 = tv2 + a.nnz2;
   int *tp2 = reinterpret_cast<int *>(tv3 + a.nnz3);
@@ -568,7 +575,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
   __shared__ int s_flags;
 
   // ============================================================ prologue
-  for (int e = threadIdx.x; e < (int)(5 * fb); e += blockDim.x) smem[e] = 0.0;
+  for (int e = threadIdx.x; e < (int)(7 * fb); e += blockDim.x) smem[e] = 0.0;
   for (int e = threadIdx.x; e <= n; e += blockDim.x) {
     tp2[e] = a.f2_ptr[e];
     tp3[e] = a.f3_ptr[e];
@@ -587,7 +594,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
     s_flags = 0;
   }
   __syncthreads();
-  if (wave == 0 || wave == 1) {
+  if (wave == 0 || wave == 2) {
     for (int i = lane; i < n; i += 64) {
       const double qi = a.q0[(size_t)i * a.ldw + w];
       if (wave == 0) {
@@ -599,7 +606,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
     }
   }
   __syncthreads();
-  if (wave == 1) {
+  if (wave == 2) {
     // w1^2 M, K + K_t(q0) and T(q0) = S + K_t(q0) lower bands; factor w1^2 M and T(q0)
     assemble_T<BW>(tl, n, Sp, qs0, FT0, lane);
     assemble_T<BW>(tl, n, Kp, qs0, KtB, lane);
@@ -636,12 +643,24 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
   if (wave == 0) {
     if (lane == 0) ldlt_solve_serial<BW>(FM, n, acc);
     wave_sync();
+    // first-order predictions q^_1 = q0 + h u0 (chord of step 0, into qn) and
+    // q^_2 = q0 + 2h u0 (chord of step 1, into pq0)
+    for (int i = lane; i < n; i += 64) {
+      qn[i] = q[i] + P.h * u[i];
+      pq0[i] = q[i] + 2.0 * P.h * u[i];
+    }
+  }
+  __syncthreads();
+  if (wave == 1) {
+    assemble_T<BW>(tl, n, Sp, qn, CB0, lane);
+    wave_sync();
+    if (lane == 0 && !ldlt_serial<BW>(CB0, n)) s_flags |= DEV_SINGULAR;
   }
   __syncthreads();
 
   // ============================================================ pipeline
-  const int c = blockIdx.x * (64 * ncw) + (wave - 2) * 64 + lane;
-  const bool colw = wave >= 2 && c < n2 && a.Phi != nullptr;
+  const int c = blockIdx.x * (64 * ncw) + (wave - 3) * 64 + lane;
+  const bool colw = wave >= 3 && c < n2 && a.Phi != nullptr;
   double *Qc = a.Phi ? a.Phi + (size_t)w * n2 * n2 + c : nullptr;
   double *Uc = a.Phi ? Qc + (size_t)n * n2 : nullptr;
   double *Ac = a.PhiA + (size_t)w * n * n2 + c;
@@ -652,9 +671,10 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
 
   for (int k = 0; k <= last; ++k) {
     if (wave == 0 && k < P.S1) {
-      // ---------------- state step k: q_k -> q_{k+1}; chord T(q_{k-1}) = FT[(k-1)&1]
-      const double *Fc = (k == 0) ? FT0 : (((k - 1) & 1) ? FT1 : FT0);
+      // ---------------- state step k: q_k -> q_{k+1}; chord matrix CB[k&1] = T(q^_{k+1})
+      const double *Fc = (k & 1) ? CB1 : CB0;
       double *qsn = ((k + 1) & 1) ? qs1 : qs0;
+      double *pqn = ((k + 1) & 1) ? pq1 : pq0;
       const double phi1 = (double)(k + 1) * P.h;
       if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s);
       wave_sync();
@@ -675,8 +695,19 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
       double prev = INFINITY;
       bool conv = false, full = false, refreshed = false;
       const double *Fcur = Fc;
-      int it = 0;
-      for (; it < P.maxit && !conv; ++it) {
+      int it = 0, itc = 0;  // total iterations; iterations of the current mode (chord / full)
+      while (!conv) {
+        if (itc >= P.maxit) {
+          if (full) break;
+          // chord budget spent: restart from the predictor with full Newton
+          for (int i = lane; i < n; i += 64) qn[i] = q[i] + P.h * u[i] + 0.5 * P.h * P.h * acc[i];
+          wave_sync();
+          full = true;
+          prev = INFINITY;
+          itc = 0;
+        }
+        ++it;
+        ++itc;
         if (full) {
           // full Newton: exact tangent at the current iterate
           assemble_T<BW>(tl, n, Sp, qn, FR, lane);
@@ -713,10 +744,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
         const double rho = prev < INFINITY ? nd / prev : 1.0;
         if (full) {
           // quadratic convergence: same rule as a full Newton step (App. E reading)
-          if (!finite) {
-            it = P.maxit;
-            break;
-          }
+          if (!finite) break;
           if (nd <= tolq || (nd <= 1e3 * tolq && nd > 0.5 * prev)) conv = true;
           prev = nd;
         } else if (finite && nd <= kChordFloor * tolq) {
@@ -730,6 +758,8 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
           prev = nd;
         } else if (finite && nd <= tolq) {
           conv = true;  // no further contraction below tol: FP64 noise floor of the residual
+        } else if (finite && refreshed && nd <= 1e3 * tolq && rho > 0.5) {
+          conv = true;  // stagnation with a fresh tangent: the noise floor lies above tol
         } else if (finite && !refreshed) {
           // poor contraction: refresh the chord matrix at the current iterate and go on
           assemble_T<BW>(tl, n, Sp, qn, FR, lane);
@@ -745,6 +775,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
           wave_sync();
           full = true;
           prev = INFINITY;
+          itc = 0;
         }
       }
       if (!conv && lane == 0) {
@@ -761,9 +792,19 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
         acc[i] = an;
         q[i] = qn[i];
         qsn[i] = qn[i];
+        // two-step first-order prediction of q_{k+3} for the chord wave
+        pqn[i] = qn[i] + 2.0 * P.h * un;
       }
       wave_sync();
-    } else if (wave == 1 && k >= 1 && k <= P.S1) {
+    } else if (wave == 1 && k + 1 < P.S1) {
+      // ---------------- chord step k: T(q^_{k+2}) -> CB[(k+1)&1]
+      double *Cn = ((k + 1) & 1) ? CB1 : CB0;
+      const double *qp = (k & 1) ? pq1 : pq0;
+      assemble_T<BW>(tl, n, Sp, qp, Cn, lane);
+      wave_sync();
+      if (lane == 0 && !ldlt_serial<BW>(Cn, n)) s_flags |= DEV_SINGULAR;
+      wave_sync();
+    } else if (wave == 2 && k >= 1 && k <= P.S1) {
       // ---------------- factor step k: T(q_k) -> FT[k&1]
       double *Fn = (k & 1) ? FT1 : FT0;
       const double *qk = (k & 1) ? qs1 : qs0;
@@ -840,7 +881,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs a, const double *__rest
 
 template <int BW>
 size_t fused_lds_bytes(int n, int nnz2, int nnz3) {
-  return sizeof(double) * ((size_t)5 * (n + BW) * (BW + 1) + 8 * (size_t)n + 8 + nnz2 + nnz3) +
+  return sizeof(double) * ((size_t)7 * (n + BW) * (BW + 1) + 10 * (size_t)n + 8 + nnz2 + nnz3) +
          sizeof(int) * (2 * ((size_t)n + 1) + nnz2 + 2 * (size_t)nnz3);
 }
 
@@ -897,7 +938,7 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   FSE_HIP(hipFuncSetAttribute((const void *)k_fused<BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
   dim3 grid(nblk, P.W);
-  hipLaunchKernelGGL(k_fused<BW>, grid, dim3(64 * (2 + ncw)), lds, ctx->stream, a, ctx->Sp, ctx->Mwp,
+  hipLaunchKernelGGL(k_fused<BW>, grid, dim3(64 * (3 + ncw)), lds, ctx->stream, a, ctx->Sp, ctx->Mwp,
                      ctx->Dwp, ctx->Kp);
   FSE_HIP(hipGetLastError());
   ctx->last_sens_launches = Phi ? 1 : 0;
@@ -920,7 +961,7 @@ size_t lds_for(const fse_ctx *ctx) {
 }  // namespace
 
 bool fused_supported(const fse_ctx *ctx) {
-  return ctx->bw <= 16 && ctx->n < 65536 && ctx->f2_pk && ctx->f3_pk && lds_for(ctx) <= 150 * 1024 &&
+  return ctx->bw <= 16 && ctx->n < 65536 && ctx->f2_pk && ctx->f3_pk && lds_for(ctx) + 64 <= 160 * 1024 &&
          ctx->fused_ncw >= 1 && ctx->fused_ncw <= 2;
 }
 
