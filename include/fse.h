@@ -54,7 +54,11 @@ typedef enum {
 
 typedef enum {
   FSE_PREC_FP64 = 0,        /* FP64 everywhere                                            */
-  FSE_PREC_MIXED_FP32 = 1   /* sensitivities propagated in FP32 with FP64 state/residuals */
+  FSE_PREC_MIXED_FP32 = 1   /* sensitivity state [Q; U; A] stored in FP32 (FP64 arithmetic),
+                               Phi returned widened to FP64; state, residuals, Jacobian
+                               assembly and Newton stay FP64.  The Newton iteration on the
+                               FP64 residual refines away the Jacobian's FP32 error.
+                               Needs the fused kernel (FSE_E_UNSUPPORTED otherwise). */
 } fse_precision;
 
 /* System of Eq. (1) with Theta = I.  Matrices in CSR (0-based, sorted column

@@ -127,10 +127,6 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     ctx->err = "unknown precision";
     return FSE_E_INVAL;
   }
-  if (desc->precision == FSE_PREC_MIXED_FP32) {
-    ctx->err = "FP32 sensitivity propagation is not implemented";
-    return FSE_E_UNSUPPORTED;
-  }
   if (desc->e < desc->d) {
     ctx->err = "unknown base frequencies (d > e) are not implemented";
     return FSE_E_UNSUPPORTED;
@@ -463,6 +459,10 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
   FSE_TRY(launch_idft(ctx, B, Z0));
   FSE_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
   const bool fused = ctx->use_fused && fused_supported(ctx);
+  if (!fused && Phi && ctx->prec == FSE_PREC_MIXED_FP32) {
+    ctx->err = "FP32 sensitivities need the fused kernel (half bandwidth <= 16, LDS fit)";
+    return FSE_E_UNSUPPORTED;
+  }
   if (fused) {
     FSE_TRY(launch_fused(ctx, B, Phi));
     FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));

@@ -29,6 +29,7 @@
 //   LDL^T      [n+BW][BW+1] entry (j + r, j) at [BW + j][r]; [BW + j][0] = 1 / d_j;
 //                           the BW leading columns are zero so sweeps need no guards.
 #include <climits>
+#include <type_traits>
 #include <cmath>
 
 #include "fse_internal.h"
@@ -66,8 +67,8 @@ struct FusedArgs {
   int ldw;
   double *zT;                              // [2n][ldw]
   double *Phi;                             // [W][2n][2n] or null
-  double *PhiA;                            // [W][n][2n]
-  double *Ysc;                             // [W][n][2n]
+  void *colQ, *colU, *colA, *colY;         // column state [n][2n] blocks (CT elements)
+  size_t colQ_ws, colU_ws, colA_ws, colY_ws;  // element stride between trajectories
   DevStatus *st;
 };
 
@@ -426,57 +427,75 @@ constexpr int kRB = 8;   // rows per block in the sensitivity sweeps
 constexpr double kChordFloor = 1e-3;
 constexpr double kChordBound = 1e-2;
 
-// One sensitivity step for the column owned by this lane (Eqs. E8-E9): RHS formation as
-// an independent pass over row blocks, then the forward and backward substitutions
-// whose per-block loads are all issued before the dependent chain.
-template <int BW>
+// One sensitivity step for the column owned by this lane (Eqs. E8-E9).  Column state
+// [Q; U; A] and the solve scratch Y are stored as CT (double, or float for the mixed
+// path); arithmetic is FP64.  Pass A walks the rows upwards in blocks of kRB: the block's
+// rows of Q, U, A are loaded together (the 2 BW rows of overlap stay in registers), the
+// right-hand side w1^2 M (c0 Q + c1 U + A) + w1 D (c2 Q + U) is formed and immediately
+// forward-substituted with the unit lower factor.  Pass B walks back down: D^-1 and the
+// backward substitution, then the Newmark update of [Q; U; A].
+template <int BW, typename CT>
 __device__ void sens_step(const double *F, const double *__restrict__ Mwp, const double *__restrict__ Dwp,
-                          int n, int n2, double c0, double c1, double c2, double *__restrict__ Qc,
-                          double *__restrict__ Uc, double *__restrict__ Ac, double *__restrict__ Yc) {
+                          int n, int n2, double c0, double c1, double c2, CT *__restrict__ Qc,
+                          CT *__restrict__ Uc, CT *__restrict__ Ac, CT *__restrict__ Yc) {
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  // pass 1: Y_i = w1^2 M (c0 Q + c1 U + A)_i + w1 D (c2 Q + U)_i
-  for (int i0 = 0; i0 < n; i0 += kRB) {
-    constexpr int NR = kRB + 2 * BW;
-    double v1[NR], v2[NR];
+  constexpr int NR = kRB + 2 * BW;
+  double v1[NR], v2[NR], yw[BW];
 #pragma unroll
-    for (int t = 0; t < NR; ++t) {
-      const int j = i0 - BW + t;
-      double Qj = 0.0, Uj = 0.0, Aj = 0.0;
-      if (j >= 0 && j < n) {
-        Qj = Qc[(size_t)j * n2];
-        Uj = Uc[(size_t)j * n2];
-        Aj = Ac[(size_t)j * n2];
-      }
-      v1[t] = c0 * Qj + c1 * Uj + Aj;
-      v2[t] = c2 * Qj + Uj;
+  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+  // rows -BW .. BW-1 of the first window (rows 0 .. BW-1 loaded together)
+  {
+    CT Qn[BW], Un[BW], An[BW];
+#pragma unroll
+    for (int t = 0; t < BW; ++t) {
+      const int j = min(t, n - 1);
+      Qn[t] = Qc[(size_t)j * n2];
+      Un[t] = Uc[(size_t)j * n2];
+      An[t] = Ac[(size_t)j * n2];
+    }
+#pragma unroll
+    for (int t = 0; t < BW; ++t) {
+      v1[t] = 0.0;
+      v2[t] = 0.0;
+      const bool in = t < n;
+      const double Qj = in ? (double)Qn[t] : 0.0, Uj = in ? (double)Un[t] : 0.0;
+      const double Aj = in ? (double)An[t] : 0.0;
+      v1[BW + t] = c0 * Qj + c1 * Uj + Aj;
+      v2[BW + t] = c2 * Qj + Uj;
+    }
+  }
+  for (int i0 = 0; i0 < n; i0 += kRB) {
+    // new rows i0+BW .. i0+BW+kRB-1 into window slots 2BW .. NR-1; every load is issued
+    // (rows past n read row n-1 and are zeroed afterwards) before any is used
+    CT Qn[kRB], Un[kRB], An[kRB];
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      const int j = min(i0 + BW + d, n - 1);
+      Qn[d] = Qc[(size_t)j * n2];
+      Un[d] = Uc[(size_t)j * n2];
+      An[d] = Ac[(size_t)j * n2];
     }
 #pragma unroll
     for (int d = 0; d < kRB; ++d) {
+      const bool in = i0 + BW + d < n;
+      const double Qj = in ? (double)Qn[d] : 0.0, Uj = in ? (double)Un[d] : 0.0;
+      const double Aj = in ? (double)An[d] : 0.0;
+      v1[2 * BW + d] = c0 * Qj + c1 * Uj + Aj;
+      v2[2 * BW + d] = c2 * Qj + Uj;
+    }
+    double yb[kRB];
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
       const int i = i0 + d;
+      double acc = 0.0;
       if (i < n) {
         const double *mr = Mwp + (size_t)i * W2;
         const double *dr = Dwp + (size_t)i * W2;
-        double rhs = 0.0;
 #pragma unroll
-        for (int t = 0; t < W2; ++t) rhs += mr[t] * v1[d + t] + dr[t] * v2[d + t];
-        Yc[(size_t)i * n2] = rhs;
+        for (int t = 0; t < W2; ++t) acc += mr[t] * v1[d + t] + dr[t] * v2[d + t];
+#pragma unroll
+        for (int t = BW; t >= 1; --t) acc -= F[(i - t) * bp + t] * yw[t - 1];
       }
-    }
-  }
-  // pass 2: forward substitution with the unit lower factor
-  double yw[BW];
-#pragma unroll
-  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-  for (int i0 = 0; i0 < n; i0 += kRB) {
-    double yb[kRB];
-#pragma unroll
-    for (int d = 0; d < kRB; ++d) yb[d] = (i0 + d < n) ? Yc[(size_t)(i0 + d) * n2] : 0.0;
-#pragma unroll
-    for (int d = 0; d < kRB; ++d) {
-      const int i = i0 + d;
-      double acc = yb[d];
-#pragma unroll
-      for (int t = BW; t >= 1; --t) acc -= F[(i - t) * bp + t] * yw[t - 1];
 #pragma unroll
       for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
       yw[0] = acc;
@@ -484,23 +503,36 @@ __device__ void sens_step(const double *F, const double *__restrict__ Mwp, const
     }
 #pragma unroll
     for (int d = 0; d < kRB; ++d)
-      if (i0 + d < n) Yc[(size_t)(i0 + d) * n2] = yb[d];
+      if (i0 + d < n) Yc[(size_t)(i0 + d) * n2] = (CT)yb[d];
+    // slide the window by kRB rows
+#pragma unroll
+    for (int t = 0; t < 2 * BW; ++t) {
+      v1[t] = v1[t + kRB];
+      v2[t] = v2[t + kRB];
+    }
   }
-  // pass 3: backward substitution and the Newmark update of [Q; U; A]
+  // pass B: backward substitution and the Newmark update of [Q; U; A]
 #pragma unroll
   for (int t = 0; t < BW; ++t) yw[t] = 0.0;
   const int nb = (n + kRB - 1) / kRB;
   for (int blk = nb - 1; blk >= 0; --blk) {
     const int i0 = blk * kRB;
+    CT ry[kRB], rq[kRB], ru[kRB], ra[kRB];
+#pragma unroll
+    for (int d = 0; d < kRB; ++d) {
+      const int i = min(i0 + d, n - 1);
+      ry[d] = Yc[(size_t)i * n2];
+      rq[d] = Qc[(size_t)i * n2];
+      ru[d] = Uc[(size_t)i * n2];
+      ra[d] = Ac[(size_t)i * n2];
+    }
     double yb[kRB], qb[kRB], ub[kRB], ab[kRB];
 #pragma unroll
     for (int d = 0; d < kRB; ++d) {
-      const int i = i0 + d;
-      const bool in = i < n;
-      yb[d] = in ? Yc[(size_t)i * n2] : 0.0;
-      qb[d] = in ? Qc[(size_t)i * n2] : 0.0;
-      ub[d] = in ? Uc[(size_t)i * n2] : 0.0;
-      ab[d] = in ? Ac[(size_t)i * n2] : 0.0;
+      yb[d] = (double)ry[d];
+      qb[d] = (double)rq[d];
+      ub[d] = (double)ru[d];
+      ab[d] = (double)ra[d];
     }
 #pragma unroll
     for (int d = kRB - 1; d >= 0; --d) {
@@ -519,14 +551,14 @@ __device__ void sens_step(const double *F, const double *__restrict__ Mwp, const
       const int i = i0 + d;
       if (i >= n) continue;
       const double dQ = yb[d] - qb[d];
-      Uc[(size_t)i * n2] = c2 * dQ - ub[d];
-      Ac[(size_t)i * n2] = c0 * dQ - c1 * ub[d] - ab[d];
-      Qc[(size_t)i * n2] = yb[d];
+      Uc[(size_t)i * n2] = (CT)(c2 * dQ - ub[d]);
+      Ac[(size_t)i * n2] = (CT)(c0 * dQ - c1 * ub[d] - ab[d]);
+      Qc[(size_t)i * n2] = (CT)yb[d];
     }
   }
 }
 
-template <int BW>
+template <int BW, typename CT>
 __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__restrict__ Sp_all,
                                                const double *__restrict__ Mwp_all,
                                                const double *__restrict__ Dwp_all,
@@ -661,10 +693,10 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
   // ============================================================ pipeline
   const int c = blockIdx.x * (64 * ncw) + (wave - 3) * 64 + lane;
   const bool colw = wave >= 3 && c < n2 && a.Phi != nullptr;
-  double *Qc = a.Phi ? a.Phi + (size_t)w * n2 * n2 + c : nullptr;
-  double *Uc = a.Phi ? Qc + (size_t)n * n2 : nullptr;
-  double *Ac = a.PhiA + (size_t)w * n * n2 + c;
-  double *Yc = a.Ysc + (size_t)w * n * n2 + c;
+  CT *Qc = static_cast<CT *>(a.colQ) + (size_t)w * a.colQ_ws + c;
+  CT *Uc = static_cast<CT *>(a.colU) + (size_t)w * a.colU_ws + c;
+  CT *Ac = static_cast<CT *>(a.colA) + (size_t)w * a.colA_ws + c;
+  CT *Yc = static_cast<CT *>(a.colY) + (size_t)w * a.colY_ws + c;
   int max_it = 0;
   unsigned long long tot_it = 0;
   const int last = a.Phi ? P.S1 + 1 : P.S1 - 1;
@@ -836,27 +868,37 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
 #pragma unroll
         for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
         yw[0] = v;
-        Yc[(size_t)i * n2] = v;
+        Yc[(size_t)i * n2] = (CT)v;
       }
 #pragma unroll
       for (int t = 0; t < BW; ++t) yw[t] = 0.0;
       for (int i = n - 1; i >= 0; --i) {
-        double v = Yc[(size_t)i * n2] * F[i * bp];
+        double v = (double)Yc[(size_t)i * n2] * F[i * bp];
 #pragma unroll
         for (int t = BW; t >= 1; --t) v -= F[i * bp + t] * yw[t - 1];
 #pragma unroll
         for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
         yw[0] = v;
-        Ac[(size_t)i * n2] = v;
-        Qc[(size_t)i * n2] = (c == i) ? 1.0 : 0.0;
-        Uc[(size_t)i * n2] = (c == n + i) ? 1.0 : 0.0;
+        Ac[(size_t)i * n2] = (CT)v;
+        Qc[(size_t)i * n2] = (CT)((c == i) ? 1.0 : 0.0);
+        Uc[(size_t)i * n2] = (CT)((c == n + i) ? 1.0 : 0.0);
       }
     } else if (colw && k >= 2) {
       // ---------------- sensitivity step k-2 -> k-1 with the factor of T(q_{k-1})
       const double *F = (((k - 1) & 1) ? FT1 : FT0) + BW * bp;
-      sens_step<BW>(F, Mwp, Dwp, n, n2, P.c0, P.c1, P.c2, Qc, Uc, Ac, Yc);
+      sens_step<BW, CT>(F, Mwp, Dwp, n, n2, P.c0, P.c1, P.c2, Qc, Uc, Ac, Yc);
     }
     __syncthreads();
+  }
+  if constexpr (!std::is_same<CT, double>::value) {
+    // reduced-precision column state: Phi = [Q; U] widened to FP64
+    if (colw) {
+      double *Pq = a.Phi + (size_t)w * n2 * n2 + c;
+      for (int i = 0; i < n; ++i) {
+        Pq[(size_t)i * n2] = (double)Qc[(size_t)i * n2];
+        Pq[(size_t)(n + i) * n2] = (double)Uc[(size_t)i * n2];
+      }
+    }
   }
 
   // ============================================================ epilogue
@@ -929,17 +971,40 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   a.ldw = ctx->Wmax;
   a.zT = ctx->zTw;
   a.Phi = Phi;
-  a.PhiA = ctx->PhiA;
-  a.Ysc = ctx->sens_scr;
   a.st = ctx->status_d;
+  const size_t blk = n * 2 * n;  // one [n][2n] block
+  const bool mixed = ctx->prec == FSE_PREC_MIXED_FP32;
+  if (mixed) {
+    // FP32 column state in the FP64 scratch: Q, U in PhiA, A, Y in sens_scr
+    float *qa = reinterpret_cast<float *>(ctx->PhiA), *sa = reinterpret_cast<float *>(ctx->sens_scr);
+    a.colQ = qa;
+    a.colU = qa ? qa + ctx->Wmax * blk : nullptr;
+    a.colA = sa;
+    a.colY = sa ? sa + ctx->Wmax * blk : nullptr;
+    a.colQ_ws = a.colU_ws = a.colA_ws = a.colY_ws = blk;
+  } else {
+    a.colQ = Phi;
+    a.colU = Phi ? Phi + blk : nullptr;
+    a.colQ_ws = a.colU_ws = 2 * blk;
+    a.colA = ctx->PhiA;
+    a.colY = ctx->sens_scr;
+    a.colA_ws = a.colY_ws = blk;
+  }
   const int ncw = Phi ? ctx->fused_ncw : 0;
   const int nblk = Phi ? (int)((2 * n + 64 * ncw - 1) / (64 * ncw)) : 1;
   const size_t lds = fused_lds_bytes<BW>((int)n, ctx->nnz2, ctx->nnz3);
-  FSE_HIP(hipFuncSetAttribute((const void *)k_fused<BW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
   dim3 grid(nblk, P.W);
-  hipLaunchKernelGGL(k_fused<BW>, grid, dim3(64 * (3 + ncw)), lds, ctx->stream, a, ctx->Sp, ctx->Mwp,
-                     ctx->Dwp, ctx->Kp);
+  if (mixed) {
+    FSE_HIP(hipFuncSetAttribute((const void *)k_fused<BW, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL((k_fused<BW, float>), grid, dim3(64 * (3 + ncw)), lds, ctx->stream, a, ctx->Sp,
+                       ctx->Mwp, ctx->Dwp, ctx->Kp);
+  } else {
+    FSE_HIP(hipFuncSetAttribute((const void *)k_fused<BW, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL((k_fused<BW, double>), grid, dim3(64 * (3 + ncw)), lds, ctx->stream, a, ctx->Sp,
+                       ctx->Mwp, ctx->Dwp, ctx->Kp);
+  }
   FSE_HIP(hipGetLastError());
   ctx->last_sens_launches = Phi ? 1 : 0;
   return FSE_OK;

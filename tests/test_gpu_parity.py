@@ -248,3 +248,44 @@ def test_forcing_amplitude_continuation_c1():
     assert all(r[0] < 1e-10 for r in ro)
     Zo, _, _ = osh.solve(wl.system, wl.torus, wl.omega, Z0, tol_R=1e-12, tables=tb)
     assert rel(Z[-1].cpu().numpy(), Zo) < 1e-8
+
+
+def test_mixed_precision_sensitivities():
+    """FP32 column state: states stay FP64-exact, Phi within 1e-4 normwise of the
+    FP64 oracle (tiny and the 147-DOF beam, sampled trajectories)."""
+    m = fse()
+    s, tr, tb, om, Z0 = _tiny_case()
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    ctx = m.fse_init_torus(s, tr, precision=m.FSE_PREC_MIXED_FP32)
+    zT, phi = m.fse_integrate_batch(ctx, om[None], Z0[None], want_phi=True)
+    assert rel(zT[0].cpu().numpy(), ref["zbarT"]) < RTOL
+    e_tiny = rel(phi[0].cpu().numpy(), ref["Phi"])
+    wl = workload("C2")
+    tb2 = osh.TorusTables(wl.torus)
+    Z2 = wl.initial_iterate(tb2.table)
+    ctx2 = m.fse_init_torus(wl.system, wl.torus, precision=m.FSE_PREC_MIXED_FP32)
+    zT2, phi2 = m.fse_integrate_batch(ctx2, wl.omega[None], Z2[None], want_phi=True)
+    samples = [0, 63]
+    ref2 = osh.evaluate(wl.system, wl.torus, wl.omega, Z2, sens=True, tables=tb2, samples=samples)
+    e_c2 = max(rel(phi2[0, s_].cpu().numpy(), ref2["Phi"][s_]) for s_ in samples)
+    log(f"mixed Phi error vs FP64 oracle: tiny {e_tiny:.2e}, 147-DOF beam {e_c2:.2e}")
+    assert e_tiny < 1e-4 and e_c2 < 1e-4
+    for s_ in samples:
+        assert rel(zT2[0][:, s_].cpu().numpy(), ref2["zbarT"][:, s_]) < RTOL
+
+
+def test_mixed_precision_newton_reaches_fp64_torus():
+    """Newton with the FP32-sensitivity Jacobian still converges on the FP64 residual to
+    the oracle's torus (C1, ||R|| < 1e-12)."""
+    m = fse()
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    ctx = m.fse_init_torus(wl.system, wl.torus, precision=m.FSE_PREC_MIXED_FP32)
+    import torch
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    it, rn = m.fse_newton_solve(ctx, wl.omega, Zg, tol=1e-12, maxit=20)
+    log(f"mixed Newton: {it} iterations, |R| {rn:.2e}")
+    assert rn < 1e-12
+    Zo, _, _ = osh.solve(wl.system, wl.torus, wl.omega, Z0, tol_R=1e-12, tables=tb)
+    assert rel(Zg.cpu().numpy(), Zo) < 1e-8
