@@ -126,22 +126,29 @@ fse_status fse_step_stats(const fse_ctx *ctx, int32_t *max_iters, int64_t *total
 /* Steps 2-5 of Sec. 3.3: residual R = (I (x) R(rho)) Z(2 pi) - Z(0) (Eq. 16),
  * [B][2n][U]; rnorm (HOST, may be NULL): ||R||_2 per point.
  * J (may be NULL): [B][2nU][2nU] row-major Jacobian of Eq. (22) (requires the
- * sensitivities).  dRdw (may be NULL): [B][2nU][d] derivatives of Eq. (23)-(24). */
+ * sensitivities).  dRdw (may be NULL, d > e only): [B][2nU][d-e] derivatives of R with
+ * respect to the unknown base frequencies omega_{e+1..d} (Eqs. 23-24; the forcing does not
+ * depend on them, so only the rotation term is present; d alpha_l / d omega_i is read as
+ * 2 pi k_{i,l} / omega_1).  FSE_E_INVAL if dRdw is given with d = e. */
 fse_status fse_shooting_residual_jacobian(fse_ctx *ctx, int32_t B, const double *omega,
                                           const double *Z0, double *R, double *rnorm,
                                           double *J, double *dRdw);
 
-/* One Newton-Raphson update of step 6 of Sec. 3.3 for one point with all base
- * frequencies known (d = e; the frequency conditions of Eq. 17b hold exactly so
- * omega is unchanged): Z0 <- Z0 - J^-1 R, dense LU with partial pivoting in FP64.
- * omega: HOST [d]; Z0: [2n][U] in/out; res_norm (HOST): ||R||_2 before the
- * update. */
-fse_status fse_newton_step(fse_ctx *ctx, const double *omega, double *Z0, double *res_norm);
+/* One Newton-Raphson update of step 6 of Sec. 3.3 for one point, dense LU with partial
+ * pivoting in FP64.  d = e: every base frequency is a forcing frequency (the frequency
+ * conditions of Eq. 17b hold exactly) and Z0 <- Z0 - J^-1 R.  d > e: the unknown base
+ * frequencies omega_{e+1..d} join the unknowns and the system is bordered by dR/d omega_u
+ * and the phase rows [(I (x) nabla_i) Z0]^T dZ = 0 of Eq. (18) (Sec. 3.2).
+ * omega: HOST [d], in/out (entries e+1..d updated when d > e); Z0: [2n][U] in/out;
+ * res_norm (HOST): ||R||_2 before the update. */
+fse_status fse_newton_step(fse_ctx *ctx, double *omega, double *Z0, double *res_norm);
 
-/* Newton iterations until ||R||_2 < tol (App. C stopping rule) or maxit.
+/* Newton iterations of fse_newton_step until ||R||_2 < tol (App. C stopping rule) or
+ * maxit, with backtracking on ||R||_2 (a step is accepted once the residual decreases).
+ * omega: HOST [d], in/out as in fse_newton_step; Z0 in/out.
  * iters / res_norm (HOST): iterations used and the final ||R||_2.
- * Returns FSE_E_NOCONV if the tolerance was not reached. */
-fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, double tol,
+ * Returns FSE_E_NOCONV if the tolerance was not reached or no step reduced ||R||. */
+fse_status fse_newton_solve(fse_ctx *ctx, double *omega, double *Z0, double tol,
                             int32_t maxit, int32_t *iters, double *res_norm);
 
 /* Forcing amplitudes: the load vectors of Eq. (25) become amp_i F_i, with the F given
@@ -165,7 +172,8 @@ fse_status fse_secant_predict(fse_ctx *ctx, int32_t np, const double *p_prev, co
  * Each point is solved by fse_newton_solve(tol, maxit).  Z_out: [P][2n][U] solutions;
  * iters, rnorm: HOST [P] Newton iterations and final ||R||_2.  On failure at point j the
  * status of that point is returned with iters[j] = -1 and later points are not touched.
- * The forcing amplitudes stay at those of the last point attempted. */
+ * The forcing amplitudes stay at those of the last point attempted.  Needs d = e
+ * (FSE_E_UNSUPPORTED otherwise). */
 fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const double *Z_init,
                             double tol, int32_t maxit, double *Z_out, int32_t *iters,
                             double *rnorm);

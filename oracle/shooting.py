@@ -102,8 +102,8 @@ def jacobian_kron(res):
     return left @ big @ right - np.eye(n2 * tb.U)
 
 
-def residual_domega(res, omega, e):
-    """dR/d omega_i of Eq. (23), i = 1..d, as a (2n U~) x d matrix.
+def residual_domega(res, omega, e, first=1):
+    """dR/d omega_i of Eq. (23), i = first..d, as a (2n U~) x (d - first + 1) matrix.
 
     For i <= e the trajectory term needs res['dzbar_domega'] (integrated with
     omega_sens=True); for i > e only the rotation term is present.
@@ -112,15 +112,15 @@ def residual_domega(res, omega, e):
     omega = np.asarray(omega, dtype=float)
     d = len(omega)
     n2 = res["Z2pi"].shape[0]
-    out = np.zeros((n2 * tb.U, d))
+    out = np.zeros((n2 * tb.U, d - first + 1))
     A = res["Rrot"] @ tb.Gi
-    for i in range(1, d + 1):
+    for i in range(first, d + 1):
         dR = tor.rotation_domega(tb.table, omega, i)
         col = res["Z2pi"] @ dR.T
         if i <= e:
             dz = res["dzbar_domega"][:, :, i - 1].T      # [2n][S~]
             col = col + dz @ A.T
-        out[:, i - 1] = col.ravel()
+        out[:, i - first] = col.ravel()
     return out
 
 
@@ -150,7 +150,7 @@ def newton_step(sysm, torus, omega, Z0, tables=None, tol=1e-12):
     if d == e:
         dZ = np.linalg.solve(J, -R)
         return Z0 + dZ.reshape(Z0.shape), np.array(omega, float), float(np.linalg.norm(R))
-    dRw = residual_domega(res, omega, e)[:, e:]
+    dRw = residual_domega(res, omega, e, first=e + 1)
     P = phase_rows(tb, Z0, e, d)
     nu = d - e
     big = np.block([[J, dRw], [P, np.zeros((nu, nu))]])

@@ -16,7 +16,8 @@ from . import _lib
 __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
            "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
-           "fse_secant_predict", "fse_continuation", "FSE_PREC_FP64", "FSE_PREC_MIXED_FP32"]
+           "fse_secant_predict", "fse_continuation", "fse_residual_domega", "FSE_PREC_FP64",
+           "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
 FSE_PREC_MIXED_FP32 = 1
@@ -175,24 +176,55 @@ def fse_shooting_residual_jacobian(ctx: Context, omega, Z0, want_J=False):
     return R, rn, J
 
 
+def _omega_inout(omega, d):
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(d)).copy()
+    return om
+
+
+def _omega_back(omega, om):
+    if isinstance(omega, np.ndarray) and omega.dtype == np.float64 and omega.size == om.size:
+        omega.reshape(-1)[:] = om
+
+
 def fse_newton_step(ctx: Context, omega, Z0):
-    """Z0 (torch cuda tensor [2n][U], updated in place) -> ||R||_2 before the update."""
+    """Z0 (torch cuda tensor [2n][U], updated in place) -> ||R||_2 before the update.
+    For d > e the unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     ctx.bind_stream()
-    om = _omega(omega, 1, ctx.d)
+    om = _omega_inout(omega, ctx.d)
     rn = C.c_double()
     ctx.check(ctx.lib.fse_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
                                       C.byref(rn)))
+    _omega_back(omega, om)
     return rn.value
 
 
 def fse_newton_solve(ctx: Context, omega, Z0, tol=1e-8, maxit=20):
-    """Z0 (torch cuda tensor, in place) -> (iterations, final ||R||_2)."""
+    """Z0 (torch cuda tensor, in place) -> (iterations, final ||R||_2).  For d > e the
+    unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     ctx.bind_stream()
-    om = _omega(omega, 1, ctx.d)
+    om = _omega_inout(omega, ctx.d)
     it, rn = C.c_int32(), C.c_double()
-    ctx.check(ctx.lib.fse_newton_solve(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
-                                       tol, maxit, C.byref(it), C.byref(rn)))
+    st = ctx.lib.fse_newton_solve(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
+                                  tol, maxit, C.byref(it), C.byref(rn))
+    _omega_back(omega, om)
+    ctx.check(st)
     return it.value, rn.value
+
+
+def fse_residual_domega(ctx: Context, omega, Z0):
+    """-> (R [B][2n][U], dR/d omega_u [B][2nU][d-e]) for the unknown base frequencies."""
+    torch = _torch()
+    ctx.bind_stream()
+    B = int(np.asarray(omega).reshape(-1, ctx.d).shape[0])
+    om = _omega(omega, B, ctx.d)
+    z0 = _dev(Z0, (B, 2 * ctx.n, ctx.U))
+    R = torch.empty_like(z0)
+    nu = ctx.d - ctx.e
+    dR = torch.empty((B, 2 * ctx.n * ctx.U, max(nu, 1)), dtype=torch.float64, device="cuda")
+    ctx.check(ctx.lib.fse_shooting_residual_jacobian(
+        ctx.h, B, _p(om, C.c_double), C.c_void_p(z0.data_ptr()), C.c_void_p(R.data_ptr()), None,
+        None, C.c_void_p(dR.data_ptr())))
+    return R, dR
 
 
 def fse_lyapunov(ctx: Context, omega, Z0, N_Ly=1000, Q0=None):

@@ -127,10 +127,6 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     ctx->err = "unknown precision";
     return FSE_E_INVAL;
   }
-  if (desc->e < desc->d) {
-    ctx->err = "unknown base frequencies (d > e) are not implemented";
-    return FSE_E_UNSUPPORTED;
-  }
   ctx->n = n;
   ctx->e = sys->e;
   ctx->d = desc->d;
@@ -390,7 +386,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)
@@ -559,9 +555,10 @@ fse_status fse_shooting_residual_jacobian(fse_ctx *ctx, int32_t B, const double 
     ctx->err = "R must not be null";
     return FSE_E_INVAL;
   }
-  if (dRdw) {
-    ctx->err = "dR/domega is not implemented (pass NULL)";
-    return FSE_E_UNSUPPORTED;
+  const int nu = ctx->d - ctx->e;
+  if (dRdw && nu == 0) {
+    ctx->err = "dR/domega is defined for the unknown base frequencies only (d > e)";
+    return FSE_E_INVAL;
   }
   double *phi = nullptr;
   if (J) {
@@ -571,76 +568,128 @@ fse_status fse_shooting_residual_jacobian(fse_ctx *ctx, int32_t B, const double 
   FSE_TRY(integrate_impl(ctx, B, omega, Z0, nullptr, phi));
   FSE_TRY(launch_dft_residual(ctx, B, Z0, R));
   if (rnorm) FSE_TRY(launch_norms(ctx, B, R, rnorm));
-  if (J) FSE_TRY(launch_jacobian(ctx, B, phi, J));
-  FSE_HIP(hipStreamSynchronize(ctx->stream));
-  return FSE_OK;
-}
-
-fse_status fse_newton_step(fse_ctx *ctx, const double *omega, double *Z0, double *res_norm) {
-  if (!ctx || !Z0) return FSE_E_INVAL;
   const size_t N = (size_t)2 * ctx->n * ctx->U;
-  if (!ctx->Jw) {
-    FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * N * N));
-    ctx->Jw_elems = N * N;
+  if (J) FSE_TRY(launch_jacobian(ctx, B, phi, J, N));
+  if (dRdw) {
+    for (int b = 0; b < B; ++b) {
+      FSE_TRY(launch_dRdw(ctx, dRdw + (size_t)b * N * nu, R + (size_t)b * N, Z0 + (size_t)b * N,
+                          omega[(size_t)b * ctx->d]));
+    }
   }
-  double rn = 0.0;
-  FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &rn, ctx->Jw, nullptr));
-  if (res_norm) *res_norm = rn;
-  // J dZ = -R  ->  solve J x = R in place, then Z0 -= x
-  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, (int)N, ctx->work_R));
-  FSE_TRY(launch_axpy(ctx, (int)N, -1.0, ctx->work_R, Z0));
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
 
-fse_status fse_newton_solve(fse_ctx *ctx, const double *omega, double *Z0, double tol, int32_t maxit,
-                            int32_t *iters, double *res_norm) {
-  if (!ctx || !Z0) return FSE_E_INVAL;
-  const int N = 2 * ctx->n * ctx->U;
-  if (!ctx->Jw) {
-    FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * (size_t)N * N));
-    ctx->Jw_elems = (size_t)N * N;
+namespace {
+
+// Residual, Newton matrix and right-hand side at (omega, Z0) for one point.  d = e: the
+// Jacobian of Eq. (22).  d > e: bordered by dR/d omega_u and the phase rows of Eq. (18),
+// Nb = N + d - e, row-major in Jb; rhs = [R; 0].
+fse_status newton_system(fse_ctx *ctx, const double *omega, const double *Z0, double *Jb, double *rhs,
+                         double *rn) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  FSE_TRY(ensure_phi(ctx));
+  FSE_TRY(integrate_impl(ctx, 1, omega, Z0, nullptr, ctx->PhiQU));
+  FSE_TRY(launch_dft_residual(ctx, 1, Z0, rhs));
+  FSE_TRY(launch_norms(ctx, 1, rhs, rn));
+  FSE_TRY(launch_jacobian(ctx, 1, ctx->PhiQU, Jb, (size_t)N + nu));
+  if (nu > 0) {
+    FSE_TRY(launch_border(ctx, Jb, (size_t)N + nu, rhs, Z0, omega[0]));
+    FSE_HIP(hipMemsetAsync(rhs + N, 0, sizeof(double) * nu, ctx->stream));
   }
-  // R and J at Z0; every accepted trial point below is evaluated with its Jacobian, so the
-  // next iteration starts from a valid (R, J) pair without integrating again
+  return FSE_OK;
+}
+
+fse_status ensure_newton_buffers(fse_ctx *ctx) {
+  const size_t N = (size_t)2 * ctx->n * ctx->U, Nb = N + (ctx->d - ctx->e);
+  if (ctx->Jw_elems < Nb * Nb) {
+    if (ctx->Jw) (void)hipFree(ctx->Jw);
+    ctx->Jw = nullptr;
+    ctx->Jw_elems = 0;
+    FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * Nb * Nb));
+    ctx->Jw_elems = Nb * Nb;
+  }
+  if (!ctx->work_b) FSE_TRY(alloc(ctx, (void **)&ctx->work_b, sizeof(double) * 2 * Nb));
+  return FSE_OK;
+}
+
+}  // namespace
+
+fse_status fse_newton_step(fse_ctx *ctx, double *omega, double *Z0, double *res_norm) {
+  if (!ctx || !Z0 || !omega) return FSE_E_INVAL;
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e, Nb = N + nu;
+  FSE_TRY(ensure_newton_buffers(ctx));
+  double rn = 0.0;
+  double *rhs = ctx->work_b;
+  FSE_TRY(newton_system(ctx, omega, Z0, ctx->Jw, rhs, &rn));
+  if (res_norm) *res_norm = rn;
+  // [J dRu; P 0] x = [R; 0], then Z0 -= x_Z, omega_u -= x_omega
+  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, Nb, rhs));
+  FSE_TRY(launch_axpy(ctx, N, -1.0, rhs, Z0));
+  if (nu > 0) {
+    std::vector<double> xw(nu);
+    FSE_HIP(hipMemcpyAsync(xw.data(), rhs + N, sizeof(double) * nu, hipMemcpyDeviceToHost, ctx->stream));
+    FSE_HIP(hipStreamSynchronize(ctx->stream));
+    for (int u = 0; u < nu; ++u) omega[ctx->e + u] -= xw[u];
+  }
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status fse_newton_solve(fse_ctx *ctx, double *omega, double *Z0, double tol, int32_t maxit,
+                            int32_t *iters, double *res_norm) {
+  if (!ctx || !Z0 || !omega) return FSE_E_INVAL;
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e, Nb = N + nu, d = ctx->d;
+  FSE_TRY(ensure_newton_buffers(ctx));
+  double *rhs = ctx->work_b, *rtrial = ctx->work_b + Nb;
+  // residual and Newton matrix at Z0; every accepted trial point below is evaluated with its
+  // matrix, so the next iteration starts from a valid pair without integrating again
   double rn = INFINITY;
-  FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &rn, ctx->Jw, nullptr));
+  FSE_TRY(newton_system(ctx, omega, Z0, ctx->Jw, rhs, &rn));
   bool have_J = true;
+  std::vector<double> om(omega, omega + d), omt(d), xw(nu);
   int it = 0;
   for (; it < maxit && !(rn < tol); ++it) {
     if (!have_J) {
       double r0 = 0.0;
-      FSE_TRY(fse_shooting_residual_jacobian(ctx, 1, omega, Z0, ctx->work_R, &r0, ctx->Jw, nullptr));
+      FSE_TRY(newton_system(ctx, om.data(), Z0, ctx->Jw, rhs, &r0));
     }
-    // work_R <- J^-1 R (the Newton direction is -work_R)
-    FSE_TRY(dense_lu_solve(ctx, ctx->Jw, N, ctx->work_R));
+    // rhs <- (Newton matrix)^-1 [R; 0]; the Newton direction is its negative
+    FSE_TRY(dense_lu_solve(ctx, ctx->Jw, Nb, rhs));
     have_J = false;
-    // backtracking on ||R||: accept Z - lambda J^-1 R once the residual decreases
+    if (nu > 0) {
+      FSE_HIP(hipMemcpyAsync(xw.data(), rhs + N, sizeof(double) * nu, hipMemcpyDeviceToHost, ctx->stream));
+      FSE_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    // backtracking on ||R||: accept (Z, omega_u) - lambda x once the residual decreases
     double lam = 1.0;
     bool accepted = false;
     for (int ls = 0; ls < 8 && !accepted; ++ls, lam *= 0.5) {
-      FSE_TRY(launch_lincomb(ctx, N, Z0, -lam, ctx->work_R, ctx->Zwork));
+      FSE_TRY(launch_lincomb(ctx, N, Z0, -lam, rhs, ctx->Zwork));
+      omt = om;
+      for (int u = 0; u < nu; ++u) omt[ctx->e + u] -= lam * xw[u];
       double rt = INFINITY;
-      const fse_status st = fse_shooting_residual_jacobian(ctx, 1, omega, ctx->Zwork, ctx->Zwork + N, &rt,
-                                                           ctx->Jw, nullptr);
+      const fse_status st = newton_system(ctx, omt.data(), ctx->Zwork, ctx->Jw, rtrial, &rt);
       if (st != FSE_OK && st != FSE_E_NOCONV && st != FSE_E_NAN && st != FSE_E_SINGULAR) return st;
       if (st == FSE_OK && rt < (1.0 - 1e-4 * lam) * rn) {
         FSE_HIP(hipMemcpyAsync(Z0, ctx->Zwork, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-        FSE_HIP(hipMemcpyAsync(ctx->work_R, ctx->Zwork + N, sizeof(double) * N, hipMemcpyDeviceToDevice,
-                               ctx->stream));
+        FSE_HIP(hipMemcpyAsync(rhs, rtrial, sizeof(double) * Nb, hipMemcpyDeviceToDevice, ctx->stream));
         FSE_HIP(hipStreamSynchronize(ctx->stream));
+        om = omt;
         rn = rt;
         accepted = true;
         have_J = true;
       }
     }
     if (!accepted) {
+      for (int i = 0; i < d; ++i) omega[i] = om[i];
       if (iters) *iters = it;
       if (res_norm) *res_norm = rn;
       ctx->err = "Newton line search failed to reduce the residual";
       return FSE_E_NOCONV;
     }
   }
+  for (int i = 0; i < d; ++i) omega[i] = om[i];
   if (iters) *iters = it;
   if (res_norm) *res_norm = rn;
   if (!(rn < tol)) {
@@ -691,6 +740,10 @@ fse_status fse_secant_predict(fse_ctx *ctx, int32_t np, const double *p_prev, co
 fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const double *Z_init,
                             double tol, int32_t maxit, double *Z_out, int32_t *iters, double *rnorm) {
   if (!ctx || P < 1 || !params || !Z_init || !Z_out || !iters || !rnorm) return FSE_E_INVAL;
+  if (ctx->d != ctx->e) {
+    ctx->err = "natural-parameter continuation needs every base frequency known (d = e)";
+    return FSE_E_UNSUPPORTED;
+  }
   const int np = ctx->d + ctx->e;
   const size_t N = (size_t)2 * ctx->n * ctx->U;
   for (int j = 0; j < P; ++j) {
@@ -706,7 +759,8 @@ fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const
     }
     int32_t it = 0;
     double rn = 0.0;
-    const fse_status st = fse_newton_solve(ctx, pj, Zj, tol, maxit, &it, &rn);
+    std::vector<double> om(pj, pj + ctx->d);
+    const fse_status st = fse_newton_solve(ctx, om.data(), Zj, tol, maxit, &it, &rn);
     iters[j] = st == FSE_OK ? it : -1;
     rnorm[j] = rn;
     if (st != FSE_OK) return st;

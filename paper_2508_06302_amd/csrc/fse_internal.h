@@ -93,6 +93,7 @@ struct fse_ctx {
   DevStatus *status_d = nullptr;
   double *rot_d = nullptr;          // [Bmax][L] rotation angles alpha_l
   double *work_R = nullptr;         // [Bmax][2n][U]
+  double *work_b = nullptr;         // bordered right-hand side [2nU + d - e]
   double *Zwork = nullptr;          // [Bmax][2n][U]
   double *Jw = nullptr;             // dense Jacobian / LU workspace [2nU][2nU]
   std::vector<double> F_host;   // unit-amplitude load vectors [e][n]
@@ -132,7 +133,10 @@ fse_status launch_idft(fse_ctx *ctx, int B, const double *Z0);
 fse_status launch_state(fse_ctx *ctx, int B);
 fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU);
 fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R);
-fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J);
+fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J, size_t ldJ);
+fse_status launch_dRdw(fse_ctx *ctx, double *out, const double *R, const double *Z0, double omega1);
+fse_status launch_border(fse_ctx *ctx, double *Jb, size_t ldJ, const double *R, const double *Z0,
+                         double omega1);
 fse_status launch_dRdw(fse_ctx *ctx, int B, const double *Z0, double *dRdw);
 fse_status launch_norms(fse_ctx *ctx, int B, const double *R, double *out_host);
 // Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16

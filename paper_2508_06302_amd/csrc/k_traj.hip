@@ -544,7 +544,7 @@ __global__ void k_jac_P(const double *__restrict__ Gi, const double *__restrict_
 // 64 (ij) x 64 (lm) tiles, 4 x 4 outputs per thread.
 __global__ __launch_bounds__(256) void k_jac_gemm(const double *__restrict__ Phi,
                                                   const double *__restrict__ Pm, int n2, int U,
-                                                  int St, double *__restrict__ J) {
+                                                  int St, double *__restrict__ J, size_t ldJ) {
   __shared__ double As[16][64 + 1];
   __shared__ double Bs[16][64 + 1];
   const size_t NIJ = (size_t)n2 * n2;
@@ -577,7 +577,6 @@ __global__ __launch_bounds__(256) void k_jac_gemm(const double *__restrict__ Phi
     }
     __syncthreads();
   }
-  const size_t N = (size_t)n2 * U;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const size_t ij = ij0 + ty * 4 + a;
@@ -589,7 +588,7 @@ __global__ __launch_bounds__(256) void k_jac_gemm(const double *__restrict__ Phi
       if (lm >= NLM) continue;
       const int l = lm / U, m = lm % U;
       const size_t row = (size_t)i * U + l, col = (size_t)j * U + m;
-      J[row * N + col] = acc[a][c] - ((row == col) ? 1.0 : 0.0);
+      J[row * ldJ + col] = acc[a][c] - ((row == col) ? 1.0 : 0.0);
     }
   }
 }
@@ -720,7 +719,73 @@ fse_status launch_norms(fse_ctx *ctx, int B, const double *R, double *out_host) 
   return FSE_OK;
 }
 
-fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J) {
+// Border of the Newton matrix for the unknown base frequencies omega_f, f = e..d-1
+// (0-based): column N + u holds dR/d omega_f (Eqs. 23-24, rotation term only, since the
+// forcing does not depend on a response frequency), computed from (R + Z0) = R(rho) Z(2 pi);
+// row N + u holds the phase row [(I (x) nabla_f) Z0]^T of Eq. (18); the corner is zero.
+__global__ void k_border(double *__restrict__ Jb, size_t ldJ, int N, int nu, const double *__restrict__ R,
+                         const double *__restrict__ Z0, const int32_t *__restrict__ ktable, int L, int dm1,
+                         int e, double two_pi_over_w1, int U) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nu) return;
+  const int u = idx / N, r = idx - u * N;
+  const int a = r % U, base = r - a;
+  const int fcol = e + u - 1;  // harmonic-table column of frequency e + u (0-based)
+  double dr = 0.0, pr = 0.0;
+  if (a > 0) {
+    const int l = (a - 1) / 2;
+    const double k = (double)ktable[(size_t)l * dm1 + fcol];
+    if (a & 1) {  // cos coefficient 2l+1
+      dr = -two_pi_over_w1 * k * (R[base + a + 1] + Z0[base + a + 1]);
+      pr = k * Z0[base + a + 1];
+    } else {      // sin coefficient 2l+2
+      dr = two_pi_over_w1 * k * (R[base + a - 1] + Z0[base + a - 1]);
+      pr = -k * Z0[base + a - 1];
+    }
+  }
+  Jb[(size_t)r * ldJ + N + u] = dr;
+  Jb[(size_t)(N + u) * ldJ + r] = pr;
+  if (r < nu) Jb[(size_t)(N + u) * ldJ + N + r] = 0.0;
+}
+
+fse_status launch_border(fse_ctx *ctx, double *Jb, size_t ldJ, const double *R, const double *Z0,
+                         double omega1) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  if (nu <= 0) return FSE_OK;
+  hipLaunchKernelGGL(k_border, dim3((N * nu + 255) / 256), dim3(256), 0, ctx->stream, Jb, ldJ, N, nu, R, Z0,
+                     ctx->ktable_d, ctx->L, ctx->d - 1, ctx->e, 2.0 * M_PI / omega1, ctx->U);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+// dR/d omega_f for the unknown base frequencies alone: out [N][nu] (same terms as k_border).
+__global__ void k_dRdw(double *__restrict__ out, int N, int nu, const double *__restrict__ R,
+                       const double *__restrict__ Z0, const int32_t *__restrict__ ktable, int dm1, int e,
+                       double two_pi_over_w1, int U) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nu) return;
+  const int u = idx / N, r = idx - u * N;
+  const int a = r % U, base = r - a;
+  double dr = 0.0;
+  if (a > 0) {
+    const int l = (a - 1) / 2;
+    const double k = (double)ktable[(size_t)l * dm1 + e + u - 1];
+    dr = (a & 1) ? -two_pi_over_w1 * k * (R[base + a + 1] + Z0[base + a + 1])
+                 : two_pi_over_w1 * k * (R[base + a - 1] + Z0[base + a - 1]);
+  }
+  out[(size_t)r * nu + u] = dr;
+}
+
+fse_status launch_dRdw(fse_ctx *ctx, double *out, const double *R, const double *Z0, double omega1) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  if (nu <= 0) return FSE_OK;
+  hipLaunchKernelGGL(k_dRdw, dim3((N * nu + 255) / 256), dim3(256), 0, ctx->stream, out, N, nu, R, Z0,
+                     ctx->ktable_d, ctx->d - 1, ctx->e, 2.0 * M_PI / omega1, ctx->U);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J, size_t ldJ) {
   const int U = ctx->U, St = ctx->St, n2 = 2 * ctx->n;
   const size_t Pn = (size_t)St * U * U;
   if (!ctx->jacP && hipMalloc((void **)&ctx->jacP, sizeof(double) * Pn) != hipSuccess) {
@@ -735,7 +800,7 @@ fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J) 
     const size_t NIJ = (size_t)n2 * n2;
     dim3 grid((unsigned)((NIJ + 63) / 64), (unsigned)((U * U + 63) / 64));
     hipLaunchKernelGGL(k_jac_gemm, grid, dim3(256), 0, ctx->stream,
-                       PhiQU + (size_t)b * St * NIJ, Pm, n2, U, St, J + (size_t)b * N * N);
+                       PhiQU + (size_t)b * St * NIJ, Pm, n2, U, St, J + (size_t)b * N * ldJ, ldJ);
   }
   FSE_HIP(hipGetLastError());
   return FSE_OK;

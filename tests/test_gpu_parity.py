@@ -289,3 +289,32 @@ def test_mixed_precision_newton_reaches_fp64_torus():
     assert rn < 1e-12
     Zo, _, _ = osh.solve(wl.system, wl.torus, wl.omega, Z0, tol_R=1e-12, tables=tb)
     assert rel(Zg.cpu().numpy(), Zo) < 1e-8
+
+
+@pytest.mark.parametrize("d,e", [(2, 1), (3, 2)])
+def test_unknown_frequency_bordered_newton_step(d, e):
+    """d > e: dR/d omega_u (rotation term, Eq. 24 reading) and one bordered Newton step with
+    the phase rows of Eq. (18), against the oracle from the same (Z0, omega)."""
+    s = tiny_system(n=3, seed=6, cubic=1.0, quad=0.3, e=e)
+    om = np.array([0.8, 0.8 * GOLDEN, 0.8 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=e, K=[np.arange(1, 4)] * (d - 1), S=[8] * (d - 1), S1=64)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(8).normal(size=(6, tb.U))
+    res = osh.evaluate(s, tr, om, Z0, tables=tb)
+    dref = osh.residual_domega(res, om, e, first=e + 1)
+    ctx = fse().fse_init_torus(s, tr)
+    R, dR = fse().fse_residual_domega(ctx, om[None], Z0[None])
+    assert rel(R[0].cpu().numpy(), res["R"]) < RTOL
+    assert rel(dR[0].cpu().numpy(), dref) < RTOL
+    Zo, omo, rn_o = osh.newton_step(s, tr, om, Z0, tables=tb)
+    import torch
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    omg = om.copy()
+    rn = fse().fse_newton_step(ctx, omg, Zg)
+    assert abs(rn - rn_o) < RTOL * rn_o
+    assert rel(Zg.cpu().numpy() - Z0, Zo - Z0) < 1e-9
+    assert np.abs((omg - om) - (omo - om)).max() < 1e-9 * np.abs(omo - om).max()
+    m = fse()
+    with pytest.raises(m.FseError, match="FSE_E_INVAL"):
+        c2 = m.fse_init_torus(tiny_system(n=3, seed=6, e=d), Torus(d=d, e=d, K=tr.K, S=tr.S, S1=64))
+        m.fse_residual_domega(c2, om[None], Z0[None])

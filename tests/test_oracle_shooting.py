@@ -171,3 +171,33 @@ def test_d1_reduces_to_classical_shooting():
         assert np.allclose(res["R"], res["Z2pi"] - Z)
         defects.append(np.abs(flow(Z[:, 0]) - Z[:, 0]).max())
     assert 3.5 < defects[0] / defects[1] < 4.5
+
+
+@pytest.mark.parametrize("d,e", [(2, 1), (3, 2)])
+def test_bordered_newton_step_solves_its_linearisation(d, e):
+    """d > e (Sec. 3.2): the step (dZ, d omega_u) satisfies the linearised residual
+    R + J dZ + dR/d omega_u d omega_u = 0, with dR/d omega_u checked against central
+    differences, and the phase condition of Eq. (18): [(I (x) nabla_i) Z0]^T dZ = 0."""
+    s = tiny_system(n=2, seed=8, cubic=1.0, quad=0.3, e=e)
+    om = np.array([1.05, 1.05 * GOLDEN, 1.05 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=e, K=[np.arange(1, 3)] * (d - 1), S=[5] * (d - 1), S1=20)
+    tb = shooting.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(2).normal(size=(4, tb.U))
+    Z1, om1, r0 = shooting.newton_step(s, tr, om, Z0, tables=tb)
+    res = shooting.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    J = shooting.jacobian(res)
+    dRw = shooting.residual_domega(res, om, e, first=e + 1)
+    h = 1e-6
+    for u in range(d - e):
+        ei = np.zeros(d)
+        ei[e + u] = h
+        rp = shooting.evaluate(s, tr, om + ei, Z0, tables=tb)["R"].ravel()
+        rm = shooting.evaluate(s, tr, om - ei, Z0, tables=tb)["R"].ravel()
+        assert np.allclose(dRw[:, u], (rp - rm) / (2 * h), rtol=1e-6, atol=1e-7)
+    dZ, dw = (Z1 - Z0).ravel(), (om1 - om)[e:]
+    assert np.allclose(om1[:e], om[:e])
+    lin = res["R"].ravel() + J @ dZ + dRw @ dw
+    assert np.linalg.norm(lin) < 1e-10 * max(1.0, np.linalg.norm(res["R"]))
+    assert abs(r0 - np.linalg.norm(res["R"])) < 1e-14
+    P = shooting.phase_rows(tb, Z0, e, d)
+    assert np.abs(P @ dZ).max() < 1e-12 * np.linalg.norm(dZ) * np.abs(P).max()
