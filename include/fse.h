@@ -178,6 +178,75 @@ fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const
                             double tol, int32_t maxit, double *Z_out, int32_t *iters,
                             double *rnorm);
 
+/* ---------------------------------------------------------------- learned predictor
+ * Initial iterates for new continuation parameters from the converged tori of earlier
+ * points: a POD basis of the converged Z(0) (method of snapshots: Gram matrix in FP64,
+ * cyclic Jacobi eigen-solver) and a multilayer perceptron p -> POD coefficients
+ * (n_in -> hidden -> hidden -> rank, GELU(erf) hidden activations, FP32 weights, mean
+ * squared error, AdamW), trained and evaluated by the library's own kernels.  This is an
+ * addition to the paper's continuation (App. C), which predicts from previous solutions
+ * only; the secant predictor stays the fallback (fse_continuation_learned).
+ *
+ * Parameter layout (FP32, one flat array of fse_learned_num_params values): for each
+ * layer l = 1..3 its weight matrix W_l [out][in] row-major, then its bias [out]. */
+typedef struct fse_learned fse_learned;
+
+/* Creates a predictor for the unknowns of ctx (N = 2 n U per point) with n_in parameters,
+ * `hidden` units per hidden layer and `rank` POD modes; uses ctx's stream.  ctx must
+ * outlive the predictor.  Weights are zero until fse_learned_set_params. */
+fse_status fse_learned_create(fse_ctx *ctx, int32_t n_in, int32_t hidden, int32_t rank,
+                              fse_learned **out);
+int64_t fse_learned_num_params(const fse_learned *m);
+int32_t fse_learned_inputs(const fse_learned *m);   /* n_in, or -1 for NULL */
+/* params: HOST FP32 [fse_learned_num_params]; copies in / out.  set_params also resets
+ * the AdamW moments and step counter. */
+fse_status fse_learned_set_params(fse_learned *m, const float *params);
+fse_status fse_learned_get_params(const fse_learned *m, float *params);
+
+/* POD of m_snap snapshots X [m_snap][N] (device, FP64, one converged Z(0) per row):
+ * mean, then the leading `rank` modes of the centred snapshots.  sigma (HOST, may be NULL):
+ * [min(m_snap, rank)] singular values of the centred snapshot matrix, descending.
+ * 2 <= m_snap <= 128. */
+fse_status fse_learned_fit_pod(fse_learned *m, int32_t m_snap, const double *X, double *sigma);
+/* POD basis out: mean [N] and modes [N][rank] (device FP64, row-major). */
+fse_status fse_learned_get_pod(const fse_learned *m, double *mean, double *modes);
+
+/* Mean squared error and its gradients for a batch, without updating: x [B][n_in] and
+ * t [B][rank] HOST FP32 (already normalised), grads HOST FP32 [num_params], loss HOST.
+ * B <= 256.  Exposed so the hand-written backward pass can be checked. */
+fse_status fse_learned_loss_grad(fse_learned *m, int32_t B, const float *x, const float *t,
+                                 float *loss, float *grads);
+
+/* `steps` full-batch AdamW steps on given normalised data: x [B][n_in], t [B][rank] HOST
+ * FP32, B <= 256; loss_hist (HOST, may be NULL) [steps] loss before each step.  The step
+ * counter and moments continue from earlier calls (fse_learned_set_params resets them). */
+fse_status fse_learned_fit(fse_learned *m, int32_t B, const float *x, const float *t, int32_t steps,
+                           double lr, double wd, double *loss_hist);
+
+/* Trains on m_snap points: params P HOST [m_snap][n_in] (FP64), snapshots X device
+ * [m_snap][N] (the ones given to fse_learned_fit_pod).  Inputs and POD coefficients are
+ * standardised with the training set's mean and deviation; full-batch AdamW (lr,
+ * beta 0.9 / 0.999, eps 1e-8, decoupled weight decay wd) for `epochs` steps.
+ * loss_hist (HOST, may be NULL): [epochs] training loss in normalised units. */
+fse_status fse_learned_train(fse_learned *m, int32_t m_snap, const double *P, const double *X,
+                             int32_t epochs, double lr, double wd, double *loss_hist);
+
+/* Prediction Z = mean + modes (sd_c * mlp((p - mu_p) / sd_p) + mu_c): p HOST [n_in],
+ * Z device [N] (FP64). */
+fse_status fse_learned_predict(fse_learned *m, const double *p, double *Z);
+void fse_learned_destroy(fse_learned *m);
+
+/* fse_continuation with a second predictor: from point first_learned on, the learned
+ * prediction for features[j] (HOST [P][n_in], e.g. (omega_1, omega_2 / omega_1, f)) and the
+ * secant prediction are both evaluated (one residual each) and Newton starts from the one
+ * with the smaller ||R||_2, so the secant predictor is both the fallback and the judge.
+ * used (HOST [P]): 1 where the learned prediction was taken, else 0.  Other arguments as
+ * fse_continuation. */
+fse_status fse_continuation_learned(fse_ctx *ctx, int32_t P, const double *params,
+                                    const double *features, const double *Z_init, double tol,
+                                    int32_t maxit, fse_learned *m, int32_t first_learned,
+                                    double *Z_out, int32_t *iters, double *rnorm, int32_t *used);
+
 /* Lyapunov exponents of App. F from the sensitivities at Z0: Psi_s of Eq. (F3),
  * trigonometric interpolation on the torus basis at phi~ = 2 pi (i-1) rho,
  * N_Ly steps of Gram-Schmidt as Householder QR with positive diagonal.

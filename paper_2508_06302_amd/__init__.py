@@ -16,8 +16,8 @@ from . import _lib
 __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
            "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
-           "fse_secant_predict", "fse_continuation", "fse_residual_domega", "FSE_PREC_FP64",
-           "FSE_PREC_MIXED_FP32"]
+           "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
+           "fse_learned_create", "fse_continuation_learned", "FSE_PREC_FP64", "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
 FSE_PREC_MIXED_FP32 = 1
@@ -287,3 +287,122 @@ def fse_continuation(ctx: Context, params, Z_init, tol=1e-8, maxit=20):
         err.iters, err.rnorm, err.Z = it, rn, Z
         raise err
     return Z, it, rn
+
+
+class Learned:
+    """Owns an fse_learned (POD + MLP predictor) bound to a Context."""
+
+    def __init__(self, ctx: Context, handle, n_in, hidden, rank):
+        self.ctx, self.h = ctx, handle
+        self.n_in, self.hidden, self.rank = n_in, hidden, rank
+        self.num_params = int(ctx.lib.fse_learned_num_params(handle))
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(self.num_params))
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.fse_learned_set_params(self.h, _p(a, C.c_float)))
+
+    def get_params(self):
+        a = np.zeros(self.num_params, np.float32)
+        self.ctx.check(self.ctx.lib.fse_learned_get_params(self.h, _p(a, C.c_float)))
+        return a
+
+    def fit_pod(self, X):
+        """X: [m][2n][U] (or [m][N]) converged Z(0) -> singular values [min(m, rank)]."""
+        ctx = self.ctx
+        ctx.bind_stream()
+        N = 2 * ctx.n * ctx.U
+        Xd = _dev(X, (-1, N))
+        m = Xd.shape[0]
+        sig = np.zeros(min(m, self.rank))
+        ctx.check(ctx.lib.fse_learned_fit_pod(self.h, m, C.c_void_p(Xd.data_ptr()), _p(sig, C.c_double)))
+        return sig
+
+    def get_pod(self):
+        torch = _torch()
+        ctx = self.ctx
+        N = 2 * ctx.n * ctx.U
+        mean = torch.empty(N, dtype=torch.float64, device="cuda")
+        modes = torch.empty((N, self.rank), dtype=torch.float64, device="cuda")
+        ctx.check(ctx.lib.fse_learned_get_pod(self.h, C.c_void_p(mean.data_ptr()), C.c_void_p(modes.data_ptr())))
+        return mean, modes
+
+    def loss_grad(self, x, t):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+        t = np.ascontiguousarray(np.asarray(t, dtype=np.float32))
+        g = np.zeros(self.num_params, np.float32)
+        loss = C.c_float()
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.fse_learned_loss_grad(self.h, x.shape[0], _p(x, C.c_float), _p(t, C.c_float),
+                                                          C.byref(loss), _p(g, C.c_float)))
+        return loss.value, g
+
+    def fit(self, x, t, steps, lr=1e-3, wd=1e-4):
+        """AdamW steps on normalised data (x [B][n_in], t [B][rank]) -> loss history."""
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+        t = np.ascontiguousarray(np.asarray(t, dtype=np.float32))
+        hist = np.zeros(steps)
+        self.ctx.bind_stream()
+        self.ctx.check(self.ctx.lib.fse_learned_fit(self.h, x.shape[0], _p(x, C.c_float), _p(t, C.c_float),
+                                                    int(steps), float(lr), float(wd), _p(hist, C.c_double)))
+        return hist
+
+    def train(self, P, X, epochs=2000, lr=1e-3, wd=1e-4):
+        ctx = self.ctx
+        ctx.bind_stream()
+        N = 2 * ctx.n * ctx.U
+        Pp = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(-1, self.n_in))
+        Xd = _dev(X, (-1, N))
+        hist = np.zeros(epochs)
+        ctx.check(ctx.lib.fse_learned_train(self.h, Pp.shape[0], _p(Pp, C.c_double), C.c_void_p(Xd.data_ptr()),
+                                            int(epochs), float(lr), float(wd), _p(hist, C.c_double)))
+        return hist
+
+    def predict(self, p):
+        torch = _torch()
+        ctx = self.ctx
+        ctx.bind_stream()
+        pp = np.ascontiguousarray(np.asarray(p, dtype=np.float64).reshape(self.n_in))
+        Z = torch.empty((2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+        ctx.check(ctx.lib.fse_learned_predict(self.h, _p(pp, C.c_double), C.c_void_p(Z.data_ptr())))
+        return Z
+
+    def __del__(self):
+        try:
+            if self.h:
+                self.ctx.lib.fse_learned_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def fse_learned_create(ctx: Context, n_in=3, hidden=256, rank=64) -> Learned:
+    h = C.c_void_p()
+    ctx.bind_stream()
+    ctx.check(ctx.lib.fse_learned_create(ctx.h, n_in, hidden, rank, C.byref(h)))
+    return Learned(ctx, h, n_in, hidden, rank)
+
+
+def fse_continuation_learned(ctx: Context, params, features, Z_init, learned: Learned, first_learned,
+                             tol=1e-8, maxit=20):
+    """As fse_continuation, with the learned predictor judged against the secant predictor
+    from point first_learned on -> (Z, iterations, residuals, used_learned)."""
+    torch = _torch()
+    ctx.bind_stream()
+    pr = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, ctx.d + ctx.e))
+    ft = np.ascontiguousarray(np.asarray(features, dtype=np.float64).reshape(pr.shape[0], learned.n_in))
+    P = pr.shape[0]
+    z0 = _dev(Z_init, (2 * ctx.n, ctx.U))
+    Z = torch.zeros((P, 2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+    it = np.zeros(P, np.int32)
+    rn = np.zeros(P)
+    used = np.zeros(P, np.int32)
+    st = ctx.lib.fse_continuation_learned(ctx.h, P, _p(pr, C.c_double), _p(ft, C.c_double), C.c_void_p(z0.data_ptr()),
+                                          float(tol), int(maxit), learned.h, int(first_learned),
+                                          C.c_void_p(Z.data_ptr()), _p(it, C.c_int32), _p(rn, C.c_double),
+                                          _p(used, C.c_int32))
+    if st != 0:
+        err = FseError(st, ctx.lib.fse_last_error(ctx.h).decode())
+        err.iters, err.rnorm, err.Z, err.used = it, rn, Z, used
+        raise err
+    return Z, it, rn, used

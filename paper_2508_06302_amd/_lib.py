@@ -13,7 +13,11 @@ FSE_STATUS = {0: "FSE_OK", 1: "FSE_E_INVAL", 2: "FSE_E_NOMEM", 3: "FSE_E_DEVICE"
 EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
            "fse_newton_solve", "fse_lyapunov", "fse_set_forcing", "fse_secant_predict",
-           "fse_continuation", "fse_last_timing", "fse_last_error", "fse_destroy"]
+           "fse_continuation", "fse_continuation_learned", "fse_learned_create",
+           "fse_learned_num_params", "fse_learned_inputs", "fse_learned_set_params",
+           "fse_learned_get_params", "fse_learned_fit_pod", "fse_learned_get_pod",
+           "fse_learned_loss_grad", "fse_learned_fit", "fse_learned_train", "fse_learned_predict",
+           "fse_learned_destroy", "fse_last_timing", "fse_last_error", "fse_destroy"]
 
 i32p = C.POINTER(C.c_int32)
 f64p = C.POINTER(C.c_double)
@@ -63,13 +67,32 @@ def load(path: str = LIB_PATH):
     lib.fse_set_forcing.argtypes = [vp, f64p]
     lib.fse_secant_predict.argtypes = [vp, C.c_int32, f64p, f64p, f64p, vp, vp, vp]
     lib.fse_continuation.argtypes = [vp, C.c_int32, f64p, vp, C.c_double, C.c_int32, vp, i32p, f64p]
+    f32p = C.POINTER(C.c_float)
+    lib.fse_continuation_learned.argtypes = [vp, C.c_int32, f64p, f64p, vp, C.c_double, C.c_int32, vp,
+                                             C.c_int32, vp, i32p, f64p, i32p]
+    lib.fse_learned_create.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(vp)]
+    lib.fse_learned_num_params.argtypes = [vp]
+    lib.fse_learned_num_params.restype = C.c_int64
+    lib.fse_learned_inputs.argtypes = [vp]
+    lib.fse_learned_inputs.restype = C.c_int32
+    lib.fse_learned_set_params.argtypes = [vp, f32p]
+    lib.fse_learned_get_params.argtypes = [vp, f32p]
+    lib.fse_learned_fit_pod.argtypes = [vp, C.c_int32, vp, f64p]
+    lib.fse_learned_get_pod.argtypes = [vp, vp, vp]
+    lib.fse_learned_loss_grad.argtypes = [vp, C.c_int32, f32p, f32p, f32p, f32p]
+    lib.fse_learned_fit.argtypes = [vp, C.c_int32, f32p, f32p, C.c_int32, C.c_double, C.c_double, f64p]
+    lib.fse_learned_train.argtypes = [vp, C.c_int32, f64p, vp, C.c_int32, C.c_double, C.c_double, f64p]
+    lib.fse_learned_predict.argtypes = [vp, f64p, vp]
+    lib.fse_learned_destroy.argtypes = [vp]
+    lib.fse_learned_destroy.restype = None
     lib.fse_last_timing.argtypes = [vp, f64p, i32p]
     lib.fse_last_error.argtypes = [vp]
     lib.fse_last_error.restype = C.c_char_p
     lib.fse_destroy.argtypes = [vp]
     lib.fse_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("fse_last_error", "fse_destroy"):
+        if name not in ("fse_last_error", "fse_destroy", "fse_learned_destroy", "fse_learned_num_params",
+                        "fse_learned_inputs"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

@@ -768,6 +768,69 @@ fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const
   return FSE_OK;
 }
 
+fse_status fse_continuation_learned(fse_ctx *ctx, int32_t P, const double *params, const double *features,
+                                    const double *Z_init, double tol, int32_t maxit, fse_learned *m,
+                                    int32_t first_learned, double *Z_out, int32_t *iters, double *rnorm,
+                                    int32_t *used) {
+  if (!ctx || P < 1 || !params || !features || !Z_init || !Z_out || !iters || !rnorm || !used || !m)
+    return FSE_E_INVAL;
+  if (ctx->d != ctx->e) {
+    ctx->err = "natural-parameter continuation needs every base frequency known (d = e)";
+    return FSE_E_UNSUPPORTED;
+  }
+  const int np = ctx->d + ctx->e, nf = fse_learned_inputs(m);
+  const size_t N = (size_t)2 * ctx->n * ctx->U;
+  double *Zl = nullptr, *Rl = nullptr;
+  FSE_TRY(alloc(ctx, (void **)&Zl, sizeof(double) * N));
+  if (alloc(ctx, (void **)&Rl, sizeof(double) * N) != FSE_OK) {
+    (void)hipFree(Zl);
+    return FSE_E_NOMEM;
+  }
+  fse_status result = FSE_OK;
+  for (int j = 0; j < P && result == FSE_OK; ++j) {
+    const double *pj = params + (size_t)j * np;
+    used[j] = 0;
+    result = fse_set_forcing(ctx, pj + ctx->d);
+    if (result != FSE_OK) break;
+    double *Zj = Z_out + j * N;
+    hipError_t e = hipSuccess;
+    if (j == 0)
+      e = hipMemcpyAsync(Zj, Z_init, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream);
+    else if (j == 1)
+      e = hipMemcpyAsync(Zj, Z_out, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream);
+    else
+      result = fse_secant_predict(ctx, np, pj - 2 * np, pj - np, pj, Zj - 2 * N, Zj - N, Zj);
+    if (e != hipSuccess) result = FSE_E_DEVICE;
+    if (result != FSE_OK) break;
+    if (j >= first_learned) {
+      // judge: the prediction with the smaller residual starts Newton
+      double rs = INFINITY, rl = INFINITY;
+      const fse_status s1 = fse_shooting_residual_jacobian(ctx, 1, pj, Zj, Rl, &rs, nullptr, nullptr);
+      result = fse_learned_predict(m, features + (size_t)j * nf, Zl);
+      if (result != FSE_OK) break;
+      const fse_status s2 = fse_shooting_residual_jacobian(ctx, 1, pj, Zl, Rl, &rl, nullptr, nullptr);
+      const bool ok1 = s1 == FSE_OK && std::isfinite(rs), ok2 = s2 == FSE_OK && std::isfinite(rl);
+      if (ok2 && (!ok1 || rl < rs)) {
+        if (hipMemcpyAsync(Zj, Zl, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+          result = FSE_E_DEVICE;
+          break;
+        }
+        used[j] = 1;
+      }
+    }
+    int32_t it = 0;
+    double rn = 0.0;
+    std::vector<double> om(pj, pj + ctx->d);
+    const fse_status st = fse_newton_solve(ctx, om.data(), Zj, tol, maxit, &it, &rn);
+    iters[j] = st == FSE_OK ? it : -1;
+    rnorm[j] = rn;
+    result = st;
+  }
+  (void)hipFree(Zl);
+  (void)hipFree(Rl);
+  return result;
+}
+
 fse_status fse_lyapunov(fse_ctx *ctx, const double *omega, const double *Z0, int32_t N_Ly,
                         const double *Q0, double *sigma) {
   if (!ctx || !Z0 || !sigma || N_Ly < 1) return FSE_E_INVAL;
