@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_fused_c2_traffic.json"))
     ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
@@ -102,6 +103,54 @@ def cpu_baseline(wl, Z0, tables, budget_s=20.0):
                       f"full {wl.torus.S1}-step integration with sensitivities, {el:.1f} s"}
 
 
+def run_precision(fse, torch, wl, prec, steps, warmup, solve):
+    """Throughput of the residual + Jacobian step and the continuation solve in one
+    precision mode; returns a dict (kernel times from HIP events on the library stream)."""
+    tr = wl.torus
+    ctx = fse.fse_init_torus(wl.system, tr, precision=prec)
+    U, St, bw, kt = fse.fse_get_layout(ctx)
+    Z0 = wl.initial_iterate(kt)
+    om = wl.omega[None]
+    Zd = torch.tensor(Z0[None], dtype=torch.float64, device="cuda")
+
+    def step():
+        return fse.fse_shooting_residual_jacobian(ctx, om, Zd, want_J=True)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kern_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        tm = fse.fse_last_timing(ctx)          # HIP events around the launch, on its stream
+        kern_ms.append(tm["state_ms"] + tm["sens_ms"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = {"ctx": ctx, "U": U, "St": St, "bw": bw, "Z0": Z0, "ms_per_step": 1e3 * el / steps,
+           "value": St * tr.S1 / (el / steps), "kernel_ms": float(np.mean(kern_ms)),
+           "fused": tm["sens_launches"] == 1 and tm["sens_ms"] < 0.05 * tm["state_ms"]}
+    if solve:
+        # shooting solve: natural-parameter continuation in the forcing amplitude
+        # f1 = f2 = 0.1 ... 0.5 N at the same omega, secant predictor, ||R||_2 < 1e-8 per point
+        amps = [0.1, 0.2, 0.3, 0.4, 0.5]
+        params = np.array([[*wl.omega, a, a] for a in amps])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        try:
+            Zs, its, rns = fse.fse_continuation(ctx, params, Z0 * amps[0], tol=1e-8, maxit=15)
+            ok = True
+        except fse.FseError as ex:
+            Zs, its, rns, ok = ex.Z, ex.iters, ex.rnorm, str(ex)
+        torch.cuda.synchronize()
+        res["solve"] = {"time_s": time.perf_counter() - t1,
+                        "newton_iterations": [int(i) for i in its],
+                        "final_residuals": [float(r) for r in rns], "converged": ok is True}
+        res["Z_solution"] = Zs[-1].clone() if ok is True else None
+        fse.fse_set_forcing(ctx, [1.0] * wl.system.e)
+    return res
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -119,44 +168,21 @@ def main():
     torch.cuda.set_device(0)
     wl = workload("C2")
     tr = wl.torus
-    ctx = fse.fse_init_torus(wl.system, tr)
-    U, St, bw, kt = fse.fse_get_layout(ctx)
-    Z0 = wl.initial_iterate(kt)
-    om = wl.omega[None]
-    Zd = torch.tensor(Z0[None], dtype=torch.float64, device="cuda")
-    N = 2 * wl.system.n * U
-    R = torch.empty_like(Zd)
-    J = torch.empty((1, N, N), dtype=torch.float64, device="cuda")
-
-    def step():
-        return fse.fse_shooting_residual_jacobian(ctx, om, Zd, want_J=True)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kern_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-        tm = fse.fse_last_timing(ctx)          # HIP events around the launch, on its stream
-        kern_ms.append(tm["state_ms"] + tm["sens_ms"])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_per_step = 1e3 * el / args.steps
-    traj_steps = St * tr.S1
-    value = traj_steps / (el / args.steps)
-
+    solve = not args.no_solve
+    plain = run_precision(fse, torch, wl, fse.FSE_PREC_FP64, args.steps, args.warmup, solve)
+    mixed = None if args.no_mixed else run_precision(fse, torch, wl, fse.FSE_PREC_MIXED_FP32, args.steps,
+                                                     args.warmup, solve)
+    U, St, bw, Z0 = plain["U"], plain["St"], plain["bw"], plain["Z0"]
     n = wl.system.n
+    traj_steps = St * tr.S1
     bytes_per_traj_step = 6 * n * (2 * n) * 8          # read + write Q, U, A (FP64)
     alg_bytes = bytes_per_traj_step * traj_steps
-    kern_avg_ms = float(np.mean(kern_ms))
-    achieved = alg_bytes / (kern_avg_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (plain["kernel_ms"] * 1e-3) / 1e9
     traffic = read_traffic(args.traffic)
-    fused = tm["sens_launches"] == 1 and tm["sens_ms"] < 0.05 * tm["state_ms"]
     out = {
         "metric": "trajectory-steps/s and shooting solve time @||R||<1e-8, mixed vs plain FP64",
-        "value": value, "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "value": plain["value"], "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": plain["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "von Karman clamped-clamped beam, 50 elements (147 DOF), d=2, "
                                "64 trajectories, H=15 (U=31), S1=512, full sensitivities, "
@@ -165,30 +191,22 @@ def main():
                    "n": n, "Stilde": St, "U": U, "S1": tr.S1, "half_band": bw},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused (state + sensitivities)" if fused else "k_state + k_sens",
-                     "kernel_ms_per_launch": kern_avg_ms,
+                     "kernel": "k_fused (state + sensitivities)" if plain["fused"] else "k_state + k_sens",
+                     "kernel_ms_per_launch": plain["kernel_ms"],
                      "algorithmic_bytes_per_launch": alg_bytes},
     }
-    if not args.no_solve:
-        # shooting solve: natural-parameter continuation in the forcing amplitude
-        # f1 = f2 = 0.1 ... 0.5 N at the same omega, secant predictor, ||R||_2 < 1e-8 per point
-        amps = [0.1, 0.2, 0.3, 0.4, 0.5]
-        params = np.array([[*wl.omega, a, a] for a in amps])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        try:
-            Zs, its, rns = fse.fse_continuation(ctx, params, Z0 * amps[0], tol=1e-8, maxit=15)
-            ok = True
-        except fse.FseError as ex:
-            its, rns, ok = ex.iters, ex.rnorm, str(ex)
-        torch.cuda.synchronize()
-        out["shooting_solve"] = {"time_s": time.perf_counter() - t1,
-                                 "path": "forcing amplitude 0.1 -> 0.5 N in 5 points from the "
-                                         "linear response at 0.1 N, secant predictor",
-                                 "newton_iterations": [int(i) for i in its],
-                                 "final_residuals": [float(r) for r in rns],
-                                 "converged": ok is True, "precision": "fp64"}
-        fse.fse_set_forcing(ctx, [1.0] * wl.system.e)
+    if mixed is not None:
+        out["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
+                        "kernel_ms_per_launch": mixed["kernel_ms"],
+                        "dtype": "f64 arithmetic, f32 sensitivity storage"}
+    if solve:
+        path = "forcing amplitude 0.1 -> 0.5 N in 5 points from the linear response at 0.1 N, secant predictor"
+        out["shooting_solve"] = {"path": path, "fp64": plain["solve"]}
+        if mixed is not None:
+            out["shooting_solve"]["mixed"] = mixed["solve"]
+            zp, zm = plain.get("Z_solution"), mixed.get("Z_solution")
+            if zp is not None and zm is not None:
+                out["shooting_solve"]["mixed_vs_fp64_torus_rel_diff"] = float((zm - zp).norm() / zp.norm())
     if not args.no_cpu_baseline:
         from oracle import shooting as osh
         tb = osh.TorusTables(tr)
