@@ -318,3 +318,23 @@ def test_unknown_frequency_bordered_newton_step(d, e):
     with pytest.raises(m.FseError, match="FSE_E_INVAL"):
         c2 = m.fse_init_torus(tiny_system(n=3, seed=6, e=d), Torus(d=d, e=d, K=tr.K, S=tr.S, S1=64))
         m.fse_residual_domega(c2, om[None], Z0[None])
+
+
+def test_c4_three_frequency_batched_points_sampled():
+    """Three-frequency beam (147 DOF, d = 3, 32 x 32 = 1024 trajectories, H = 8 x 8,
+    S1 = 512) with two continuation points in one launch: every trajectory on the GPU,
+    sampled trajectories of each point by the oracle."""
+    wl = workload("C4")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    oms = np.stack([wl.omega, wl.omega * 1.0125])
+    Zs = np.stack([Z0, Z0])
+    ctx = fse().fse_init_torus(wl.system, wl.torus, max_batch=2)
+    log("C4 gpu integrate, 2 points x 1024 trajectories with sensitivities")
+    zT, phi = fse().fse_integrate_batch(ctx, oms, Zs, want_phi=True)
+    for b, samples in ((0, [0, 517]), (1, [1023])):
+        log(f"C4 oracle point {b} samples {samples}")
+        ref = osh.evaluate(wl.system, wl.torus, oms[b], Zs[b], sens=True, tables=tb, samples=samples)
+        for s_ in samples:
+            assert rel(zT[b][:, s_].cpu().numpy(), ref["zbarT"][:, s_]) < RTOL, (b, s_)
+            assert rel(phi[b, s_].cpu().numpy(), ref["Phi"][s_]) < 1e-9, (b, s_)
