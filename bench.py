@@ -127,7 +127,9 @@ def run_precision(fse, torch, wl, prec, steps, warmup, solve):
         kern_ms.append(tm["state_ms"] + tm["sens_ms"])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    ncw, tune_ms = fse.fse_get_tuning(ctx)
     res = {"ctx": ctx, "U": U, "St": St, "bw": bw, "Z0": Z0, "ms_per_step": 1e3 * el / steps,
+           "tuning": {"column_waves_per_workgroup": ncw, "tuned_launch_ms": [float(x) for x in tune_ms]},
            "value": St * tr.S1 / (el / steps), "kernel_ms": float(np.mean(kern_ms)),
            "fused": tm["sens_launches"] == 1 and tm["sens_ms"] < 0.05 * tm["state_ms"]}
     if solve:
@@ -194,6 +196,7 @@ def main():
                      "kernel": "k_fused (state + sensitivities)" if plain["fused"] else "k_state + k_sens",
                      "kernel_ms_per_launch": plain["kernel_ms"],
                      "algorithmic_bytes_per_launch": alg_bytes},
+        "autotuner": plain["tuning"],
     }
     if mixed is not None:
         out["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],

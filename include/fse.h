@@ -260,6 +260,13 @@ fse_status fse_lyapunov(fse_ctx *ctx, const double *omega, const double *Z0, int
  * propagation, [3] AFT; launches_out: launches of the sensitivity kernel. */
 fse_status fse_last_timing(const fse_ctx *ctx, double *ms4, int32_t *launches_out);
 
+/* Autotuner of the fused trajectory kernel: the first launch with sensitivities times each
+ * candidate number of sensitivity-column waves per work-group (1 and 2) and keeps the
+ * fastest.  ncw (HOST): the count in use; ms2 (HOST [2], may be NULL): the timed launches
+ * (0 until tuned).  Setting FSE_FUSED_NCW in the environment before fse_init_torus fixes
+ * the count and skips the tuning. */
+fse_status fse_get_tuning(const fse_ctx *ctx, int32_t *ncw, float *ms2);
+
 const char *fse_last_error(const fse_ctx *ctx);
 void fse_destroy(fse_ctx *ctx);
 

@@ -17,7 +17,8 @@ __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integ
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
            "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
-           "fse_learned_create", "fse_continuation_learned", "FSE_PREC_FP64", "FSE_PREC_MIXED_FP32"]
+           "fse_learned_create", "fse_continuation_learned", "fse_get_tuning", "FSE_PREC_FP64",
+           "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
 FSE_PREC_MIXED_FP32 = 1
@@ -245,6 +246,14 @@ def fse_last_timing(ctx: Context):
     ctx.check(ctx.lib.fse_last_timing(ctx.h, _p(ms, C.c_double), C.byref(nl)))
     return {"total_ms": ms[0], "state_ms": ms[1], "sens_ms": ms[2], "idft_ms": ms[3],
             "sens_launches": nl.value}
+
+
+def fse_get_tuning(ctx: Context):
+    """-> (column waves per fused work-group in use, timed launches [ms] for 1 and 2 waves)."""
+    ncw = C.c_int32()
+    ms = np.zeros(2, np.float32)
+    ctx.check(ctx.lib.fse_get_tuning(ctx.h, C.byref(ncw), _p(ms, C.c_float)))
+    return ncw.value, ms
 
 
 def fse_set_forcing(ctx: Context, amp):

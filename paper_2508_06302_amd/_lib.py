@@ -17,7 +17,7 @@ EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_
            "fse_learned_num_params", "fse_learned_inputs", "fse_learned_set_params",
            "fse_learned_get_params", "fse_learned_fit_pod", "fse_learned_get_pod",
            "fse_learned_loss_grad", "fse_learned_fit", "fse_learned_train", "fse_learned_predict",
-           "fse_learned_destroy", "fse_last_timing", "fse_last_error", "fse_destroy"]
+           "fse_learned_destroy", "fse_get_tuning", "fse_last_timing", "fse_last_error", "fse_destroy"]
 
 i32p = C.POINTER(C.c_int32)
 f64p = C.POINTER(C.c_double)
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.fse_learned_predict.argtypes = [vp, f64p, vp]
     lib.fse_learned_destroy.argtypes = [vp]
     lib.fse_learned_destroy.restype = None
+    lib.fse_get_tuning.argtypes = [vp, i32p, f32p]
     lib.fse_last_timing.argtypes = [vp, f64p, i32p]
     lib.fse_last_error.argtypes = [vp]
     lib.fse_last_error.restype = C.c_char_p

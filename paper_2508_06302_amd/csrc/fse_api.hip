@@ -137,7 +137,10 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   ctx->maxit = desc->step_maxit > 0 ? desc->step_maxit : 30;
   // FSE_KERNELS=fused|generic selects the trajectory kernels (tests cover both paths)
   if (const char *kv = std::getenv("FSE_KERNELS")) ctx->use_fused = std::strcmp(kv, "generic") != 0;
-  if (const char *nc = std::getenv("FSE_FUSED_NCW")) ctx->fused_ncw = std::max(1, std::atoi(nc));
+  if (const char *nc = std::getenv("FSE_FUSED_NCW")) {
+    ctx->fused_ncw = std::max(1, std::atoi(nc));
+    ctx->ncw_autotune = false;
+  }
   FSE_HIP(hipGetDevice(&ctx->device));
 
   // ---- torus tables (App. B, App. D)
@@ -844,6 +847,16 @@ fse_status fse_last_timing(const fse_ctx *ctx, double *ms4, int32_t *launches_ou
   if (ms4)
     for (int i = 0; i < 4; ++i) ms4[i] = ctx->last_ms[i];
   if (launches_out) *launches_out = ctx->last_sens_launches;
+  return FSE_OK;
+}
+
+fse_status fse_get_tuning(const fse_ctx *ctx, int32_t *ncw, float *ms2) {
+  if (!ctx) return FSE_E_INVAL;
+  if (ncw) *ncw = ctx->fused_ncw;
+  if (ms2) {
+    ms2[0] = ctx->ncw_ms[0];
+    ms2[1] = ctx->ncw_ms[1];
+  }
   return FSE_OK;
 }
 

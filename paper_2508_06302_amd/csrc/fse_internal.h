@@ -117,6 +117,8 @@ struct fse_ctx {
   // tuning
   int sens_cols = 64;               // columns per sensitivity work-group (generic kernel)
   int fused_ncw = 2;                // column waves per fused work-group
+  bool ncw_autotune = true;         // tune fused_ncw on the first launch with sensitivities
+  float ncw_ms[2] = {0.0f, 0.0f};   // autotuner timings for 1 and 2 column waves
 
   // timing of the last integration
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -1052,12 +1052,49 @@ fse_status launch_fused(fse_ctx *ctx, int B, double *Phi) {
       return FSE_E_NOMEM;
     }
   }
-  FSE_TRY(reset_status(ctx));
-  switch (bw_bucket(ctx->bw)) {
-    case 4: return launch_bw<4>(ctx, B, Phi, p);
-    case 6: return launch_bw<6>(ctx, B, Phi, p);
-    case 8: return launch_bw<8>(ctx, B, Phi, p);
-    case 12: return launch_bw<12>(ctx, B, Phi, p);
-    default: return launch_bw<16>(ctx, B, Phi, p);
+  auto launch = [&]() -> fse_status {
+    FSE_TRY(reset_status(ctx));
+    switch (bw_bucket(ctx->bw)) {
+      case 4: return launch_bw<4>(ctx, B, Phi, p);
+      case 6: return launch_bw<6>(ctx, B, Phi, p);
+      case 8: return launch_bw<8>(ctx, B, Phi, p);
+      case 12: return launch_bw<12>(ctx, B, Phi, p);
+      default: return launch_bw<16>(ctx, B, Phi, p);
+    }
+  };
+  if (Phi && ctx->ncw_autotune) {
+    // Autotuner: the first launch with sensitivities times every column-wave count (each
+    // launch computes the full, identical result) and keeps the fastest for this context.
+    // More column waves per work-group mean fewer work-groups per trajectory but a larger
+    // work-group; which wins depends on n, the trajectory count and the CU count.
+    ctx->ncw_autotune = false;
+    hipEvent_t e0, e1;
+    FSE_HIP(hipEventCreate(&e0));
+    FSE_HIP(hipEventCreate(&e1));
+    int best = ctx->fused_ncw;
+    float best_ms = INFINITY;
+    for (int ncw = 1; ncw <= 2; ++ncw) {
+      ctx->fused_ncw = ncw;
+      FSE_HIP(hipEventRecord(e0, ctx->stream));
+      const fse_status st = launch();
+      FSE_HIP(hipEventRecord(e1, ctx->stream));
+      FSE_HIP(hipEventSynchronize(e1));
+      if (st != FSE_OK) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return st;
+      }
+      float ms = 0.0f;
+      FSE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ctx->ncw_ms[ncw - 1] = ms;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = ncw;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->fused_ncw = best;
   }
+  return launch();
 }

@@ -338,3 +338,24 @@ def test_c4_three_frequency_batched_points_sampled():
         for s_ in samples:
             assert rel(zT[b][:, s_].cpu().numpy(), ref["zbarT"][:, s_]) < RTOL, (b, s_)
             assert rel(phi[b, s_].cpu().numpy(), ref["Phi"][s_]) < 1e-9, (b, s_)
+
+
+def test_autotuner_times_both_configs_and_they_agree(monkeypatch):
+    """The fused kernel's column-wave count is tuned on the first launch with sensitivities;
+    the candidate configurations compute bit-identical states and sensitivities."""
+    m = fse()
+    s, tr, tb, om, Z0 = _tiny_case(n=4)
+    ctx = m.fse_init_torus(s, tr)
+    zT, phi = m.fse_integrate_batch(ctx, om[None], Z0[None], want_phi=True)
+    ncw, ms = m.fse_get_tuning(ctx)
+    log(f"autotuner: {ncw} column waves; timed launches {ms.tolist()} ms")
+    assert ncw in (1, 2) and ms.min() > 0 and ms[ncw - 1] == ms.min()
+    outs = []
+    for k in ("1", "2"):
+        monkeypatch.setenv("FSE_FUSED_NCW", k)
+        c = m.fse_init_torus(s, tr)
+        outs.append(m.fse_integrate_batch(c, om[None], Z0[None], want_phi=True))
+        assert m.fse_get_tuning(c)[0] == int(k)
+    assert np.array_equal(outs[0][0].cpu().numpy(), outs[1][0].cpu().numpy())
+    assert np.array_equal(outs[0][1].cpu().numpy(), outs[1][1].cpu().numpy())
+    assert np.array_equal(phi.cpu().numpy(), outs[0][1].cpu().numpy())
