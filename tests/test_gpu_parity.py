@@ -359,3 +359,32 @@ def test_autotuner_times_both_configs_and_they_agree(monkeypatch):
     assert np.array_equal(outs[0][0].cpu().numpy(), outs[1][0].cpu().numpy())
     assert np.array_equal(outs[0][1].cpu().numpy(), outs[1][1].cpu().numpy())
     assert np.array_equal(phi.cpu().numpy(), outs[0][1].cpu().numpy())
+
+
+def test_wide_band_shell_generic_kernels():
+    """A 360-DOF shell-like system (half bandwidth 47, 39k quadratic and 93k cubic force
+    terms) goes through the generic kernels with their global-memory factor scratch:
+    sampled trajectories against the oracle; the FP32-sensitivity path, which needs the
+    fused kernel, reports FSE_E_UNSUPPORTED."""
+    from fse_inputs.systems import synthetic_shell
+    m = fse()
+    s = synthetic_shell(NH=5, NL=10)
+    w1 = 0.98 * 628.31853072
+    om = np.array([w1, w1 / 2 ** 0.5])
+    tr = Torus(d=2, e=2, K=[np.arange(1, 4)], S=[8], S1=64)
+    tb = osh.TorusTables(tr)
+    Z0 = 1e-3 * np.random.default_rng(21).normal(size=(2 * s.n, tb.U)) / (1 + np.arange(tb.U))
+    ctx = m.fse_init_torus(s, tr)
+    U, St, bw, kt = m.fse_get_layout(ctx)
+    assert bw == 47
+    log("wide-band shell: gpu integrate with sensitivities")
+    zT, phi = m.fse_integrate_batch(ctx, om[None], Z0[None], want_phi=True)
+    samples = [0, 5]
+    log("wide-band shell: oracle samples")
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb, samples=samples)
+    for s_ in samples:
+        assert rel(zT[0][:, s_].cpu().numpy(), ref["zbarT"][:, s_]) < RTOL, s_
+        assert rel(phi[0, s_].cpu().numpy(), ref["Phi"][s_]) < 1e-9, s_
+    cm = m.fse_init_torus(s, tr, precision=m.FSE_PREC_MIXED_FP32)
+    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
+        m.fse_integrate_batch(cm, om[None], Z0[None], want_phi=True)
