@@ -165,15 +165,17 @@ fse_status fse_secant_predict(fse_ctx *ctx, int32_t np, const double *p_prev, co
                               const double *p_next, const double *Z_prev, const double *Z_cur,
                               double *Z_next);
 
-/* Natural-parameter continuation over P points (App. C, secant predictor).
+/* Natural-parameter continuation over P points (App. C, secant predictor, step control).
  * params: HOST [P][d+e]; point j has omega = params[j][0:d] and forcing amplitudes
  * params[j][d:d+e].  Point 0 starts from Z_init [2n][U], point 1 from the solution of
- * point 0, every later point from the secant prediction of the two previous solutions.
- * Each point is solved by fse_newton_solve(tol, maxit).  Z_out: [P][2n][U] solutions;
- * iters, rnorm: HOST [P] Newton iterations and final ||R||_2.  On failure at point j the
- * status of that point is returned with iters[j] = -1 and later points are not touched.
- * The forcing amplitudes stay at those of the last point attempted.  Needs d = e
- * (FSE_E_UNSUPPORTED otherwise). */
+ * point 0, every later point from the secant prediction of the two most recent solutions.
+ * Each point is solved by fse_newton_solve(tol, maxit); when that fails, the parameter step
+ * is halved by inserting the midpoint between the last solved point and the target (up to
+ * 6 times per requested point; inserted points are solved but not returned).
+ * Z_out: [P][2n][U] solutions; iters, rnorm: HOST [P] Newton iterations (including those
+ * of inserted points) and final ||R||_2.  On failure at point j the status is returned with
+ * iters[j] = -1 and later points are not touched.  The forcing amplitudes stay at those of
+ * the last point attempted.  Needs d = e (FSE_E_UNSUPPORTED otherwise). */
 fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const double *Z_init,
                             double tol, int32_t maxit, double *Z_out, int32_t *iters,
                             double *rnorm);

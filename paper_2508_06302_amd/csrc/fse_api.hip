@@ -749,26 +749,67 @@ fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const
   }
   const int np = ctx->d + ctx->e;
   const size_t N = (size_t)2 * ctx->n * ctx->U;
-  for (int j = 0; j < P; ++j) {
+  constexpr int kMaxBisect = 6;
+  // the last two solved points (requested or inserted): parameters on the host, tori on the
+  // device; the secant predictor uses them, so inserted points sharpen the prediction
+  double *hist = nullptr;
+  FSE_TRY(alloc(ctx, (void **)&hist, sizeof(double) * 2 * N));
+  double *Za = hist, *Zb = hist + N;
+  std::vector<double> pa(np), pb(np);
+  int solved = 0;
+  fse_status result = FSE_OK;
+  for (int j = 0; j < P && result == FSE_OK; ++j) {
     const double *pj = params + (size_t)j * np;
-    FSE_TRY(fse_set_forcing(ctx, pj + ctx->d));
     double *Zj = Z_out + j * N;
-    if (j == 0) {
-      FSE_HIP(hipMemcpyAsync(Zj, Z_init, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-    } else if (j == 1) {
-      FSE_HIP(hipMemcpyAsync(Zj, Z_out, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
-    } else {
-      FSE_TRY(fse_secant_predict(ctx, np, pj - 2 * np, pj - np, pj, Zj - 2 * N, Zj - N, Zj));
-    }
-    int32_t it = 0;
+    // targets still to reach on the way to p_j (a stack: the back is solved next)
+    std::vector<std::vector<double>> targets{std::vector<double>(pj, pj + np)};
+    int bisections = 0, total_it = 0;
     double rn = 0.0;
-    std::vector<double> om(pj, pj + ctx->d);
-    const fse_status st = fse_newton_solve(ctx, om.data(), Zj, tol, maxit, &it, &rn);
-    iters[j] = st == FSE_OK ? it : -1;
+    while (!targets.empty() && result == FSE_OK) {
+      const std::vector<double> pt = targets.back();
+      result = fse_set_forcing(ctx, pt.data() + ctx->d);
+      if (result != FSE_OK) break;
+      hipError_t e = hipSuccess;
+      if (solved == 0)
+        e = hipMemcpyAsync(Zj, Z_init, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream);
+      else if (solved == 1)
+        e = hipMemcpyAsync(Zj, Zb, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream);
+      else
+        result = fse_secant_predict(ctx, np, pa.data(), pb.data(), pt.data(), Za, Zb, Zj);
+      if (e != hipSuccess) result = FSE_E_DEVICE;
+      if (result != FSE_OK) break;
+      int32_t it = 0;
+      std::vector<double> om(pt.begin(), pt.begin() + ctx->d);
+      const fse_status st = fse_newton_solve(ctx, om.data(), Zj, tol, maxit, &it, &rn);
+      total_it += it;
+      if (st == FSE_OK) {
+        // accept: shift the history
+        if (hipMemcpyAsync(Za, Zb, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(Zb, Zj, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess) {
+          result = FSE_E_DEVICE;
+          break;
+        }
+        pa = pb;
+        pb = pt;
+        ++solved;
+        targets.pop_back();
+      } else if ((st == FSE_E_NOCONV || st == FSE_E_NAN || st == FSE_E_SINGULAR) && solved > 0 &&
+                 bisections < kMaxBisect) {
+        // step control: insert the midpoint between the last solved point and this target
+        std::vector<double> mid(np);
+        for (int k = 0; k < np; ++k) mid[k] = 0.5 * (pb[k] + pt[k]);
+        targets.push_back(mid);
+        ++bisections;
+      } else {
+        result = st;
+      }
+    }
+    iters[j] = result == FSE_OK ? total_it : -1;
     rnorm[j] = rn;
-    if (st != FSE_OK) return st;
   }
-  return FSE_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(hist);
+  return result;
 }
 
 fse_status fse_continuation_learned(fse_ctx *ctx, int32_t P, const double *params, const double *features,

@@ -250,6 +250,40 @@ def test_forcing_amplitude_continuation_c1():
     assert rel(Z[-1].cpu().numpy(), Zo) < 1e-8
 
 
+def test_continuation_step_control_bisects():
+    """A forcing step 0.1 -> 1.0 N that Newton cannot close in 4 iterations (the FP64
+    oracle's full-step Newton needs 5 from the 0.1 N solution): the continuation halves the
+    step, solves the inserted points, and returns the requested ones only.  Both results are
+    re-evaluated by the oracle and the 1.0 N torus is the oracle's own solution."""
+    import copy
+    s = tiny_system(n=3, seed=2, cubic=1.0, quad=0.3, e=2)
+    tr = Torus(d=2, e=2, K=[np.arange(1, 6)], S=[16], S1=64)
+    tb = osh.TorusTables(tr)
+    w = 0.45
+    om = np.array([w, GOLDEN * w])
+    amps = [0.1, 1.0]
+    params = np.array([[*om, a, a] for a in amps])
+    ctx = fse().fse_init_torus(s, tr)
+    Z0 = np.zeros((6, ctx.U))
+    Z, it, rn = fse().fse_continuation(ctx, params, Z0, tol=1e-12, maxit=4)
+    log(f"step-controlled continuation: iterations {it.tolist()} residuals {rn.tolist()}")
+    assert np.all(rn < 1e-12)
+    # a single solve stops after maxit iterations: more at point 1 means inserted points
+    assert it[1] > 4
+    for j, a in enumerate(amps):
+        sj = copy.copy(s)
+        sj.F = s.F * a
+        ref = osh.evaluate(sj, tr, om, Z[j].cpu().numpy(), tables=tb)
+        assert np.linalg.norm(ref["R"]) < 1e-10, (a, np.linalg.norm(ref["R"]))
+    s1 = copy.copy(s)
+    s1.F = s.F * 0.1
+    Zo1, _, _ = osh.solve(s1, tr, om, Z0, tol_R=1e-12, tables=tb)
+    s1.F = s.F * 1.0
+    Zo, _, h = osh.solve(s1, tr, om, Zo1, tol_R=1e-12, tables=tb)
+    assert h[-1] < 1e-12
+    assert rel(Z[1].cpu().numpy(), Zo) < 1e-8
+
+
 def test_mixed_precision_sensitivities():
     """FP32 column state: states stay FP64-exact, Phi within 1e-4 normwise of the
     FP64 oracle (tiny and the 147-DOF beam, sampled trajectories)."""
