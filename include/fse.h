@@ -180,6 +180,35 @@ fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const
                             double tol, int32_t maxit, double *Z_out, int32_t *iters,
                             double *rnorm);
 
+/* dR/dp for the continuation parameter p = omega_1 (Sec. 3.2.1): the forcing frequencies
+ * follow omega_1 at fixed ratios (frequency conditions omega_j = rho_j omega_1, j = 2..e) and
+ * the unknown frequencies omega_{e+1..d} are held.  By Eqs. (23)-(24) this is
+ * (I (x) R(rho) Gamma^-1) d zbar(2 pi)/d omega_1 - sum_u rho_u dR/d omega_u, where the
+ * trajectory derivative is the exact derivative of the converged discrete Newmark map with
+ * respect to the omega_1 of Eq. (E1) (App. E); the second sum is present for d > e only.
+ * omega: HOST [B][d]; Z0: device [B][2n][U]; R, dRdp: device [B][2n][U] outputs (R as in
+ * fse_shooting_residual_jacobian).  Errors as fse_integrate_batch. */
+fse_status fse_residual_dp(fse_ctx *ctx, int32_t B, const double *omega, const double *Z0, double *R,
+                           double *dRdp);
+
+/* Pseudo-arclength continuation in omega_1 (App. C): tangent predictor of Eqs. (C1)-(C2)
+ * and Newton corrections orthogonal to the tangent (Eq. C3) on the unknowns
+ * X = [Z(0); omega_u; omega_1] of the continuation problem of Sec. 3.2.1 (phase rows of
+ * Eq. 18 for d > e, forcing frequencies at the ratios of omega0).  The tangent has unit
+ * 2-norm over X; the first one solves Eq. (C1) with the row e_p oriented by the sign of ds.
+ * Point 0 is Z_init corrected at omega0 (fixed omega_1); every later point is predicted at
+ * step s from the previous one and corrected until ||R||_2 < tol in at most maxit Newton
+ * corrections.  Step control: a failed corrector is retried from the same point with s
+ * halved (at most 6 times); after an accepted point s doubles back, never beyond |ds|.
+ * omega0: HOST [d] (start; its ratios define the frequency conditions), Z_init: device
+ * [2n][U].  Outputs: Z_out device [P][2n][U]; HOST omega_out [P][d], steps [P] (step taken,
+ * 0 for point 0), iters [P] (corrections), rnorm [P] (final ||R||_2).  On failure at point
+ * j the status is returned with iters[j] = -1; earlier points are valid.  One dense
+ * (2nU + d - e + 1)^2 FP64 workspace is held by the context. */
+fse_status fse_arclength(fse_ctx *ctx, int32_t P, const double *omega0, const double *Z_init, double ds,
+                         double tol, int32_t maxit, double *Z_out, double *omega_out, double *steps,
+                         int32_t *iters, double *rnorm);
+
 /* ---------------------------------------------------------------- learned predictor
  * Initial iterates for new continuation parameters from the converged tori of earlier
  * points: a POD basis of the converged Z(0) (method of snapshots: Gram matrix in FP64,

@@ -17,7 +17,7 @@ __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integ
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
            "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
-           "fse_learned_create", "fse_continuation_learned", "fse_get_tuning", "FSE_PREC_FP64",
+           "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength", "fse_get_tuning", "FSE_PREC_FP64",
            "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
@@ -296,6 +296,45 @@ def fse_continuation(ctx: Context, params, Z_init, tol=1e-8, maxit=20):
         err.iters, err.rnorm, err.Z = it, rn, Z
         raise err
     return Z, it, rn
+
+
+def fse_residual_dp(ctx: Context, omega, Z0):
+    """omega host [B][d], Z0 [B][2n][U] -> (R, dR/dp) torch cuda [B][2n][U], p = omega_1 along
+    the frequency conditions (forcing ratios fixed, unknown frequencies held)."""
+    torch = _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(-1, ctx.d))
+    B = om.shape[0]
+    Z = _dev(Z0, (B, 2 * ctx.n, ctx.U))
+    R = torch.empty((B, 2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+    dRdp = torch.empty_like(R)
+    ctx.check(ctx.lib.fse_residual_dp(ctx.h, B, _p(om, C.c_double), C.c_void_p(Z.data_ptr()),
+                                      C.c_void_p(R.data_ptr()), C.c_void_p(dRdp.data_ptr())))
+    return R, dRdp
+
+
+def fse_arclength(ctx: Context, omega0, Z_init, ds, npts, tol=1e-8, maxit=8):
+    """Pseudo-arclength continuation in omega_1 from (omega0, Z_init): npts points ->
+    (Z [P][2n][U] torch cuda, omega [P][d], steps [P], corrections [P], ||R|| [P]).  Raises
+    FseError on a failed point, with the valid points attached (.Z, .omega, .iters...)."""
+    torch = _torch()
+    ctx.bind_stream()
+    om0 = np.ascontiguousarray(np.asarray(omega0, dtype=np.float64).reshape(ctx.d))
+    P = int(npts)
+    z0 = _dev(Z_init, (2 * ctx.n, ctx.U))
+    Z = torch.zeros((P, 2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+    om = np.zeros((P, ctx.d))
+    steps = np.zeros(P)
+    it = np.zeros(P, np.int32)
+    rn = np.zeros(P)
+    st = ctx.lib.fse_arclength(ctx.h, P, _p(om0, C.c_double), C.c_void_p(z0.data_ptr()), float(ds), float(tol),
+                               int(maxit), C.c_void_p(Z.data_ptr()), _p(om, C.c_double), _p(steps, C.c_double),
+                               _p(it, C.c_int32), _p(rn, C.c_double))
+    if st != 0:
+        err = FseError(st, ctx.lib.fse_last_error(ctx.h).decode())
+        err.Z, err.omega, err.steps, err.iters, err.rnorm = Z, om, steps, it, rn
+        raise err
+    return Z, om, steps, it, rn
 
 
 class Learned:

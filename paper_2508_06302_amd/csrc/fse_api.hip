@@ -389,7 +389,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)
@@ -603,8 +603,45 @@ fse_status newton_system(fse_ctx *ctx, const double *omega, const double *Z0, do
   return FSE_OK;
 }
 
-fse_status ensure_newton_buffers(fse_ctx *ctx) {
-  const size_t N = (size_t)2 * ctx->n * ctx->U, Nb = N + (ctx->d - ctx->e);
+fse_status ensure_dp_buffers(fse_ctx *ctx) {
+  const size_t N = (size_t)2 * ctx->n * ctx->U;
+  if (!ctx->dzw) FSE_TRY(alloc(ctx, (void **)&ctx->dzw, sizeof(double) * 2 * ctx->n * ctx->Wmax));
+  if (!ctx->zeros_d) {
+    FSE_TRY(alloc(ctx, (void **)&ctx->zeros_d, sizeof(double) * ctx->Bmax * N));
+    FSE_HIP(hipMemsetAsync(ctx->zeros_d, 0, sizeof(double) * ctx->Bmax * N, ctx->stream));
+  }
+  return FSE_OK;
+}
+
+// Integration of B points that also leaves the displacement history for the omega_1
+// sensitivity (the fused kernel writes it only on request).
+fse_status integrate_with_history(fse_ctx *ctx, int B, const double *omega, const double *Z0, double *Phi) {
+  ctx->want_qhist = true;
+  const fse_status st = integrate_impl(ctx, B, omega, Z0, nullptr, Phi);
+  ctx->want_qhist = false;
+  return st;
+}
+
+// dR/dp (p = omega_1 along the frequency conditions) after integrate_with_history and the
+// residual R at the same points: the trajectory term through the DFT and rotation of
+// d zbar(2 pi)/d omega_1, then, for d > e, minus rho_u dR/d omega_u.
+fse_status dp_after_integration(fse_ctx *ctx, int B, const double *omega, const double *Z0, const double *R,
+                                double *dRdp) {
+  const int mi = ctx->last_max_iters;
+  const unsigned long long ti = ctx->last_total_iters;
+  FSE_TRY(reset_status(ctx));
+  FSE_TRY(launch_wsens(ctx, B, ctx->dzw));
+  const fse_status st = check_status(ctx);
+  ctx->last_max_iters = mi;  // the step statistics stay those of the integration
+  ctx->last_total_iters = ti;
+  FSE_TRY(st);
+  FSE_TRY(launch_dft(ctx, B, ctx->dzw, ctx->zeros_d, dRdp));
+  FSE_TRY(launch_dRdp_rot(ctx, B, omega, R, Z0, dRdp));
+  return FSE_OK;
+}
+
+// Square workspace for an Nb x Nb dense system (grown, never shrunk).
+fse_status ensure_matrix(fse_ctx *ctx, size_t Nb) {
   if (ctx->Jw_elems < Nb * Nb) {
     if (ctx->Jw) (void)hipFree(ctx->Jw);
     ctx->Jw = nullptr;
@@ -612,6 +649,12 @@ fse_status ensure_newton_buffers(fse_ctx *ctx) {
     FSE_TRY(alloc(ctx, (void **)&ctx->Jw, sizeof(double) * Nb * Nb));
     ctx->Jw_elems = Nb * Nb;
   }
+  return FSE_OK;
+}
+
+fse_status ensure_newton_buffers(fse_ctx *ctx) {
+  const size_t N = (size_t)2 * ctx->n * ctx->U, Nb = N + (ctx->d - ctx->e);
+  FSE_TRY(ensure_matrix(ctx, Nb));
   if (!ctx->work_b) FSE_TRY(alloc(ctx, (void **)&ctx->work_b, sizeof(double) * 2 * Nb));
   return FSE_OK;
 }
@@ -810,6 +853,186 @@ fse_status fse_continuation(fse_ctx *ctx, int32_t P, const double *params, const
   (void)hipStreamSynchronize(ctx->stream);
   (void)hipFree(hist);
   return result;
+}
+
+fse_status fse_residual_dp(fse_ctx *ctx, int32_t B, const double *omega, const double *Z0, double *R,
+                           double *dRdp) {
+  if (!ctx || !omega || !Z0 || !R || !dRdp) return FSE_E_INVAL;
+  FSE_TRY(ensure_dp_buffers(ctx));
+  FSE_TRY(integrate_with_history(ctx, B, omega, Z0, nullptr));
+  FSE_TRY(launch_dft_residual(ctx, B, Z0, R));
+  FSE_TRY(dp_after_integration(ctx, B, omega, Z0, R, dRdp));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kArcHalvings = 6;
+
+// Extended matrix of the arclength corrector at (omega, Z0) (Eqs. C1, C3): rows [R; phase rows;
+// t^T], columns [Z(0) (N), omega_u (d - e), p = omega_1], row-major with ld = Na = N + d - e + 1;
+// rhs = [R; 0; 0].  col receives dR/dp (N).
+fse_status arclength_system(fse_ctx *ctx, const double *omega, const double *Z0, const double *t, double *A,
+                            double *rhs, double *col, double *rn) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  const size_t Na = (size_t)N + nu + 1;
+  FSE_TRY(ensure_phi(ctx));
+  FSE_TRY(ensure_dp_buffers(ctx));
+  FSE_TRY(integrate_with_history(ctx, 1, omega, Z0, ctx->PhiQU));
+  FSE_TRY(launch_dft_residual(ctx, 1, Z0, rhs));
+  FSE_TRY(launch_norms(ctx, 1, rhs, rn));
+  FSE_TRY(launch_jacobian(ctx, 1, ctx->PhiQU, A, Na));
+  if (nu > 0) FSE_TRY(launch_border(ctx, A, Na, rhs, Z0, omega[0]));
+  FSE_TRY(dp_after_integration(ctx, 1, omega, Z0, rhs, col));
+  FSE_TRY(launch_set_pcol(ctx, A, Na, col));
+  FSE_HIP(hipMemcpyAsync(A + (Na - 1) * Na, t, sizeof(double) * Na, hipMemcpyDeviceToDevice, ctx->stream));
+  FSE_HIP(hipMemsetAsync(rhs + N, 0, sizeof(double) * (nu + 1), ctx->stream));
+  return FSE_OK;
+}
+
+// Frequencies of the iterate X = [Z(0); omega_u; p]: omega_1 = p, the forcing frequencies at
+// the ratios of omega_ref (frequency conditions), omega_u from X.
+fse_status arc_frequencies(fse_ctx *ctx, const double *omega_ref, const double *X, std::vector<double> &om) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e, e = ctx->e;
+  std::vector<double> tail(nu + 1);
+  FSE_HIP(hipMemcpyAsync(tail.data(), X + N, sizeof(double) * (nu + 1), hipMemcpyDeviceToHost, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  const double p = tail[nu];
+  om[0] = p;
+  for (int j = 1; j < e; ++j) om[j] = omega_ref[j] / omega_ref[0] * p;
+  for (int u = 0; u < nu; ++u) om[e + u] = tail[u];
+  if (!(p > 0.0) || !std::isfinite(p)) {
+    ctx->err = "arclength iterate left omega_1 > 0";
+    return FSE_E_NAN;
+  }
+  return FSE_OK;
+}
+
+// Corrector of Eq. (C3): Newton on [F; t^T (X - X_pred)] from X = X_pred (in place).  On
+// success A holds the extended matrix at the solution (last row t^T).
+fse_status arc_corrector(fse_ctx *ctx, const double *omega_ref, double *X, const double *t, double tol,
+                         int maxit, double *A, double *rhs, double *col, int *iters, double *rn,
+                         std::vector<double> &om) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  const int Na = N + nu + 1;
+  *rn = INFINITY;
+  for (int k = 0;; ++k) {
+    *iters = k;
+    FSE_TRY(arc_frequencies(ctx, omega_ref, X, om));
+    FSE_TRY(arclength_system(ctx, om.data(), X, t, A, rhs, col, rn));
+    if (*rn < tol) return FSE_OK;
+    if (k >= maxit || !std::isfinite(*rn)) {
+      ctx->err = "arclength corrector did not reach the residual tolerance";
+      return FSE_E_NOCONV;
+    }
+    FSE_TRY(dense_lu_solve(ctx, A, Na, rhs));
+    FSE_TRY(launch_axpy(ctx, Na, -1.0, rhs, X));
+  }
+}
+
+// Tangent of Eq. (C1) at the point where A was built: A y = e_last, t = y / ||y||_2.
+fse_status arc_tangent(fse_ctx *ctx, double *A, double *y, double *t) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  const int Na = N + nu + 1;
+  const double one = 1.0;
+  FSE_HIP(hipMemsetAsync(y, 0, sizeof(double) * Na, ctx->stream));
+  FSE_HIP(hipMemcpyAsync(y + Na - 1, &one, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  FSE_TRY(dense_lu_solve(ctx, A, Na, y));
+  double nrm = 0.0;
+  FSE_TRY(launch_norm(ctx, y, (size_t)Na, &nrm));
+  if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+    ctx->err = "degenerate tangent";
+    return FSE_E_SINGULAR;
+  }
+  FSE_TRY(launch_axpby(ctx, Na, 1.0 / nrm, y, 0.0, y, t));
+  return FSE_OK;
+}
+
+bool arc_retryable(fse_status st) {
+  return st == FSE_E_NOCONV || st == FSE_E_NAN || st == FSE_E_SINGULAR;
+}
+
+}  // namespace
+
+extern "C" {
+
+fse_status fse_arclength(fse_ctx *ctx, int32_t P, const double *omega0, const double *Z_init, double ds,
+                         double tol, int32_t maxit, double *Z_out, double *omega_out, double *steps,
+                         int32_t *iters, double *rnorm) {
+  if (!ctx || P < 1 || !omega0 || !Z_init || !Z_out || !omega_out || !steps || !iters || !rnorm || maxit < 0)
+    return FSE_E_INVAL;
+  if (!(ds != 0.0) || !std::isfinite(ds) || !(tol > 0.0)) {
+    ctx->err = "arclength step must be finite and non-zero, tol positive";
+    return FSE_E_INVAL;
+  }
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e, d = ctx->d, e = ctx->e;
+  const size_t Na = (size_t)N + nu + 1;
+  FSE_TRY(ensure_matrix(ctx, Na));
+  if (ctx->arc_elems < 6 * Na) {
+    if (ctx->arc) (void)hipFree(ctx->arc);
+    ctx->arc = nullptr;
+    ctx->arc_elems = 0;
+    FSE_TRY(alloc(ctx, (void **)&ctx->arc, sizeof(double) * 6 * Na));
+    ctx->arc_elems = 6 * Na;
+  }
+  double *X = ctx->arc, *Xj = X + Na, *t = Xj + Na, *rhs = t + Na, *y = rhs + Na, *col = y + Na;
+  double *A = ctx->Jw;
+  // X = [Z_init; omega_u; omega_1]; first tangent row sign(ds) e_p
+  std::vector<double> tail(nu + 1);
+  for (int u = 0; u < nu; ++u) tail[u] = omega0[e + u];
+  tail[nu] = omega0[0];
+  FSE_HIP(hipMemcpyAsync(X, Z_init, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+  FSE_HIP(hipMemcpyAsync(X + N, tail.data(), sizeof(double) * (nu + 1), hipMemcpyHostToDevice, ctx->stream));
+  const double sgn = ds > 0.0 ? 1.0 : -1.0;
+  FSE_HIP(hipMemsetAsync(t, 0, sizeof(double) * Na, ctx->stream));
+  FSE_HIP(hipMemcpyAsync(t + Na - 1, &sgn, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<double> om(d);
+  int it = 0;
+  double rn = INFINITY;
+  // point 0: corrected at fixed omega_1 (the row e_p^T dX = 0), then the tangent with e_p
+  fse_status st = arc_corrector(ctx, omega0, X, t, tol, maxit, A, rhs, col, &it, &rn, om);
+  if (st != FSE_OK) {
+    iters[0] = -1;
+    rnorm[0] = rn;
+    return st;
+  }
+  const double s_max = std::fabs(ds);
+  double s = s_max;
+  for (int j = 0;; ++j) {
+    FSE_HIP(hipMemcpyAsync(Z_out + (size_t)j * N, X, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    for (int k = 0; k < d; ++k) omega_out[(size_t)j * d + k] = om[k];
+    steps[j] = j == 0 ? 0.0 : s;
+    iters[j] = it;
+    rnorm[j] = rn;
+    if (j + 1 == P) break;
+    FSE_TRY(arc_tangent(ctx, A, y, t));
+    FSE_HIP(hipMemcpyAsync(Xj, X, sizeof(double) * Na, hipMemcpyDeviceToDevice, ctx->stream));
+    if (j > 0) s = std::min(2.0 * s, s_max);
+    bool ok = false;
+    for (int h = 0; h <= kArcHalvings; ++h) {
+      FSE_TRY(launch_lincomb(ctx, (int)Na, Xj, s, t, X));  // predictor, Eq. (C2)
+      st = arc_corrector(ctx, omega0, X, t, tol, maxit, A, rhs, col, &it, &rn, om);
+      if (st == FSE_OK) {
+        ok = true;
+        break;
+      }
+      if (!arc_retryable(st)) return st;
+      s *= 0.5;
+    }
+    if (!ok) {
+      iters[j + 1] = -1;
+      rnorm[j + 1] = rn;
+      ctx->err = "arclength corrector failed after " + std::to_string(kArcHalvings) + " step halvings";
+      return FSE_E_NOCONV;
+    }
+  }
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
 }
 
 fse_status fse_continuation_learned(fse_ctx *ctx, int32_t P, const double *params, const double *features,

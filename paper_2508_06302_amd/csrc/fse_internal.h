@@ -106,6 +106,12 @@ struct fse_ctx {
   double *sens_gscr = nullptr;      // factor scratch when it does not fit in LDS
   size_t sens_gscr_elems = 0;
   size_t Jw_elems = 0;
+  // omega_1 derivative (arclength continuation)
+  bool want_qhist = false;          // the next integration writes the displacement history
+  double *dzw = nullptr;            // [2n][Wmax] d zbar(2 pi) / d omega_1
+  double *zeros_d = nullptr;        // [Bmax][2n][U] zeros
+  double *arc = nullptr;            // arclength vectors, 5 x (2nU + d - e + 1)
+  size_t arc_elems = 0;
 
   // packed tensors for LDS staging: t2 (j | k << 16), t3 (j | k << 16, l)
   uint32_t *f2_pk = nullptr, *f3_pk = nullptr;
@@ -135,12 +141,18 @@ fse_status launch_idft(fse_ctx *ctx, int B, const double *Z0);
 fse_status launch_state(fse_ctx *ctx, int B);
 fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU);
 fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R);
+// (I (x) R(rho) Gamma^-1) zT - Z0 for terminal samples zT [2n][Wmax]
+fse_status launch_dft(fse_ctx *ctx, int B, const double *zT, const double *Z0, double *R);
 fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J, size_t ldJ);
 fse_status launch_dRdw(fse_ctx *ctx, double *out, const double *R, const double *Z0, double omega1);
 fse_status launch_border(fse_ctx *ctx, double *Jb, size_t ldJ, const double *R, const double *Z0,
                          double omega1);
-fse_status launch_dRdw(fse_ctx *ctx, int B, const double *Z0, double *dRdw);
 fse_status launch_norms(fse_ctx *ctx, int B, const double *R, double *out_host);
+fse_status launch_norm(fse_ctx *ctx, const double *x, size_t len, double *out_host);
+fse_status launch_wsens(fse_ctx *ctx, int B, double *dzT);
+fse_status launch_dRdp_rot(fse_ctx *ctx, int B, const double *omega, const double *R, const double *Z0,
+                           double *dRdp);
+fse_status launch_set_pcol(fse_ctx *ctx, double *A, size_t ldA, const double *col);
 // Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16
 bool fused_supported(const fse_ctx *ctx);
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);

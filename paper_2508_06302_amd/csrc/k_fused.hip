@@ -66,6 +66,7 @@ struct FusedArgs {
   const double *q0, *u0;                   // [n][ldw]
   int ldw;
   double *zT;                              // [2n][ldw]
+  double *qhist;                           // [S1+1][n][ldw] rows 1..S1 written, or null
   double *Phi;                             // [W][2n][2n] or null
   void *colQ, *colU, *colA, *colY;         // column state [n][2n] blocks (CT elements)
   size_t colQ_ws, colU_ws, colA_ws, colY_ws;  // element stride between trajectories
@@ -826,6 +827,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
         qsn[i] = qn[i];
         // two-step first-order prediction of q_{k+3} for the chord wave
         pqn[i] = qn[i] + 2.0 * P.h * un;
+        if (a.qhist && blockIdx.x == 0) a.qhist[((size_t)(k + 1) * n + i) * a.ldw + w] = qn[i];
       }
       wave_sync();
     } else if (wave == 1 && k + 1 < P.S1) {
@@ -970,6 +972,7 @@ fse_status launch_bw(fse_ctx *ctx, int B, double *Phi, const TrajParams &P) {
   a.u0 = ctx->u0;
   a.ldw = ctx->Wmax;
   a.zT = ctx->zTw;
+  a.qhist = ctx->want_qhist ? ctx->qhist : nullptr;
   a.Phi = Phi;
   a.st = ctx->status_d;
   const size_t blk = n * 2 * n;  // one [n][2n] block

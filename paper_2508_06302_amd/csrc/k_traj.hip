@@ -469,6 +469,139 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
   }
 }
 
+// ------------------------------------------------------------------------ omega_1 sensitivity
+// d zbar(2 pi) / d omega_1 with the forcing frequency ratios held (frequency conditions of
+// Sec. 3.2.1): the forcing is then a fixed function of phi_1 and omega_1 enters Eq. (E1) only
+// through w1^2 M and w1 D.  Exact derivative of the converged discrete map (Eqs. E4-E7):
+//   T Qw_{k+1} = w1^2 M (c0 Qw_k + c1 Uw_k + Aw_k) + w1 D (c2 Qw_k + Uw_k)
+//                - (2 w1 c0 M + c2 D) q_{k+1} + 2 w1 M (c0 q_k + c1 u_k + a_k) + D (c2 q_k + u_k)
+//   Uw_{k+1} = c2 (Qw_{k+1} - Qw_k) - Uw_k,  Aw_{k+1} = c0 (Qw_{k+1} - Qw_k) - c1 Uw_k - Aw_k
+// with T = S + K_t(q_{k+1}), Qw_0 = Uw_0 = 0 and w1^2 M Aw_0 = -D u_0 - 2 w1 M a_0 (the
+// derivative of the consistent initial acceleration).  One block per trajectory; the state is
+// replayed from the displacement history of the integration, so the derivative is that of the
+// very trajectory whose end point enters R.  Output dzT [2n][ldw] = [Qw; Uw](2 pi).
+template <bool LDS>
+__global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omega,
+                        const int32_t *__restrict__ sidx, const int32_t *__restrict__ Sdim,
+                        const double *__restrict__ qhist, const double *__restrict__ u0, int ldw,
+                        double *__restrict__ dzT, double *__restrict__ gscr, DevStatus *st) {
+  extern __shared__ double smem[];
+  const int n = P.n, bw = P.bw, bp = bw + 1, w = blockIdx.x;
+  const size_t stride = (size_t)n * bp + 8 * (size_t)n + 80;
+  double *base = LDS ? smem : gscr + (size_t)w * stride;
+  double *Lf = base;
+  double *q = Lf + (size_t)n * bp;
+  double *u = q + n;
+  double *a = u + n;
+  double *qn = a + n;
+  double *Qw = qn + n;
+  double *Uw = Qw + n;
+  double *Aw = Uw + n;
+  double *x = Aw + n;
+  double *cs = x + n;            // e cosines (<= 8)
+  double *red = cs + 8;          // block reduction scratch (<= 64)
+  const int b = w / P.St, s = w - b * P.St;
+  const double *om = omega + b * P.d;
+  const double w1 = om[0];
+  const double w1s = w1 * w1;
+  const int W2 = 2 * bw + 1;
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  for (int i = tid; i < n; i += nt) {
+    q[i] = qhist[(size_t)i * ldw + w];
+    u[i] = u0[(size_t)i * ldw + w];
+  }
+  if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s);
+  __syncthreads();
+  // consistent initial acceleration (w1^2 M) a0 = e0 - w1 D u0 - K q0 - f_nl(q0)
+  for (int i = tid; i < n; i += nt) {
+    double v = 0.0;
+    for (int f = 0; f < P.e; ++f) v += sy.F[(size_t)f * n + i] * cs[f];
+    for (int t = 0; t < W2; ++t) {
+      const int j = i - bw + t;
+      if (j < 0 || j >= n) continue;
+      v -= w1 * sy.Db[(size_t)i * W2 + t] * u[j] + sy.Kb[(size_t)i * W2 + t] * q[j];
+    }
+    a[i] = v - fnl_row(sy, q, i);
+  }
+  for (int pos = tid; pos < n * bp; pos += nt) {
+    const int m = pos / bp, t = pos - m * bp, i = m + t;
+    Lf[pos] = i < n ? w1s * sy.Mb[(size_t)i * W2 + (bw - t)] : 0.0;
+  }
+  __syncthreads();
+  band_ldlt(Lf, n, bw, st);
+  band_solve(Lf, n, bw, a, red);
+  // (w1^2 M) Aw_0 = -D u0 - 2 w1 M a0
+  for (int i = tid; i < n; i += nt) {
+    double v = 0.0;
+    for (int t = 0; t < W2; ++t) {
+      const int j = i - bw + t;
+      if (j < 0 || j >= n) continue;
+      v -= sy.Db[(size_t)i * W2 + t] * u[j] + 2.0 * w1 * sy.Mb[(size_t)i * W2 + t] * a[j];
+    }
+    x[i] = v;
+  }
+  __syncthreads();
+  band_solve(Lf, n, bw, x, red);
+  for (int i = tid; i < n; i += nt) {
+    Qw[i] = 0.0;
+    Uw[i] = 0.0;
+    Aw[i] = x[i];
+  }
+  __syncthreads();
+
+  for (int k = 0; k < P.S1; ++k) {
+    for (int i = tid; i < n; i += nt) qn[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
+    __syncthreads();
+    for (int i = tid; i < n; i += nt) {
+      double v = 0.0;
+      for (int t = 0; t < W2; ++t) {
+        const int j = i - bw + t;
+        if (j < 0 || j >= n) continue;
+        const double Mij = sy.Mb[(size_t)i * W2 + t], Dij = sy.Db[(size_t)i * W2 + t];
+        v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + Uw[j]);
+        v += -(2.0 * w1 * P.c0 * Mij + P.c2 * Dij) * qn[j] +
+             2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + a[j]) + Dij * (P.c2 * q[j] + u[j]);
+      }
+      x[i] = v;
+    }
+    for (int pos = tid; pos < n * bp; pos += nt) {
+      const int m = pos / bp, t = pos - m * bp, i = m + t;
+      double v = 0.0;
+      if (i < n) {
+        const size_t e = (size_t)i * W2 + (bw - t);
+        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, pos);
+      }
+      Lf[pos] = v;
+    }
+    __syncthreads();
+    band_ldlt(Lf, n, bw, st);
+    band_solve(Lf, n, bw, x, red);
+    for (int i = tid; i < n; i += nt) {
+      const double dQ = x[i] - Qw[i];
+      const double uwn = P.c2 * dQ - Uw[i];
+      const double awn = P.c0 * dQ - P.c1 * Uw[i] - Aw[i];
+      Qw[i] = x[i];
+      Uw[i] = uwn;
+      Aw[i] = awn;
+      const double dqk = qn[i] - q[i];
+      const double un = P.c2 * dqk - u[i];
+      const double an = P.c0 * dqk - P.c1 * u[i] - a[i];
+      u[i] = un;
+      a[i] = an;
+      q[i] = qn[i];
+    }
+    __syncthreads();
+  }
+  bool nan = false;
+  for (int i = tid; i < n; i += nt) {
+    dzT[(size_t)i * ldw + w] = Qw[i];
+    dzT[(size_t)(n + i) * ldw + w] = Uw[i];
+    if (!isfinite(Qw[i]) || !isfinite(Uw[i])) nan = true;
+  }
+  if (nan) atomicOr(&st->flags, (int)DEV_NAN);
+}
+
 // ------------------------------------------------------------------------ DFT, rotation, residual
 // R = (I (x) R(rho)) (I (x) Gamma^-1) zbar(2 pi) - Z(0)   (Eqs. 15, 16, 21)
 __global__ void k_dft_residual(const double *__restrict__ zT, int ldw, const double *__restrict__ Gi,
@@ -701,8 +834,12 @@ fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU) {
 }
 
 fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R) {
+  return launch_dft(ctx, B, ctx->zTw, Z0, R);
+}
+
+fse_status launch_dft(fse_ctx *ctx, int B, const double *zT, const double *Z0, double *R) {
   const int total = B * 2 * ctx->n * (ctx->L + 1);
-  hipLaunchKernelGGL(k_dft_residual, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, ctx->zTw,
+  hipLaunchKernelGGL(k_dft_residual, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, zT,
                      ctx->Wmax, ctx->Gi_d, ctx->rot_d, Z0, ctx->n, ctx->U, ctx->L, ctx->St, B, R);
   FSE_HIP(hipGetLastError());
   return FSE_OK;
@@ -782,6 +919,99 @@ fse_status launch_dRdw(fse_ctx *ctx, double *out, const double *R, const double 
   hipLaunchKernelGGL(k_dRdw, dim3((N * nu + 255) / 256), dim3(256), 0, ctx->stream, out, N, nu, R, Z0,
                      ctx->ktable_d, ctx->d - 1, ctx->e, 2.0 * M_PI / omega1, ctx->U);
   FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+// dR/dp -= sum_u rho_u dR/d omega_u (u = e..d-1): with omega_u held while omega_1 = p moves,
+// rho_u = omega_u / omega_1 changes by -rho_u / omega_1 per unit p; the rotation term of
+// dR/d omega_u (Eqs. 23-24, as in k_dRdw) is taken from R + Z0 = R(rho) Z(2 pi).
+struct RhoU {
+  double v[8];
+};
+
+__global__ void k_dRdp_rot(double *__restrict__ dRdp, int N, int nu, const double *__restrict__ R,
+                           const double *__restrict__ Z0, const int32_t *__restrict__ ktable, int dm1,
+                           int e, double two_pi_over_w1, int U, RhoU rho) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const int a = r % U, base = r - a;
+  if (a == 0) return;
+  const int l = (a - 1) / 2;
+  double acc = 0.0;
+  for (int u = 0; u < nu; ++u) {
+    const double k = (double)ktable[(size_t)l * dm1 + e + u - 1];
+    const double dr = (a & 1) ? -two_pi_over_w1 * k * (R[base + a + 1] + Z0[base + a + 1])
+                              : two_pi_over_w1 * k * (R[base + a - 1] + Z0[base + a - 1]);
+    acc += rho.v[u] * dr;
+  }
+  dRdp[r] -= acc;
+}
+
+// Column N + nu of the arclength matrix: dR/dp in rows 0..N-1, zero in the phase rows.
+__global__ void k_set_pcol(double *__restrict__ A, size_t ldA, int N, int nu, const double *__restrict__ col) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N + nu) return;
+  A[(size_t)r * ldA + N + nu] = r < N ? col[r] : 0.0;
+}
+
+fse_status launch_wsens(fse_ctx *ctx, int B, double *dzT) {
+  const TrajParams P = params(ctx, B);
+  const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 8 * (size_t)ctx->n + 80;
+  const size_t bytes = elems * sizeof(double);
+  const int threads = ctx->bw > 24 ? 256 : 64;
+  if (bytes <= kLdsLimit) {
+    hipLaunchKernelGGL(k_wsens<true>, dim3(P.W), dim3(threads), bytes, ctx->stream, P, sysdev(ctx),
+                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->Wmax, dzT, nullptr,
+                       ctx->status_d);
+  } else {
+    if (!ctx->state_scr) {
+      if (hipMalloc((void **)&ctx->state_scr, sizeof(double) * elems * ctx->Wmax) != hipSuccess) {
+        ctx->err = "hipMalloc failed for the state scratch";
+        return FSE_E_NOMEM;
+      }
+    }
+    hipLaunchKernelGGL(k_wsens<false>, dim3(P.W), dim3(threads), 0, ctx->stream, P, sysdev(ctx),
+                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->Wmax, dzT,
+                       ctx->state_scr, ctx->status_d);
+  }
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_dRdp_rot(fse_ctx *ctx, int B, const double *omega, const double *R, const double *Z0,
+                           double *dRdp) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  if (nu <= 0) return FSE_OK;
+  if (nu > 8) {
+    ctx->err = "at most 8 unknown base frequencies";
+    return FSE_E_UNSUPPORTED;
+  }
+  for (int b = 0; b < B; ++b) {
+    const double *om = omega + (size_t)b * ctx->d;
+    RhoU rho{};
+    for (int u = 0; u < nu; ++u) rho.v[u] = om[ctx->e + u] / om[0];
+    hipLaunchKernelGGL(k_dRdp_rot, dim3((N + 255) / 256), dim3(256), 0, ctx->stream, dRdp + (size_t)b * N, N,
+                       nu, R + (size_t)b * N, Z0 + (size_t)b * N, ctx->ktable_d, ctx->d - 1, ctx->e,
+                       2.0 * M_PI / om[0], ctx->U, rho);
+  }
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_set_pcol(fse_ctx *ctx, double *A, size_t ldA, const double *col) {
+  const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e;
+  hipLaunchKernelGGL(k_set_pcol, dim3((N + nu + 255) / 256), dim3(256), 0, ctx->stream, A, ldA, N, nu, col);
+  FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status launch_norm(fse_ctx *ctx, const double *x, size_t len, double *out_host) {
+  hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, ctx->stream, x, len, ctx->norm_d);
+  FSE_HIP(hipGetLastError());
+  double h = 0.0;
+  FSE_HIP(hipMemcpyAsync(&h, ctx->norm_d, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  *out_host = std::sqrt(h);
   return FSE_OK;
 }
 

@@ -1,0 +1,154 @@
+"""GPU pseudo-arclength continuation in omega_1 (App. C) and its dR/dp (Eqs. 23-24, frequency
+conditions of Sec. 3.2.1) against the oracle.
+
+Bar: dR/dp normwise relative <= 1e-10 (exact derivative of the same discrete map on both
+sides); converged path points (||R|| < 1e-12) within 1e-9 relative of the oracle's path,
+the same steps taken, and the folds at the same points.
+"""
+import numpy as np
+import pytest
+
+from fse_inputs import Torus, tiny_system, workload
+from fse_inputs.systems import System
+from oracle import continuation as ocont
+from oracle import shooting as osh
+
+pytestmark = pytest.mark.gpu
+GOLDEN = (1 + 5 ** 0.5) / 2
+RTOL = 1e-10
+
+
+def fse():
+    import paper_2508_06302_amd as m
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def duffing(k3=0.5, F=0.15, D=0.1):
+    return System("duffing", np.eye(1), np.array([[D]]), np.eye(1), np.zeros((0, 3), np.int32),
+                  np.zeros(0), np.array([[0, 0, 0, 0]], np.int32), np.array([k3]), np.array([[F]]))
+
+
+def _case(d, e, n=3, seed=2):
+    s = tiny_system(n=n, seed=seed, cubic=1.0, quad=0.3, e=e)
+    om = np.array([0.8, 0.8 * GOLDEN, 0.8 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=e, K=[np.arange(1, 4)] * (d - 1), S=[8] * (d - 1), S1=64)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(seed).normal(size=(2 * n, tb.U))
+    return s, tr, tb, om, Z0
+
+
+@pytest.mark.parametrize("kernels", ["fused", "generic"])
+@pytest.mark.parametrize("d,e", [(2, 2), (2, 1), (3, 2), (3, 3)])
+def test_residual_dp_matches_oracle(d, e, kernels, monkeypatch):
+    monkeypatch.setenv("FSE_KERNELS", kernels)
+    s, tr, tb, om, Z0 = _case(d, e)
+    log(f"dR/dp d={d} e={e} kernels={kernels}")
+    ref = osh.evaluate(s, tr, om, Z0, omega_sens=True, tables=tb)
+    dref = ocont.residual_dp(ref, om, e)
+    ctx = fse().fse_init_torus(s, tr)
+    R, dRdp = fse().fse_residual_dp(ctx, om[None], Z0[None])
+    assert rel(R[0].cpu().numpy(), ref["R"]) < RTOL
+    err = rel(dRdp[0].cpu().numpy().ravel(), dref)
+    log(f"  dR/dp rel err {err:.2e}")
+    assert err < RTOL
+
+
+def test_residual_dp_batched_points_and_d1():
+    """B = 3 points with different omega in one launch; and d = 1 (classical shooting)."""
+    s, tr, tb, om, Z0 = _case(2, 2)
+    oms = np.stack([om, om * 1.01, om * 0.97])
+    Zs = np.stack([Z0, 0.5 * Z0, -Z0])
+    ctx = fse().fse_init_torus(s, tr, max_batch=3)
+    R, dRdp = fse().fse_residual_dp(ctx, oms, Zs)
+    for b in range(3):
+        ref = osh.evaluate(s, tr, oms[b], Zs[b], omega_sens=True, tables=tb)
+        assert rel(dRdp[b].cpu().numpy().ravel(), ocont.residual_dp(ref, oms[b], 2)) < RTOL
+    s1 = duffing()
+    tr1 = Torus(d=1, e=1, K=[], S=[], S1=64)
+    tb1 = osh.TorusTables(tr1)
+    Z1 = np.array([[0.3], [-0.2]])
+    om1 = np.array([0.9])
+    ref = osh.evaluate(s1, tr1, om1, Z1, omega_sens=True, tables=tb1)
+    ctx1 = fse().fse_init_torus(s1, tr1)
+    _, d1 = fse().fse_residual_dp(ctx1, om1[None], Z1[None])
+    assert rel(d1[0].cpu().numpy().ravel(), ocont.residual_dp(ref, om1, 1)) < RTOL
+
+
+def test_residual_dp_c1_all_trajectories():
+    """C1 (10-DOF cantilever, 256 trajectories, S1 = 256) through the fused kernel."""
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    ref = osh.evaluate(wl.system, wl.torus, wl.omega, Z0, omega_sens=True, tables=tb)
+    dref = ocont.residual_dp(ref, wl.omega, wl.torus.e)
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    _, dRdp = fse().fse_residual_dp(ctx, wl.omega[None], Z0[None])
+    err = rel(dRdp[0].cpu().numpy().ravel(), dref)
+    log(f"C1 dR/dp rel err {err:.2e}")
+    assert err < RTOL
+
+
+def _compare_paths(Z, om, steps, it, path, ztol=1e-9):
+    assert np.all(it >= 0)
+    for j, p in enumerate(path):
+        assert abs(om[j][0] - p["omega"][0]) < ztol * p["omega"][0], (j, om[j], p["omega"])
+        assert rel(Z[j].cpu().numpy(), p["Z"]) < ztol, (j, rel(Z[j].cpu().numpy(), p["Z"]))
+        assert steps[j] == p["s"], (j, steps[j], p["s"])
+
+
+def test_arclength_duffing_through_both_folds():
+    """Forced Duffing oscillator (d = 1): the GPU path is the oracle's, point by point,
+    through the upper and the lower fold of the resonance curve."""
+    s = duffing()
+    tr = Torus(d=1, e=1, K=[], S=[], S1=64)
+    tb = osh.TorusTables(tr)
+    om0 = np.array([0.6])
+    Z0, _, _ = osh.solve(s, tr, om0, np.zeros((2, 1)), tol_R=1e-13, tables=tb)
+    path = ocont.arclength(s, tr, om0, Z0, 0.15, 26, tables=tb, tol_R=1e-12)
+    ctx = fse().fse_init_torus(s, tr)
+    Z, om, steps, it, rn = fse().fse_arclength(ctx, om0, Z0, 0.15, 26, tol=1e-12, maxit=8)
+    log(f"omega_1 along the path {np.round(om[:, 0], 4).tolist()}")
+    log(f"corrections {it.tolist()}")
+    assert np.all(rn < 1e-12)
+    _compare_paths(Z, om, steps, it, path)
+    dp = np.diff(om[:, 0])
+    assert np.count_nonzero(np.sign(dp[1:]) != np.sign(dp[:-1])) == 2
+
+
+def test_arclength_quasi_periodic_d2_matches_oracle():
+    """3-DOF system, d = e = 2 (forcing ratio the golden mean): six points of the
+    quasi-periodic branch in omega_1, GPU against the oracle."""
+    s = tiny_system(n=3, seed=2, cubic=1.0, quad=0.3, e=2)
+    tr = Torus(d=2, e=2, K=[np.arange(1, 6)], S=[16], S1=64)
+    tb = osh.TorusTables(tr)
+    om0 = np.array([0.45, 0.45 * GOLDEN])
+    Z0, _, _ = osh.solve(s, tr, om0, np.zeros((6, tb.U)), tol_R=1e-13, tables=tb)
+    path = ocont.arclength(s, tr, om0, Z0, 0.05, 6, tables=tb, tol_R=1e-12)
+    ctx = fse().fse_init_torus(s, tr)
+    Z, om, steps, it, rn = fse().fse_arclength(ctx, om0, Z0, 0.05, 6, tol=1e-12, maxit=8)
+    log(f"omega along the path {np.round(om, 5).tolist()}; corrections {it.tolist()}")
+    assert np.all(rn < 1e-12)
+    assert np.allclose(om[:, 1] / om[:, 0], GOLDEN, rtol=1e-15)
+    _compare_paths(Z, om, steps, it, path)
+
+
+def test_arclength_error_paths():
+    s = duffing()
+    tr = Torus(d=1, e=1, K=[], S=[], S1=64)
+    ctx = fse().fse_init_torus(s, tr)
+    with pytest.raises(fse().FseError, match="FSE_E_INVAL"):
+        fse().fse_arclength(ctx, np.array([0.6]), np.zeros((2, 1)), 0.0, 3)
+    # a start far from any solution with no corrections allowed fails at point 0
+    with pytest.raises(fse().FseError) as ex:
+        fse().fse_arclength(ctx, np.array([0.6]), np.full((2, 1), 5.0), 0.1, 3, tol=1e-12, maxit=0)
+    assert ex.value.iters[0] == -1
