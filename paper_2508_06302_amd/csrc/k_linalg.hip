@@ -85,6 +85,119 @@ __global__ __launch_bounds__(1024) void k_lu_leaf(double *__restrict__ B, int N,
   }
 }
 
+// The same leaf with the panel held in registers: thread t owns rows j0 + t + 1024 r
+// (r < RPT) of the NB columns, so each column costs one block reduction for the pivot and one
+// exchange of the pivot row and row j through LDS, and the rank-1 update never leaves the
+// registers.  Pivots and arithmetic are those of k_lu_leaf.  Needs N - j0 <= 1024 RPT.
+template <int NB, int RPT>
+__global__ __launch_bounds__(1024) void k_lu_leaf_reg(double *__restrict__ B, int N, int j0, int nb,
+                                                      int32_t *__restrict__ piv, DevStatus *st) {
+  constexpr int NT = 1024;
+  __shared__ double sv[NT / 64];
+  __shared__ int si[NT / 64];
+  __shared__ double prow[NB], jrow[NB];
+  __shared__ int piv_s;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double v[RPT][NB];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = j0 + tid + r * NT;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) v[r][c] = (i < N && c < nb) ? B[(size_t)(j0 + c) * N + i] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c >= nb) break;
+    const int j = j0 + c;
+    double best = -1.0;
+    int bi = j;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = j0 + tid + r * NT;
+      const double a = fabs(v[r][c]);
+      if (i >= j && i < N && a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      sv[wid] = best;
+      si[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = sv[0];
+      int ix = si[0];
+      for (int w = 1; w < NT / 64; ++w)
+        if (sv[w] > b || (sv[w] == b && si[w] < ix)) {
+          b = sv[w];
+          ix = si[w];
+        }
+      piv_s = ix;
+      piv[j] = ix;
+      if (!(b > 0.0) || !isfinite(b)) atomicOr(&st->flags, (int)DEV_SINGULAR);
+    }
+    __syncthreads();
+    const int p = piv_s;
+    const int tp = (p - j0) % NT, rp = (p - j0) / NT;  // owner of row p; row j is thread c, slot 0
+    if (tid == tp) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (r == rp) {
+#pragma unroll
+          for (int c2 = 0; c2 < NB; ++c2) prow[c2] = v[r][c2];
+        }
+    }
+    if (tid == c) {
+#pragma unroll
+      for (int c2 = 0; c2 < NB; ++c2) jrow[c2] = v[0][c2];
+    }
+    __syncthreads();
+    if (p != j) {
+      if (tid == c) {
+#pragma unroll
+        for (int c2 = 0; c2 < NB; ++c2) v[0][c2] = prow[c2];
+      }
+      if (tid == tp) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (r == rp) {
+#pragma unroll
+            for (int c2 = 0; c2 < NB; ++c2) v[r][c2] = jrow[c2];
+          }
+      }
+    }
+    const double inv = 1.0 / prow[c];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = j0 + tid + r * NT;
+      if (i > j && i < N) {
+        const double l = v[r][c] * inv;
+        v[r][c] = l;
+#pragma unroll
+        for (int c2 = c + 1; c2 < NB; ++c2) v[r][c2] -= l * prow[c2];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = j0 + tid + r * NT;
+    if (i >= N) continue;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) B[(size_t)(j0 + c) * N + i] = v[r][c];
+  }
+}
+
 // Interchanges piv[k0..k1) applied in order to the columns [c0, c1) of B.
 __global__ void k_lu_swap(double *__restrict__ B, int N, int c0, int c1, int k0, int k1,
                           const int32_t *__restrict__ piv) {
@@ -380,14 +493,37 @@ void lu_trsm(fse_ctx *ctx, double *B, int N, int j0, int nb, int c0, int nc) {
   hipLaunchKernelGGL(k_lu_trsm, dim3((nc + 3) / 4), dim3(256), 0, ctx->stream, B, N, j0, nb, c0, nc);
 }
 
-// Recursive panel B[j0:N, j0:j0+nb], nb <= kLuBlock.
-void lu_panel(fse_ctx *ctx, double *B, int N, int j0, int nb) {
-  if (nb <= kLuLeaf) {
+// Leaf width for a panel of m rows: as wide as the register-resident leaf holds
+// (1024 threads x RPT rows x NB columns), else kLuLeaf with the panel in global memory.
+constexpr int kRegRows8 = 5, kRegRows4 = 9;
+
+int leaf_width(int m) {
+  if (m <= 1024 * kRegRows8) return 8;
+  if (m <= 1024 * kRegRows4) return 4;
+  return kLuLeaf;
+}
+
+void lu_leaf(fse_ctx *ctx, double *B, int N, int j0, int nb) {
+  const int m = N - j0;
+  if (nb <= 8 && m <= 1024 * kRegRows8)
+    hipLaunchKernelGGL((k_lu_leaf_reg<8, kRegRows8>), dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb,
+                       ctx->piv_d, ctx->status_d);
+  else if (nb <= 4 && m <= 1024 * kRegRows4)
+    hipLaunchKernelGGL((k_lu_leaf_reg<4, kRegRows4>), dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb,
+                       ctx->piv_d, ctx->status_d);
+  else
     hipLaunchKernelGGL(k_lu_leaf, dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb, ctx->piv_d,
                        ctx->status_d);
+}
+
+// Recursive panel B[j0:N, j0:j0+nb], nb <= kLuBlock.
+void lu_panel(fse_ctx *ctx, double *B, int N, int j0, int nb) {
+  const int lw = leaf_width(N - j0);
+  if (nb <= lw) {
+    lu_leaf(ctx, B, N, j0, nb);
     return;
   }
-  const int n1 = ((nb / 2 + kLuLeaf - 1) / kLuLeaf) * kLuLeaf, n2 = nb - n1;
+  const int n1 = ((nb / 2 + lw - 1) / lw) * lw, n2 = nb - n1;
   lu_panel(ctx, B, N, j0, n1);
   lu_swap(ctx, B, N, j0 + n1, j0 + nb, j0, j0 + n1);
   lu_trsm(ctx, B, N, j0, n1, j0 + n1, n2);

@@ -207,6 +207,29 @@ def test_newton_step_ragged_lu():
     assert rel(Zg.cpu().numpy() - Z0, Zo - Z0) < 1e-9
 
 
+def test_c2_newton_step_solves_its_linearisation():
+    """Full-size beam (N = 9114 unknowns): the LU runs its register-resident leaves of 8
+    (panels of <= 5120 rows) and of 4 columns (<= 9216 rows).  The Newton update dZ must
+    satisfy R + J dZ = 0 with the J and R of the same point (J applied on the host)."""
+    import torch
+    wl = workload("C2")
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    U, St, bw, kt = fse().fse_get_layout(ctx)
+    fse().fse_set_forcing(ctx, [0.3, 0.3])
+    Z0 = torch.tensor(wl.initial_iterate(kt) * 0.3, dtype=torch.float64, device="cuda")
+    R, rn, J = fse().fse_shooting_residual_jacobian(ctx, wl.omega[None], Z0[None], want_J=True)
+    Rh = R[0].cpu().numpy().ravel()
+    Jh = J[0].cpu().numpy()
+    del J
+    Zg = Z0.clone()
+    rn2 = fse().fse_newton_step(ctx, wl.omega.copy(), Zg)
+    assert abs(rn2 - rn[0]) <= 1e-14 * rn[0]
+    dZ = (Zg - Z0).cpu().numpy().ravel()
+    lin = np.linalg.norm(Rh + Jh @ dZ) / np.linalg.norm(Rh)
+    log(f"C2 Newton step: ||R|| {rn[0]:.3e}, ||R + J dZ|| / ||R|| {lin:.2e}")
+    assert lin < 1e-10
+
+
 def test_secant_predict_matches_oracle():
     from oracle import learned as olearn
     s, tr, tb, om, Z0 = _tiny_case()
