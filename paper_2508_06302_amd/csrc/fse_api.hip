@@ -137,6 +137,8 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   ctx->maxit = desc->step_maxit > 0 ? desc->step_maxit : 30;
   // FSE_KERNELS=fused|generic selects the trajectory kernels (tests cover both paths)
   if (const char *kv = std::getenv("FSE_KERNELS")) ctx->use_fused = std::strcmp(kv, "generic") != 0;
+  // FSE_WSENS=generic keeps the omega_1 sensitivity on the generic replay kernel
+  if (const char *kv = std::getenv("FSE_WSENS")) ctx->wsens_generic = std::strcmp(kv, "generic") == 0;
   if (const char *nc = std::getenv("FSE_FUSED_NCW")) {
     ctx->fused_ncw = std::max(1, std::atoi(nc));
     ctx->ncw_autotune = false;
@@ -389,7 +391,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)

@@ -108,10 +108,13 @@ struct fse_ctx {
   size_t Jw_elems = 0;
   // omega_1 derivative (arclength continuation)
   bool want_qhist = false;          // the next integration writes the displacement history
+  bool wsens_generic = false;       // omega_1 sensitivity by the generic replay kernel
   double *dzw = nullptr;            // [2n][Wmax] d zbar(2 pi) / d omega_1
   double *zeros_d = nullptr;        // [Bmax][2n][U] zeros
-  double *arc = nullptr;            // arclength vectors, 5 x (2nU + d - e + 1)
+  double *arc = nullptr;            // arclength vectors, 6 x (2nU + d - e + 1)
   size_t arc_elems = 0;
+  double *wfac = nullptr;           // factors of T(q_{k+1}) for every step and trajectory
+  size_t wfac_elems = 0;
 
   // packed tensors for LDS staging: t2 (j | k << 16), t3 (j | k << 16, l)
   uint32_t *f2_pk = nullptr, *f3_pk = nullptr;
@@ -156,6 +159,9 @@ fse_status launch_set_pcol(fse_ctx *ctx, double *A, size_t ldA, const double *co
 // Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16
 bool fused_supported(const fse_ctx *ctx);
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);
+// omega_1 sensitivity with the fused kernel's per-point bands (after a fused integration);
+// FSE_E_UNSUPPORTED when the generic replay must be used
+fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT);
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 fse_status launch_axpby(fse_ctx *ctx, int N, double a, const double *x, double b, const double *z, double *y);

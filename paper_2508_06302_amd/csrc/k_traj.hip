@@ -955,6 +955,8 @@ __global__ void k_set_pcol(double *__restrict__ A, size_t ldA, int N, int nu, co
 }
 
 fse_status launch_wsens(fse_ctx *ctx, int B, double *dzT) {
+  const fse_status fs = ctx->wsens_generic ? FSE_E_UNSUPPORTED : launch_wsens_fused(ctx, B, dzT);
+  if (fs != FSE_E_UNSUPPORTED) return fs;
   const TrajParams P = params(ctx, B);
   const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 8 * (size_t)ctx->n + 80;
   const size_t bytes = elems * sizeof(double);

@@ -47,12 +47,15 @@ def _case(d, e, n=3, seed=2):
     return s, tr, tb, om, Z0
 
 
-@pytest.mark.parametrize("kernels", ["fused", "generic"])
+@pytest.mark.parametrize("kernels,wsens", [("fused", "fused"), ("fused", "generic"), ("generic", "generic")])
 @pytest.mark.parametrize("d,e", [(2, 2), (2, 1), (3, 2), (3, 3)])
-def test_residual_dp_matches_oracle(d, e, kernels, monkeypatch):
+def test_residual_dp_matches_oracle(d, e, kernels, wsens, monkeypatch):
+    """Trajectory kernels fused or generic; the omega_1 column by the factor-all-steps +
+    staged-solve pair (fused) or by the generic replay."""
     monkeypatch.setenv("FSE_KERNELS", kernels)
+    monkeypatch.setenv("FSE_WSENS", wsens)
     s, tr, tb, om, Z0 = _case(d, e)
-    log(f"dR/dp d={d} e={e} kernels={kernels}")
+    log(f"dR/dp d={d} e={e} kernels={kernels} omega_1 column={wsens}")
     ref = osh.evaluate(s, tr, om, Z0, omega_sens=True, tables=tb)
     dref = ocont.residual_dp(ref, om, e)
     ctx = fse().fse_init_torus(s, tr)
