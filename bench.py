@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ARC_POINTS = 10
+ARC_DS = 0.5
 
 
 def parse():
@@ -103,9 +105,14 @@ def cpu_baseline(wl, Z0, tables, budget_s=20.0):
                       f"full {wl.torus.S1}-step integration with sensitivities, {el:.1f} s"}
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_precision(fse, torch, wl, prec, steps, warmup, solve):
     """Throughput of the residual + Jacobian step and the continuation solve in one
     precision mode; returns a dict (kernel times from HIP events on the library stream)."""
+    progress(f"precision {prec}: {warmup} warmup + {steps} timed steps")
     tr = wl.torus
     ctx = fse.fse_init_torus(wl.system, tr, precision=prec)
     U, St, bw, kt = fse.fse_get_layout(ctx)
@@ -132,6 +139,7 @@ def run_precision(fse, torch, wl, prec, steps, warmup, solve):
            "tuning": {"column_waves_per_workgroup": ncw, "tuned_launch_ms": [float(x) for x in tune_ms]},
            "value": St * tr.S1 / (el / steps), "kernel_ms": float(np.mean(kern_ms)),
            "fused": tm["sens_launches"] == 1 and tm["sens_ms"] < 0.05 * tm["state_ms"]}
+    progress(f"precision {prec}: {res['ms_per_step']:.1f} ms per step")
     if solve:
         # shooting solve: natural-parameter continuation in the forcing amplitude
         # f1 = f2 = 0.1 ... 0.5 N at the same omega, secant predictor, ||R||_2 < 1e-8 per point
@@ -149,6 +157,27 @@ def run_precision(fse, torch, wl, prec, steps, warmup, solve):
                         "newton_iterations": [int(i) for i in its],
                         "final_residuals": [float(r) for r in rns], "converged": ok is True}
         res["Z_solution"] = Zs[-1].clone() if ok is True else None
+        progress(f"precision {prec}: amplitude continuation {res['solve']['time_s']:.1f} s")
+        if ok is True:
+            # pseudo-arclength continuation in omega_1 (tangent predictor, orthogonal
+            # corrector) from the 0.3 N torus: ARC_POINTS points, step ARC_DS in the 2-norm of
+            # [Z(0); omega_1], ||R||_2 < 1e-8 per point
+            fse.fse_set_forcing(ctx, [amps[2]] * wl.system.e)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            try:
+                _, oms, steps, cits, crn = fse.fse_arclength(ctx, wl.omega, Zs[2], ARC_DS, ARC_POINTS,
+                                                             tol=1e-8, maxit=8)
+                aok = True
+            except fse.FseError as ex:
+                oms, steps, cits, crn, aok = ex.omega, ex.steps, ex.iters, ex.rnorm, str(ex)
+            torch.cuda.synchronize()
+            el2 = time.perf_counter() - t2
+            progress(f"precision {prec}: arclength {el2:.1f} s")
+            res["arclength"] = {"time_s": el2, "points": ARC_POINTS, "s_per_point": el2 / ARC_POINTS,
+                                "corrections": [int(i) for i in cits],
+                                "omega1": [float(o[0]) for o in oms], "final_residuals": [float(r) for r in crn],
+                                "converged": aok is True}
         fse.fse_set_forcing(ctx, [1.0] * wl.system.e)
     return res
 
@@ -205,6 +234,13 @@ def main():
     if solve:
         path = "forcing amplitude 0.1 -> 0.5 N in 5 points from the linear response at 0.1 N, secant predictor"
         out["shooting_solve"] = {"path": path, "fp64": plain["solve"]}
+        if "arclength" in plain:
+            out["arclength_continuation"] = {
+                "path": f"omega_1 from {wl.omega[0]:g} rad/s at 0.3 N, {ARC_POINTS} points, step {ARC_DS} "
+                        "(2-norm of [Z(0); omega_1]), tangent predictor and orthogonal corrector",
+                "fp64": plain["arclength"]}
+            if mixed is not None and "arclength" in mixed:
+                out["arclength_continuation"]["mixed"] = mixed["arclength"]
         if mixed is not None:
             out["shooting_solve"]["mixed"] = mixed["solve"]
             zp, zm = plain.get("Z_solution"), mixed.get("Z_solution")
@@ -213,6 +249,7 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import shooting as osh
         tb = osh.TorusTables(tr)
+        progress("oracle on the host cores (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(wl, Z0, tb)
     print(json.dumps(out), flush=True)
 

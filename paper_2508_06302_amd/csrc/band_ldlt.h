@@ -1,0 +1,344 @@
+// Banded LDL^T kernels-in-a-lane shared by the trajectory kernels (App. E, Eqs. E6-E9):
+// the tangent T = S + K_t(q) assembled in LDS from the sparse polynomial forces, its
+// factorisation and solves by one lane with register windows.  Every translation unit that
+// includes this header gets its own copies (anonymous namespace).
+//
+// Padded LDL^T storage [n+BW][BW+1]: entry (j + r, j) at [BW + j][r], [BW + j][0] = 1 / d_j;
+// the BW leading rows are zero so sweeps need no guards.  Full rows [n][2BW+1]: entry (i, j)
+// at [i][j - i + BW].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace {
+
+// Order LDS traffic between the lanes of one wave (LDS operations of a wave are
+// executed in issue order; this keeps the compiler from reordering across it).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Polynomial forces staged in LDS: row pointers, packed indices and values.
+struct TensLds {
+  const int *p2, *p3;
+  const uint32_t *i2, *i3;
+  const double *v2, *v3;
+};
+
+// f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l over row i (four partial sums)
+__device__ inline double fnl_row(const TensLds &t, const double *q, int i) {
+  double f[4] = {0.0, 0.0, 0.0, 0.0};
+  const int a0 = t.p2[i], a1 = t.p2[i + 1];
+  int p = a0;
+  for (; p + 3 < a1; p += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t x = t.i2[p + u];
+      f[u] += t.v2[p + u] * q[x & 0xffff] * q[x >> 16];
+    }
+  }
+  for (; p < a1; ++p) {
+    const uint32_t x = t.i2[p];
+    f[0] += t.v2[p] * q[x & 0xffff] * q[x >> 16];
+  }
+  const int b0 = t.p3[i], b1 = t.p3[i + 1];
+  p = b0;
+  for (; p + 3 < b1; p += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t x = t.i3[2 * (p + u)], xl = t.i3[2 * (p + u) + 1];
+      f[u] += t.v3[p + u] * q[x & 0xffff] * q[x >> 16] * q[xl];
+    }
+  }
+  for (; p < b1; ++p) {
+    const uint32_t x = t.i3[2 * p], xl = t.i3[2 * p + 1];
+    f[1] += t.v3[p] * q[x & 0xffff] * q[x >> 16] * q[xl];
+  }
+  return (f[0] + f[1]) + (f[2] + f[3]);
+}
+
+// Lower band of T = S + K_t(q) into F (padded column storage), lanes of one wave over
+// rows: the lane of row i owns the entries (i, i - r), so no two lanes write the same
+// word.  K_t(i, m) = d f_i / d q_m collects the terms of row i whose index set holds m
+// (entries with m > i are the transposes of lower entries of a symmetric tangent).
+template <int BW>
+__device__ void assemble_T(const TensLds &t, int n, const double *__restrict__ Sp, const double *q,
+                           double *Fp, int lane) {
+  constexpr int bp = BW + 1, W2 = 2 * BW + 1;
+  double *F = Fp + BW * bp;
+  for (int i = lane; i < n; i += 64) {
+#pragma unroll
+    for (int r = 0; r <= BW; ++r) {
+      const int m = i - r;
+      if (m >= 0) F[m * bp + r] = Sp[(size_t)i * W2 + (BW - r)];
+    }
+    for (int p = t.p2[i]; p < t.p2[i + 1]; ++p) {
+      const uint32_t x = t.i2[p];
+      const int j = x & 0xffff, k = x >> 16;
+      const double v = t.v2[p];
+      if (j <= i) F[j * bp + (i - j)] += v * q[k];
+      if (k <= i) F[k * bp + (i - k)] += v * q[j];
+    }
+    for (int p = t.p3[i]; p < t.p3[i + 1]; ++p) {
+      const uint32_t x = t.i3[2 * p];
+      const int j = x & 0xffff, k = x >> 16, l = t.i3[2 * p + 1];
+      const double v = t.v3[p];
+      if (j <= i) F[j * bp + (i - j)] += v * q[k] * q[l];
+      if (k <= i) F[k * bp + (i - k)] += v * q[j] * q[l];
+      if (l <= i) F[l * bp + (i - l)] += v * q[j] * q[k];
+    }
+  }
+}
+
+// In-place banded LDL^T by one lane with a register window (padded storage, see
+// file header).  Returns false on a zero or non-finite pivot.
+template <int BW>
+__device__ bool ldlt_serial_shift(double *Fp, int n) {
+  constexpr int bp = BW + 1;
+  double *F = Fp + BW * bp;
+  double Wn[BW + 1][BW + 1];
+#pragma unroll
+  for (int r = 0; r <= BW; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) Wn[r][c] = (r < n) ? F[c * bp + (r - c)] : 0.0;
+  bool ok = true;
+  for (int j = 0; j < n; ++j) {
+    const double d = Wn[0][0];
+    ok = ok && (d != 0.0) && isfinite(d);
+    // reciprocal: hardware estimate refined by one Newton step (relative error ~1 ulp)
+    double inv = __builtin_amdgcn_rcp(d);
+    inv = fma(inv, fma(-d, inv, 1.0), inv);
+    double l[BW + 1];
+#pragma unroll
+    for (int r = 1; r <= BW; ++r) l[r] = Wn[r][0] * inv;
+    F[j * bp] = inv;
+#pragma unroll
+    for (int r = 1; r <= BW; ++r) F[j * bp + r] = (j + r < n) ? l[r] : 0.0;
+#pragma unroll
+    for (int r = 1; r <= BW; ++r)
+#pragma unroll
+      for (int c = 1; c <= r; ++c) Wn[r][c] -= Wn[r][0] * l[c];
+#pragma unroll
+    for (int r = 0; r < BW; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c) Wn[r][c] = Wn[r + 1][c + 1];
+    const bool in = j + 1 + BW < n;
+#pragma unroll
+    for (int c = 0; c <= BW; ++c) Wn[BW][c] = in ? F[(j + 1 + c) * bp + (BW - c)] : 0.0;
+  }
+  return ok;
+}
+
+// Solve (L D L^T) x = x in place by one lane.  The coefficients of the next row
+// are loaded while the current row is reduced, and the term with the most recent
+// unknown is applied last, so each row adds one dependent FMA to the critical path.
+template <int BW>
+__device__ void ldlt_solve_shift(const double *Fp, int n, double *x) {
+  constexpr int bp = BW + 1;
+  const double *F = Fp + BW * bp;
+  double yw[BW], cf[BW + 1], cn[BW + 1];
+#pragma unroll
+  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+#pragma unroll
+  for (int t = 1; t <= BW; ++t) cf[t] = F[(0 - t) * bp + t];
+  double xn = x[0];
+  for (int i = 0; i < n; ++i) {
+    const double xi = xn;
+    const int i1 = i + 1 < n ? i + 1 : i;
+#pragma unroll
+    for (int t = 1; t <= BW; ++t) cn[t] = F[(i1 - t) * bp + t];
+    xn = x[i1];
+    // older terms in two independent partial sums, off the critical path
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = BW; t >= 2; --t) {
+      if ((t & 1) == 0)
+        s0 += cf[t] * yw[t - 1];
+      else
+        s1 += cf[t] * yw[t - 1];
+    }
+    const double acc = (xi - (s0 + s1)) - cf[1] * yw[0];
+#pragma unroll
+    for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
+    yw[0] = acc;
+    x[i] = acc;
+#pragma unroll
+    for (int t = 1; t <= BW; ++t) cf[t] = cn[t];
+  }
+#pragma unroll
+  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t <= BW; ++t) cf[t] = F[(n - 1) * bp + t];
+  xn = x[n - 1];
+  for (int i = n - 1; i >= 0; --i) {
+    const double xi = xn;
+    const int i1 = i > 0 ? i - 1 : 0;
+#pragma unroll
+    for (int t = 0; t <= BW; ++t) cn[t] = F[i1 * bp + t];
+    xn = x[i1];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int t = BW; t >= 2; --t) {
+      if ((t & 1) == 0)
+        s0 += cf[t] * yw[t - 1];
+      else
+        s1 += cf[t] * yw[t - 1];
+    }
+    const double acc = (xi * cf[0] - (s0 + s1)) - cf[1] * yw[0];
+#pragma unroll
+    for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
+    yw[0] = acc;
+    x[i] = acc;
+#pragma unroll
+    for (int t = 0; t <= BW; ++t) cf[t] = cn[t];
+  }
+}
+
+// Register-ring variants for half bandwidths up to 6 (P = BW + 1 slots).
+// Factorisation: entry A(R, C) of the active window lives in G[R % P][C % P]; with the
+// column loop unrolled by P every slot index is a compile-time constant, so the window
+// never moves between registers.  The row entering the window after column j (row
+// j + P) is loaded at the end of column j, one column ahead of its first use.
+template <int BW>
+__device__ bool ldlt_serial_ring(double *Fp, int n) {
+  constexpr int P = BW + 1, bp = BW + 1;
+  double *F = Fp + BW * bp;
+  double G[P][P];
+#pragma unroll
+  for (int r = 0; r < P; ++r)
+#pragma unroll
+    for (int c = 0; c < P; ++c) G[r][c] = (c <= r && r < n) ? F[c * bp + (r - c)] : 0.0;
+  bool ok = true;
+  for (int j0 = 0; j0 < n; j0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int j = j0 + u;
+      if (j >= n) break;
+      const double d = G[u][u];
+      ok = ok && (d != 0.0) && isfinite(d);
+      // reciprocal: hardware estimate refined by one Newton step
+      double inv = __builtin_amdgcn_rcp(d);
+      inv = fma(inv, fma(-d, inv, 1.0), inv);
+      double l[P];
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) l[t] = G[(u + t) % P][u] * inv;
+      F[j * bp] = inv;
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) F[j * bp + t] = l[t];
+#pragma unroll
+      for (int r = 1; r <= BW; ++r)
+#pragma unroll
+        for (int c = 1; c <= r; ++c) G[(u + r) % P][(u + c) % P] -= G[(u + r) % P][u] * l[c];
+      // row R = j + P enters slot u: A(R, C) for C = j + 1 .. j + P
+      const int R = j + P;
+      const bool in = R < n;
+#pragma unroll
+      for (int c = 0; c <= BW; ++c) {
+        const int C = j + 1 + c;
+        G[u][(u + 1 + c) % P] = in ? F[C * bp + (R - C)] : 0.0;
+      }
+    }
+  }
+  return ok;
+}
+
+// Solve (L D L^T) x = x in place by one lane; step k of each sweep keeps its result in
+// slot k % P of a register ring and the coefficients of step k + P are loaded when step
+// k retires, P steps before they are needed.  The term of the newest unknown is
+// applied last, so each row adds one dependent FMA to the critical path.
+template <int BW>
+__device__ void ldlt_solve_ring(const double *Fp, int n, double *x) {
+  constexpr int P = BW + 1, bp = BW + 1;
+  const double *F = Fp + BW * bp;
+  double y[P], cf[P][P], xv[P];
+  // forward: row i = k, coefficients L(i, i - t) = F[(i - t) bp + t]
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int ir = u < n ? u : n - 1;
+    y[u] = 0.0;
+    xv[u] = x[ir];
+#pragma unroll
+    for (int t = 1; t <= BW; ++t) cf[u][t] = F[(ir - t) * bp + t];
+  }
+  for (int k0 = 0; k0 < n; k0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int i = k0 + u;
+      if (i >= n) break;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = BW; t >= 2; --t) {
+        if ((t & 1) == 0)
+          s0 += cf[u][t] * y[(u - t + P) % P];
+        else
+          s1 += cf[u][t] * y[(u - t + P) % P];
+      }
+      const double acc = (xv[u] - (s0 + s1)) - cf[u][1] * y[(u - 1 + P) % P];
+      y[u] = acc;
+      x[i] = acc;
+      const int ir = i + P < n ? i + P : n - 1;
+      xv[u] = x[ir];
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) cf[u][t] = F[(ir - t) * bp + t];
+    }
+  }
+  // backward: row i = n - 1 - k, coefficients D^-1 = F[i bp], L(i + t, i) = F[i bp + t]
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    const int ir = n - 1 - u >= 0 ? n - 1 - u : 0;
+    y[u] = 0.0;
+    xv[u] = x[ir];
+#pragma unroll
+    for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
+  }
+  for (int k0 = 0; k0 < n; k0 += P) {
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int k = k0 + u;
+      if (k >= n) break;
+      const int i = n - 1 - k;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int t = BW; t >= 2; --t) {
+        if ((t & 1) == 0)
+          s0 += cf[u][t] * y[(u - t + P) % P];
+        else
+          s1 += cf[u][t] * y[(u - t + P) % P];
+      }
+      const double acc = (xv[u] * cf[u][0] - (s0 + s1)) - cf[u][1] * y[(u - 1 + P) % P];
+      y[u] = acc;
+      x[i] = acc;
+      const int ir = i - P >= 0 ? i - P : 0;
+      xv[u] = x[ir];
+#pragma unroll
+      for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
+    }
+  }
+}
+
+template <int BW>
+__device__ bool ldlt_serial(double *Fp, int n) {
+  if constexpr (BW <= 6)
+    return ldlt_serial_ring<BW>(Fp, n);
+  else
+    return ldlt_serial_shift<BW>(Fp, n);
+}
+
+template <int BW>
+__device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
+  if constexpr (BW <= 6)
+    ldlt_solve_ring<BW>(Fp, n, x);
+  else
+    ldlt_solve_shift<BW>(Fp, n, x);
+}
+
+}  // namespace

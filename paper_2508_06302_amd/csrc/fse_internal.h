@@ -159,8 +159,10 @@ fse_status launch_set_pcol(fse_ctx *ctx, double *A, size_t ldA, const double *co
 // Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16
 bool fused_supported(const fse_ctx *ctx);
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);
-// omega_1 sensitivity with the fused kernel's per-point bands (after a fused integration);
-// FSE_E_UNSUPPORTED when the generic replay must be used
+// compile-time half bandwidth (4, 6, 8, 12 or 16) the fused kernels use for this system
+int fused_band_bucket(const fse_ctx *ctx);
+// omega_1 sensitivity with the fused kernel's per-point bands (after a fused integration,
+// k_wsens.hip); FSE_E_UNSUPPORTED when the generic replay must be used
 fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT);
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);

@@ -32,24 +32,12 @@
 #include <type_traits>
 #include <cmath>
 
+#include "band_ldlt.h"
 #include "fse_internal.h"
 
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-
-// Order LDS traffic between the lanes of one wave (LDS operations of a wave are
-// executed in issue order; this keeps the compiler from reordering across it).
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ inline double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
 
 struct FusedArgs {
   TrajParams P;
@@ -72,320 +60,6 @@ struct FusedArgs {
   size_t colQ_ws, colU_ws, colA_ws, colY_ws;  // element stride between trajectories
   DevStatus *st;
 };
-
-// Polynomial forces staged in LDS: row pointers, packed indices and values.
-struct TensLds {
-  const int *p2, *p3;
-  const uint32_t *i2, *i3;
-  const double *v2, *v3;
-};
-
-// f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l over row i (four partial sums)
-__device__ inline double fnl_row(const TensLds &t, const double *q, int i) {
-  double f[4] = {0.0, 0.0, 0.0, 0.0};
-  const int a0 = t.p2[i], a1 = t.p2[i + 1];
-  int p = a0;
-  for (; p + 3 < a1; p += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t x = t.i2[p + u];
-      f[u] += t.v2[p + u] * q[x & 0xffff] * q[x >> 16];
-    }
-  }
-  for (; p < a1; ++p) {
-    const uint32_t x = t.i2[p];
-    f[0] += t.v2[p] * q[x & 0xffff] * q[x >> 16];
-  }
-  const int b0 = t.p3[i], b1 = t.p3[i + 1];
-  p = b0;
-  for (; p + 3 < b1; p += 4) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t x = t.i3[2 * (p + u)], xl = t.i3[2 * (p + u) + 1];
-      f[u] += t.v3[p + u] * q[x & 0xffff] * q[x >> 16] * q[xl];
-    }
-  }
-  for (; p < b1; ++p) {
-    const uint32_t x = t.i3[2 * p], xl = t.i3[2 * p + 1];
-    f[1] += t.v3[p] * q[x & 0xffff] * q[x >> 16] * q[xl];
-  }
-  return (f[0] + f[1]) + (f[2] + f[3]);
-}
-
-// Lower band of T = S + K_t(q) into F (padded column storage), lanes of one wave over
-// rows: the lane of row i owns the entries (i, i - r), so no two lanes write the same
-// word.  K_t(i, m) = d f_i / d q_m collects the terms of row i whose index set holds m
-// (entries with m > i are the transposes of lower entries of a symmetric tangent).
-template <int BW>
-__device__ void assemble_T(const TensLds &t, int n, const double *__restrict__ Sp, const double *q,
-                           double *Fp, int lane) {
-  constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  double *F = Fp + BW * bp;
-  for (int i = lane; i < n; i += 64) {
-#pragma unroll
-    for (int r = 0; r <= BW; ++r) {
-      const int m = i - r;
-      if (m >= 0) F[m * bp + r] = Sp[(size_t)i * W2 + (BW - r)];
-    }
-    for (int p = t.p2[i]; p < t.p2[i + 1]; ++p) {
-      const uint32_t x = t.i2[p];
-      const int j = x & 0xffff, k = x >> 16;
-      const double v = t.v2[p];
-      if (j <= i) F[j * bp + (i - j)] += v * q[k];
-      if (k <= i) F[k * bp + (i - k)] += v * q[j];
-    }
-    for (int p = t.p3[i]; p < t.p3[i + 1]; ++p) {
-      const uint32_t x = t.i3[2 * p];
-      const int j = x & 0xffff, k = x >> 16, l = t.i3[2 * p + 1];
-      const double v = t.v3[p];
-      if (j <= i) F[j * bp + (i - j)] += v * q[k] * q[l];
-      if (k <= i) F[k * bp + (i - k)] += v * q[j] * q[l];
-      if (l <= i) F[l * bp + (i - l)] += v * q[j] * q[k];
-    }
-  }
-}
-
-// In-place banded LDL^T by one lane with a register window (padded storage, see
-// file header).  Returns false on a zero or non-finite pivot.
-template <int BW>
-__device__ bool ldlt_serial_shift(double *Fp, int n) {
-  constexpr int bp = BW + 1;
-  double *F = Fp + BW * bp;
-  double Wn[BW + 1][BW + 1];
-#pragma unroll
-  for (int r = 0; r <= BW; ++r)
-#pragma unroll
-    for (int c = 0; c <= r; ++c) Wn[r][c] = (r < n) ? F[c * bp + (r - c)] : 0.0;
-  bool ok = true;
-  for (int j = 0; j < n; ++j) {
-    const double d = Wn[0][0];
-    ok = ok && (d != 0.0) && isfinite(d);
-    // reciprocal: hardware estimate refined by one Newton step (relative error ~1 ulp)
-    double inv = __builtin_amdgcn_rcp(d);
-    inv = fma(inv, fma(-d, inv, 1.0), inv);
-    double l[BW + 1];
-#pragma unroll
-    for (int r = 1; r <= BW; ++r) l[r] = Wn[r][0] * inv;
-    F[j * bp] = inv;
-#pragma unroll
-    for (int r = 1; r <= BW; ++r) F[j * bp + r] = (j + r < n) ? l[r] : 0.0;
-#pragma unroll
-    for (int r = 1; r <= BW; ++r)
-#pragma unroll
-      for (int c = 1; c <= r; ++c) Wn[r][c] -= Wn[r][0] * l[c];
-#pragma unroll
-    for (int r = 0; r < BW; ++r)
-#pragma unroll
-      for (int c = 0; c <= r; ++c) Wn[r][c] = Wn[r + 1][c + 1];
-    const bool in = j + 1 + BW < n;
-#pragma unroll
-    for (int c = 0; c <= BW; ++c) Wn[BW][c] = in ? F[(j + 1 + c) * bp + (BW - c)] : 0.0;
-  }
-  return ok;
-}
-
-// Solve (L D L^T) x = x in place by one lane.  The coefficients of the next row
-// are loaded while the current row is reduced, and the term with the most recent
-// unknown is applied last, so each row adds one dependent FMA to the critical path.
-template <int BW>
-__device__ void ldlt_solve_shift(const double *Fp, int n, double *x) {
-  constexpr int bp = BW + 1;
-  const double *F = Fp + BW * bp;
-  double yw[BW], cf[BW + 1], cn[BW + 1];
-#pragma unroll
-  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-#pragma unroll
-  for (int t = 1; t <= BW; ++t) cf[t] = F[(0 - t) * bp + t];
-  double xn = x[0];
-  for (int i = 0; i < n; ++i) {
-    const double xi = xn;
-    const int i1 = i + 1 < n ? i + 1 : i;
-#pragma unroll
-    for (int t = 1; t <= BW; ++t) cn[t] = F[(i1 - t) * bp + t];
-    xn = x[i1];
-    // older terms in two independent partial sums, off the critical path
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int t = BW; t >= 2; --t) {
-      if ((t & 1) == 0)
-        s0 += cf[t] * yw[t - 1];
-      else
-        s1 += cf[t] * yw[t - 1];
-    }
-    const double acc = (xi - (s0 + s1)) - cf[1] * yw[0];
-#pragma unroll
-    for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
-    yw[0] = acc;
-    x[i] = acc;
-#pragma unroll
-    for (int t = 1; t <= BW; ++t) cf[t] = cn[t];
-  }
-#pragma unroll
-  for (int t = 0; t < BW; ++t) yw[t] = 0.0;
-#pragma unroll
-  for (int t = 0; t <= BW; ++t) cf[t] = F[(n - 1) * bp + t];
-  xn = x[n - 1];
-  for (int i = n - 1; i >= 0; --i) {
-    const double xi = xn;
-    const int i1 = i > 0 ? i - 1 : 0;
-#pragma unroll
-    for (int t = 0; t <= BW; ++t) cn[t] = F[i1 * bp + t];
-    xn = x[i1];
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int t = BW; t >= 2; --t) {
-      if ((t & 1) == 0)
-        s0 += cf[t] * yw[t - 1];
-      else
-        s1 += cf[t] * yw[t - 1];
-    }
-    const double acc = (xi * cf[0] - (s0 + s1)) - cf[1] * yw[0];
-#pragma unroll
-    for (int t = BW - 1; t >= 1; --t) yw[t] = yw[t - 1];
-    yw[0] = acc;
-    x[i] = acc;
-#pragma unroll
-    for (int t = 0; t <= BW; ++t) cf[t] = cn[t];
-  }
-}
-
-// Register-ring variants for half bandwidths up to 6 (P = BW + 1 slots).
-// Factorisation: entry A(R, C) of the active window lives in G[R % P][C % P]; with the
-// column loop unrolled by P every slot index is a compile-time constant, so the window
-// never moves between registers.  The row entering the window after column j (row
-// j + P) is loaded at the end of column j, one column ahead of its first use.
-template <int BW>
-__device__ bool ldlt_serial_ring(double *Fp, int n) {
-  constexpr int P = BW + 1, bp = BW + 1;
-  double *F = Fp + BW * bp;
-  double G[P][P];
-#pragma unroll
-  for (int r = 0; r < P; ++r)
-#pragma unroll
-    for (int c = 0; c < P; ++c) G[r][c] = (c <= r && r < n) ? F[c * bp + (r - c)] : 0.0;
-  bool ok = true;
-  for (int j0 = 0; j0 < n; j0 += P) {
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      const int j = j0 + u;
-      if (j >= n) break;
-      const double d = G[u][u];
-      ok = ok && (d != 0.0) && isfinite(d);
-      // reciprocal: hardware estimate refined by one Newton step
-      double inv = __builtin_amdgcn_rcp(d);
-      inv = fma(inv, fma(-d, inv, 1.0), inv);
-      double l[P];
-#pragma unroll
-      for (int t = 1; t <= BW; ++t) l[t] = G[(u + t) % P][u] * inv;
-      F[j * bp] = inv;
-#pragma unroll
-      for (int t = 1; t <= BW; ++t) F[j * bp + t] = l[t];
-#pragma unroll
-      for (int r = 1; r <= BW; ++r)
-#pragma unroll
-        for (int c = 1; c <= r; ++c) G[(u + r) % P][(u + c) % P] -= G[(u + r) % P][u] * l[c];
-      // row R = j + P enters slot u: A(R, C) for C = j + 1 .. j + P
-      const int R = j + P;
-      const bool in = R < n;
-#pragma unroll
-      for (int c = 0; c <= BW; ++c) {
-        const int C = j + 1 + c;
-        G[u][(u + 1 + c) % P] = in ? F[C * bp + (R - C)] : 0.0;
-      }
-    }
-  }
-  return ok;
-}
-
-// Solve (L D L^T) x = x in place by one lane; step k of each sweep keeps its result in
-// slot k % P of a register ring and the coefficients of step k + P are loaded when step
-// k retires, P steps before they are needed.  The term of the newest unknown is
-// applied last, so each row adds one dependent FMA to the critical path.
-template <int BW>
-__device__ void ldlt_solve_ring(const double *Fp, int n, double *x) {
-  constexpr int P = BW + 1, bp = BW + 1;
-  const double *F = Fp + BW * bp;
-  double y[P], cf[P][P], xv[P];
-  // forward: row i = k, coefficients L(i, i - t) = F[(i - t) bp + t]
-#pragma unroll
-  for (int u = 0; u < P; ++u) {
-    const int ir = u < n ? u : n - 1;
-    y[u] = 0.0;
-    xv[u] = x[ir];
-#pragma unroll
-    for (int t = 1; t <= BW; ++t) cf[u][t] = F[(ir - t) * bp + t];
-  }
-  for (int k0 = 0; k0 < n; k0 += P) {
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      const int i = k0 + u;
-      if (i >= n) break;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int t = BW; t >= 2; --t) {
-        if ((t & 1) == 0)
-          s0 += cf[u][t] * y[(u - t + P) % P];
-        else
-          s1 += cf[u][t] * y[(u - t + P) % P];
-      }
-      const double acc = (xv[u] - (s0 + s1)) - cf[u][1] * y[(u - 1 + P) % P];
-      y[u] = acc;
-      x[i] = acc;
-      const int ir = i + P < n ? i + P : n - 1;
-      xv[u] = x[ir];
-#pragma unroll
-      for (int t = 1; t <= BW; ++t) cf[u][t] = F[(ir - t) * bp + t];
-    }
-  }
-  // backward: row i = n - 1 - k, coefficients D^-1 = F[i bp], L(i + t, i) = F[i bp + t]
-#pragma unroll
-  for (int u = 0; u < P; ++u) {
-    const int ir = n - 1 - u >= 0 ? n - 1 - u : 0;
-    y[u] = 0.0;
-    xv[u] = x[ir];
-#pragma unroll
-    for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
-  }
-  for (int k0 = 0; k0 < n; k0 += P) {
-#pragma unroll
-    for (int u = 0; u < P; ++u) {
-      const int k = k0 + u;
-      if (k >= n) break;
-      const int i = n - 1 - k;
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int t = BW; t >= 2; --t) {
-        if ((t & 1) == 0)
-          s0 += cf[u][t] * y[(u - t + P) % P];
-        else
-          s1 += cf[u][t] * y[(u - t + P) % P];
-      }
-      const double acc = (xv[u] * cf[u][0] - (s0 + s1)) - cf[u][1] * y[(u - 1 + P) % P];
-      y[u] = acc;
-      x[i] = acc;
-      const int ir = i - P >= 0 ? i - P : 0;
-      xv[u] = x[ir];
-#pragma unroll
-      for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
-    }
-  }
-}
-
-template <int BW>
-__device__ bool ldlt_serial(double *Fp, int n) {
-  if constexpr (BW <= 6)
-    return ldlt_serial_ring<BW>(Fp, n);
-  else
-    return ldlt_serial_shift<BW>(Fp, n);
-}
-
-template <int BW>
-__device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
-  if constexpr (BW <= 6)
-    ldlt_solve_ring<BW>(Fp, n, x);
-  else
-    ldlt_solve_shift<BW>(Fp, n, x);
-}
 
 // Per-point padded bands: S = w1^2 c0 M + w1 c2 D + K, w1^2 M, w1 D; and K itself.
 template <int BW>
@@ -923,205 +597,6 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
   }
 }
 
-// ---------------------------------------------------------------- omega_1 sensitivity
-// d zbar(2 pi) / d omega_1 at fixed forcing ratios (the recursion of k_wsens in k_traj.hip:
-// T Qw_{k+1} = w1^2 M (c0 Qw_k + c1 Uw_k + Aw_k) + w1 D (c2 Qw_k + Uw_k)
-//              - (2 w1 c0 M + c2 D) q_{k+1} + 2 w1 M (c0 q_k + c1 u_k + a_k) + D (c2 q_k + u_k)),
-// split in two for half bandwidths up to 16.  The factors of T(q_{k+1}) depend on the
-// stored trajectory only, so k_wfactor computes all of them at once, one wave per (step,
-// trajectory), and writes them to global memory; k_wsolve then runs the recursion, one
-// work-group per trajectory: wave 0 forms the right-hand side and solves step k while
-// wave 1 stages the factor and displacements of step k + 1 into the other LDS buffer.
-template <int BW>
-__global__ __launch_bounds__(64) void k_wfactor(TrajParams P, TensLds tl, const double *__restrict__ Sp_all,
-                                                const double *__restrict__ qhist, int ldw,
-                                                double *__restrict__ Fall, DevStatus *st) {
-  constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  extern __shared__ double smem[];
-  const int n = P.n, k = blockIdx.x, w = blockIdx.y, lane = threadIdx.x;
-  const int b = w / P.St;
-  const size_t fb = (size_t)(n + BW) * bp;
-  double *F = smem;
-  double *q = F + fb;
-  for (size_t e = lane; e < fb; e += 64) F[e] = 0.0;
-  for (int i = lane; i < n; i += 64) q[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
-  __syncthreads();
-  assemble_T<BW>(tl, n, Sp_all + (size_t)b * n * W2, q, F, lane);
-  __syncthreads();
-  if (lane == 0 && !ldlt_serial<BW>(F, n)) atomicOr(&st->flags, (int)DEV_SINGULAR);
-  __syncthreads();
-  double *out = Fall + ((size_t)w * P.S1 + k) * fb;
-  for (size_t e = lane; e < fb; e += 64) out[e] = F[e];
-}
-
-template <int BW>
-__global__ __launch_bounds__(128) void k_wsolve(TrajParams P, TensLds tl, const double *__restrict__ Mb,
-                                                const double *__restrict__ Db, const double *__restrict__ Kb,
-                                                const double *__restrict__ Floads, const double *__restrict__ Mwp_all,
-                                                const double *__restrict__ omega, const int32_t *__restrict__ sidx,
-                                                const int32_t *__restrict__ Sdim, const double *__restrict__ qhist,
-                                                const double *__restrict__ u0, int ldw,
-                                                const double *__restrict__ Fall, double *__restrict__ dzT,
-                                                DevStatus *st) {
-  constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  extern __shared__ double smem[];
-  const int n = P.n, w = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int b = w / P.St, s = w - b * P.St;
-  const int bw = P.bw, W2u = 2 * bw + 1;  // unpadded full rows of M, D, K
-  const size_t fb = (size_t)(n + BW) * bp;
-  double *FM = smem;                 // factor of w1^2 M
-  double *FS0 = FM + fb;             // factors of T(q_{k+1}), double buffered
-  double *FS1 = FS0 + fb;
-  double *QN0 = FS1 + fb;            // q_{k+1}, double buffered
-  double *QN1 = QN0 + n;
-  double *q = QN1 + n;
-  double *u = q + n;
-  double *a = u + n;
-  double *Qw = a + n;
-  double *Uw = Qw + n;
-  double *Aw = Uw + n;
-  double *x = Aw + n;
-  double *cs = x + n;
-  const double *om = omega + b * P.d;
-  const double w1 = om[0], w1s = w1 * w1;
-  const double *__restrict__ Mwp = Mwp_all + (size_t)b * n * W2;
-  const double *__restrict__ Fw = Fall + (size_t)w * P.S1 * fb;
-
-  if (wave == 0) {
-    for (size_t e = lane; e < fb; e += 64) FM[e] = 0.0;
-    for (int i = lane; i < n; i += 64) {
-      q[i] = qhist[(size_t)i * ldw + w];
-      u[i] = u0[(size_t)i * ldw + w];
-    }
-    if (lane < P.e)
-      cs[lane] = lane == 0 ? 1.0 : cos(kTwoPi * (double)sidx[(lane - 1) * P.St + s] / (double)Sdim[lane - 1]);
-    wave_sync();
-    for (int pos = lane; pos < n * bp; pos += 64) {
-      const int m = pos / bp, rr = pos - m * bp, i = m + rr;
-      FM[BW * bp + pos] = i < n ? Mwp[(size_t)i * W2 + (BW - rr)] : 0.0;
-    }
-    // consistent initial acceleration: (w1^2 M) a0 = e0 - w1 D u0 - K q0 - f_nl(q0)
-    for (int i = lane; i < n; i += 64) {
-      double v = 0.0;
-      for (int f = 0; f < P.e; ++f) v += Floads[(size_t)f * n + i] * cs[f];
-      for (int t = 0; t < W2u; ++t) {
-        const int j = i - bw + t;
-        if (j < 0 || j >= n) continue;
-        v -= w1 * Db[(size_t)i * W2u + t] * u[j] + Kb[(size_t)i * W2u + t] * q[j];
-      }
-      a[i] = v - fnl_row(tl, q, i);
-    }
-    wave_sync();
-    if (lane == 0) {
-      if (!ldlt_serial<BW>(FM, n)) atomicOr(&st->flags, (int)DEV_SINGULAR);
-      ldlt_solve_serial<BW>(FM, n, a);
-    }
-    wave_sync();
-    // (w1^2 M) Aw_0 = -D u0 - 2 w1 M a0;  Qw_0 = Uw_0 = 0
-    for (int i = lane; i < n; i += 64) {
-      double v = 0.0;
-      for (int t = 0; t < W2u; ++t) {
-        const int j = i - bw + t;
-        if (j < 0 || j >= n) continue;
-        v -= Db[(size_t)i * W2u + t] * u[j] + 2.0 * w1 * Mb[(size_t)i * W2u + t] * a[j];
-      }
-      x[i] = v;
-      Qw[i] = 0.0;
-      Uw[i] = 0.0;
-    }
-    wave_sync();
-    if (lane == 0) ldlt_solve_serial<BW>(FM, n, x);
-    wave_sync();
-    for (int i = lane; i < n; i += 64) Aw[i] = x[i];
-  } else {
-    for (size_t e = lane; e < fb; e += 64) FS0[e] = Fw[e];
-    for (int i = lane; i < n; i += 64) QN0[i] = qhist[((size_t)n + i) * ldw + w];
-  }
-  __syncthreads();
-
-  for (int k = 0; k < P.S1; ++k) {
-    if (wave == 1) {
-      if (k + 1 < P.S1) {
-        double *Fn = (k & 1) ? FS0 : FS1;
-        double *Qn = (k & 1) ? QN0 : QN1;
-        const double *src = Fw + (size_t)(k + 1) * fb;
-        for (size_t e = lane; e < fb; e += 64) Fn[e] = src[e];
-        for (int i = lane; i < n; i += 64) Qn[i] = qhist[((size_t)(k + 2) * n + i) * ldw + w];
-      }
-    } else {
-      const double *Fk = (k & 1) ? FS1 : FS0;
-      const double *qn = (k & 1) ? QN1 : QN0;
-      for (int i = lane; i < n; i += 64) {
-        double v = 0.0;
-        for (int t = 0; t < W2u; ++t) {
-          const int j = i - bw + t;
-          if (j < 0 || j >= n) continue;
-          const double Mij = Mb[(size_t)i * W2u + t], Dij = Db[(size_t)i * W2u + t];
-          v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + Uw[j]);
-          v += -(2.0 * w1 * P.c0 * Mij + P.c2 * Dij) * qn[j] +
-               2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + a[j]) + Dij * (P.c2 * q[j] + u[j]);
-        }
-        x[i] = v;
-      }
-      wave_sync();
-      if (lane == 0) ldlt_solve_serial<BW>(Fk, n, x);
-      wave_sync();
-      for (int i = lane; i < n; i += 64) {
-        const double dQ = x[i] - Qw[i];
-        const double uwn = P.c2 * dQ - Uw[i];
-        const double awn = P.c0 * dQ - P.c1 * Uw[i] - Aw[i];
-        Qw[i] = x[i];
-        Uw[i] = uwn;
-        Aw[i] = awn;
-        const double dqk = qn[i] - q[i];
-        const double un = P.c2 * dqk - u[i];
-        const double an = P.c0 * dqk - P.c1 * u[i] - a[i];
-        u[i] = un;
-        a[i] = an;
-        q[i] = qn[i];
-      }
-    }
-    __syncthreads();
-  }
-  if (wave == 0) {
-    bool nan = false;
-    for (int i = lane; i < n; i += 64) {
-      dzT[(size_t)i * ldw + w] = Qw[i];
-      dzT[(size_t)(n + i) * ldw + w] = Uw[i];
-      if (!isfinite(Qw[i]) || !isfinite(Uw[i])) nan = true;
-    }
-    if (nan) atomicOr(&st->flags, (int)DEV_NAN);
-  }
-}
-
-template <int BW>
-fse_status launch_wsens_bw(fse_ctx *ctx, const TrajParams &P, double *dzT) {
-  constexpr int bp = BW + 1;
-  const size_t n = ctx->n, fb = (n + BW) * bp;
-  const size_t need = (size_t)P.W * P.S1 * fb;
-  if (ctx->wfac_elems < need) {
-    if (ctx->wfac) (void)hipFree(ctx->wfac);
-    ctx->wfac = nullptr;
-    ctx->wfac_elems = 0;
-    if (hipMalloc((void **)&ctx->wfac, sizeof(double) * need) != hipSuccess) {
-      ctx->err = "hipMalloc failed for the omega-sensitivity factors";
-      return FSE_E_NOMEM;
-    }
-    ctx->wfac_elems = need;
-  }
-  const TensLds tl{ctx->f2_ptr, ctx->f3_ptr, ctx->f2_pk, ctx->f3_pk, ctx->f2_v, ctx->f3_v};
-  const size_t lds_f = sizeof(double) * (fb + n);
-  hipLaunchKernelGGL(k_wfactor<BW>, dim3(P.S1, P.W), dim3(64), lds_f, ctx->stream, P, tl, ctx->Sp, ctx->qhist,
-                     ctx->Wmax, ctx->wfac, ctx->status_d);
-  FSE_HIP(hipGetLastError());
-  const size_t lds_s = sizeof(double) * (3 * fb + 9 * n + 8);
-  hipLaunchKernelGGL(k_wsolve<BW>, dim3(P.W), dim3(128), lds_s, ctx->stream, P, tl, ctx->Mb, ctx->Db, ctx->Kb,
-                     ctx->F, ctx->Mwp, ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->Wmax,
-                     ctx->wfac, dzT, ctx->status_d);
-  FSE_HIP(hipGetLastError());
-  return FSE_OK;
-}
-
 template <int BW>
 size_t fused_lds_bytes(int n, int nnz2, int nnz3) {
   return sizeof(double) * ((size_t)7 * (n + BW) * (BW + 1) + 10 * (size_t)n + 8 + nnz2 + nnz3) +
@@ -1227,6 +702,8 @@ size_t lds_for(const fse_ctx *ctx) {
 
 }  // namespace
 
+int fused_band_bucket(const fse_ctx *ctx) { return bw_bucket(ctx->bw); }
+
 bool fused_supported(const fse_ctx *ctx) {
   return ctx->bw <= 16 && ctx->n < 65536 && ctx->f2_pk && ctx->f3_pk && lds_for(ctx) + 64 <= 160 * 1024 &&
          ctx->fused_ncw >= 1 && ctx->fused_ncw <= 2;
@@ -1300,36 +777,3 @@ fse_status launch_fused(fse_ctx *ctx, int B, double *Phi) {
   }
   return launch();
 }
-
-fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT) {
-  if (!(ctx->use_fused && fused_supported(ctx))) return FSE_E_UNSUPPORTED;
-  const int BWb = bw_bucket(ctx->bw);
-  const size_t fb = (size_t)(ctx->n + BWb) * (BWb + 1);
-  // the per-step factors of every trajectory are held at once: stay within 8 GiB, and the
-  // solve kernel's three factor buffers and vectors within the LDS
-  if ((size_t)B * ctx->St > 65535 || (size_t)B * ctx->St * ctx->S1 * fb * sizeof(double) > (8ull << 30) ||
-      sizeof(double) * (3 * fb + 9 * (size_t)ctx->n + 8) > 64 * 1024)
-    return FSE_E_UNSUPPORTED;
-  TrajParams p;
-  p.n = ctx->n;
-  p.bw = ctx->bw;
-  p.S1 = ctx->S1;
-  p.e = ctx->e;
-  p.d = ctx->d;
-  p.St = ctx->St;
-  p.W = B * ctx->St;
-  p.maxit = ctx->maxit;
-  p.tol = ctx->tol;
-  p.h = 2.0 * M_PI / ctx->S1;
-  p.c0 = 4.0 / (p.h * p.h);
-  p.c1 = 4.0 / p.h;
-  p.c2 = 2.0 / p.h;
-  switch (BWb) {
-    case 4: return launch_wsens_bw<4>(ctx, p, dzT);
-    case 6: return launch_wsens_bw<6>(ctx, p, dzT);
-    case 8: return launch_wsens_bw<8>(ctx, p, dzT);
-    case 12: return launch_wsens_bw<12>(ctx, p, dzT);
-    default: return FSE_E_UNSUPPORTED;  // the register windows of BW = 16 spill: generic replay
-  }
-}
-

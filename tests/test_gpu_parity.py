@@ -207,9 +207,6 @@ def test_newton_step_ragged_lu():
     assert rel(Zg.cpu().numpy() - Z0, Zo - Z0) < 1e-9
 
 
-@pytest.mark.skip(reason="a Newton step on the 147-DOF beam aborted once with a memory-aperture fault "
-                         "in the first trajectory-kernel launch, with no cause found in the code; kept "
-                         "off the GPU until one is shown")
 def test_c2_newton_step_solves_its_linearisation():
     """Full-size beam (N = 9114 unknowns): the LU runs its register-resident leaves of 8
     (panels of <= 5120 rows) and of 4 columns (<= 9216 rows).  The Newton update dZ must
