@@ -209,6 +209,36 @@ fse_status fse_arclength(fse_ctx *ctx, int32_t P, const double *omega0, const do
                          double tol, int32_t maxit, double *Z_out, double *omega_out, double *steps,
                          int32_t *iters, double *rnorm);
 
+/* ---------------------------------------------------------------- matrix-free Newton-Krylov
+ * For unknown counts whose dense Jacobian is too large to factor, the Jacobian of Eq. (22) is
+ * applied to vectors instead:
+ *     J v = (I (x) R(rho) Gamma^-1) blkdiag_s(Phi_s) (I (x) Gamma) v - v,
+ * using the trajectory sensitivities kept by the context (one point, d = e). */
+
+/* Residual R (device [2n][U], and ||R||_2 on the host if rnorm is non-null) at one point
+ * (omega HOST [d], Z0 device [2n][U]); keeps the sensitivities of every trajectory in the
+ * context for fse_jacobian_apply.  Errors as fse_integrate_batch. */
+fse_status fse_shooting_residual_matfree(fse_ctx *ctx, const double *omega, const double *Z0, double *R,
+                                         double *rnorm);
+
+/* Jv = J v (device [2n][U] each, must not alias) with the sensitivities of the last
+ * fse_shooting_residual_matfree; FSE_E_INVAL if there are none (or a Newton-Krylov step has
+ * moved Z0 since). */
+fse_status fse_jacobian_apply(fse_ctx *ctx, const double *v, double *Jv);
+
+/* One Newton update Z0 <- Z0 + dZ (Z0 device [2n][U], omega HOST [d], d = e only:
+ * FSE_E_UNSUPPORTED otherwise), with J dZ = -R solved by restarted GMRES(restart) to
+ * ||J dZ + R|| <= rtol ||R|| or maxit iterations.  precond != 0 uses right preconditioning by
+ * the harmonic-block matrix P = Phi_bar (x) R(rho) - I (Phi_bar the mean of the trajectory
+ * sensitivities; P = J for a linear system).  Each of its blocks (one 2n x 2n, one 4n x 4n per
+ * harmonic pair) is factored once per step.  HOST outputs (any may be NULL): res_norm =
+ * ||R||_2 before the update, gmres_iters, gmres_relres = ||J dZ + R|| / ||R|| reached.
+ * Device workspace: (restart + 7) vectors of 2nU doubles and the preconditioner blocks
+ * (2n)^2 (1 + 4 L) doubles, held by the context. */
+fse_status fse_newton_krylov_step(fse_ctx *ctx, const double *omega, double *Z0, double rtol, int32_t restart,
+                                  int32_t maxit, int32_t precond, double *res_norm, int32_t *gmres_iters,
+                                  double *gmres_relres);
+
 /* ---------------------------------------------------------------- learned predictor
  * Initial iterates for new continuation parameters from the converged tori of earlier
  * points: a POD basis of the converged Z(0) (method of snapshots: Gram matrix in FP64,

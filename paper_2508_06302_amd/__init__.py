@@ -17,7 +17,8 @@ __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integ
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
            "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
-           "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength", "fse_get_tuning", "FSE_PREC_FP64",
+           "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
+           "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step", "fse_get_tuning", "FSE_PREC_FP64",
            "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
@@ -335,6 +336,45 @@ def fse_arclength(ctx: Context, omega0, Z_init, ds, npts, tol=1e-8, maxit=8):
         err.Z, err.omega, err.steps, err.iters, err.rnorm = Z, om, steps, it, rn
         raise err
     return Z, om, steps, it, rn
+
+
+def fse_shooting_residual_matfree(ctx: Context, omega, Z0):
+    """omega host [d], Z0 [2n][U] -> (R torch cuda [2n][U], ||R||); keeps the sensitivities for
+    fse_jacobian_apply."""
+    torch = _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    z = _dev(Z0, (2 * ctx.n, ctx.U))
+    R = torch.empty((2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+    rn = C.c_double()
+    ctx.check(ctx.lib.fse_shooting_residual_matfree(ctx.h, _p(om, C.c_double), C.c_void_p(z.data_ptr()),
+                                                    C.c_void_p(R.data_ptr()), C.byref(rn)))
+    return R, rn.value
+
+
+def fse_jacobian_apply(ctx: Context, v):
+    """J v with the sensitivities of the last fse_shooting_residual_matfree."""
+    torch = _torch()
+    ctx.bind_stream()
+    x = _dev(v, (2 * ctx.n, ctx.U))
+    out = torch.empty_like(x)
+    ctx.check(ctx.lib.fse_jacobian_apply(ctx.h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr())))
+    return out
+
+
+def fse_newton_krylov_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxit=300, precond=True):
+    """Z0 (torch cuda [2n][U], updated in place) <- Z0 + dZ with J dZ = -R by GMRES ->
+    (||R|| before, GMRES iterations, relative linear residual)."""
+    _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    rn = C.c_double()
+    its = C.c_int32()
+    rel = C.c_double()
+    ctx.check(ctx.lib.fse_newton_krylov_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()), float(rtol),
+                                             int(restart), int(maxit), int(bool(precond)), C.byref(rn),
+                                             C.byref(its), C.byref(rel)))
+    return rn.value, its.value, rel.value
 
 
 class Learned:

@@ -391,7 +391,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)
@@ -504,6 +504,12 @@ fse_status ensure_phi(fse_ctx *ctx) {
 }
 
 }  // namespace
+
+fse_status integrate_points(fse_ctx *ctx, int B, const double *omega, const double *Z0, double *zT, double *Phi) {
+  return integrate_impl(ctx, B, omega, Z0, zT, Phi);
+}
+
+fse_status ensure_phi_buffer(fse_ctx *ctx) { return ensure_phi(ctx); }
 
 // ============================================================================= C-ABI
 extern "C" {

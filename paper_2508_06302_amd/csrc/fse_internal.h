@@ -115,6 +115,11 @@ struct fse_ctx {
   size_t arc_elems = 0;
   double *wfac = nullptr;           // factors of T(q_{k+1}) for every step and trajectory
   size_t wfac_elems = 0;
+  // matrix-free Newton-Krylov (k_krylov.hip)
+  bool mf_ready = false;            // PhiQU and rot_d hold the sensitivities of one evaluation
+  double *kr = nullptr;             // Krylov basis, work vectors, preconditioner blocks
+  size_t kr_elems = 0;
+  int32_t *kr_piv = nullptr;        // pivots of the preconditioner blocks
 
   // packed tensors for LDS staging: t2 (j | k << 16), t3 (j | k << 16, l)
   uint32_t *f2_pk = nullptr, *f3_pk = nullptr;
@@ -136,6 +141,12 @@ struct fse_ctx {
   int last_max_iters = 0;
   unsigned long long last_total_iters = 0;
 };
+
+// ----------------------------------------------------------------------------- host helpers (fse_api.hip)
+// integrate B points (state, and sensitivities into Phi when non-null) with timing and status
+fse_status integrate_points(fse_ctx *ctx, int B, const double *omega, const double *Z0, double *zT, double *Phi);
+// the internal sensitivity buffer PhiQU [Wmax][2n][2n]
+fse_status ensure_phi_buffer(fse_ctx *ctx);
 
 // ----------------------------------------------------------------------------- launches
 // Trajectory integration (k_traj.hip)
@@ -166,6 +177,10 @@ int fused_band_bucket(const fse_ctx *ctx);
 fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT);
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
+// the two halves of dense_lu_solve: factor A (row-major N x N, in place, pivots piv[N]), then
+// solve with the factor for one right-hand side (in place; enqueued, no synchronisation)
+fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv);
+fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs);
 fse_status launch_axpby(fse_ctx *ctx, int N, double a, const double *x, double b, const double *z, double *y);
 fse_status launch_axpy(fse_ctx *ctx, int N, double alpha, const double *x, double *y);
 fse_status launch_lincomb(fse_ctx *ctx, int N, const double *x, double alpha, const double *d, double *y);

@@ -321,15 +321,32 @@ __global__ __launch_bounds__(64) void k_lu_diag(const double *__restrict__ A, in
 }
 
 // x = Pi^T w: interchanges applied in reverse order (one thread).
-__global__ void k_lu_unpermute(double *__restrict__ x, int N, const int32_t *__restrict__ piv) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  for (int k = N - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k) {
-      const double t = x[k];
-      x[k] = x[p];
-      x[p] = t;
+// x <- Pi^T x: the interchanges in reverse order.  Vectors of up to kUnpermLds entries are
+// staged in LDS so the serial chain of swaps runs at LDS latency.
+constexpr int kUnpermLds = 16384;
+
+__global__ __launch_bounds__(1024) void k_lu_unpermute(double *__restrict__ x, int N,
+                                                       const int32_t *__restrict__ piv) {
+  extern __shared__ double xs[];
+  const bool staged = N <= kUnpermLds;
+  if (staged) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = x[i];
+    __syncthreads();
+  }
+  double *v = staged ? xs : x;
+  if (threadIdx.x == 0) {
+    for (int k = N - 1; k >= 0; --k) {
+      const int p = piv[k];
+      if (p != k) {
+        const double t = v[k];
+        v[k] = v[p];
+        v[p] = t;
+      }
     }
+  }
+  if (staged) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = xs[i];
   }
 }
 
@@ -534,19 +551,11 @@ void lu_panel(fse_ctx *ctx, double *B, int N, int j0, int nb) {
 
 }  // namespace
 
-fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
+fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv) {
   FSE_TRY(reset_status(ctx));
-  if (ctx->piv_n < N) {
-    if (ctx->piv_d) (void)hipFree(ctx->piv_d);
-    ctx->piv_d = nullptr;
-    ctx->piv_n = 0;
-    if (hipMalloc((void **)&ctx->piv_d, sizeof(int32_t) * N) != hipSuccess) {
-      ctx->err = "hipMalloc failed for the pivots";
-      return FSE_E_NOMEM;
-    }
-    ctx->piv_n = N;
-  }
-  double *B = A;  // B = J^T column-major
+  int32_t *const saved = ctx->piv_d;
+  ctx->piv_d = piv;  // the panel routines take the pivots from the context
+  double *B = A;     // B = J^T column-major
   for (int j0 = 0; j0 < N; j0 += kLuBlock) {
     const int nb = (N - j0) < kLuBlock ? (N - j0) : kLuBlock;
     lu_panel(ctx, B, N, j0, nb);
@@ -556,6 +565,19 @@ fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
     lu_trsm(ctx, B, N, j0, nb, c1, N - c1);
     lu_gemm(ctx, B, N, c1, N - c1, c1, N - c1, j0, nb);
   }
+  ctx->piv_d = saved;
+  FSE_HIP(hipGetLastError());
+  DevStatus st;
+  FSE_HIP(hipMemcpyAsync(&st, ctx->status_d, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  if (st.flags & DEV_SINGULAR) {
+    ctx->err = "singular Jacobian in the dense LU";
+    return FSE_E_SINGULAR;
+  }
+  return FSE_OK;
+}
+
+fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs) {
   // U^T v = r (forward, memory rows), then L^T w = v (backward), then x = Pi^T w
   for (int r0 = 0; r0 < N; r0 += 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
@@ -572,15 +594,29 @@ fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
                          rhs, rhs);
     hipLaunchKernelGGL(k_lu_diag, dim3(1), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs);
   }
-  hipLaunchKernelGGL(k_lu_unpermute, dim3(1), dim3(1), 0, ctx->stream, rhs, N, ctx->piv_d);
+  const size_t lds = N <= kUnpermLds ? sizeof(double) * N : 0;
+  if (lds > 64 * 1024)
+    FSE_HIP(hipFuncSetAttribute((const void *)k_lu_unpermute, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * kUnpermLds)));
+  hipLaunchKernelGGL(k_lu_unpermute, dim3(1), dim3(1024), lds, ctx->stream, rhs, N, piv);
   FSE_HIP(hipGetLastError());
-  DevStatus st;
-  FSE_HIP(hipMemcpyAsync(&st, ctx->status_d, sizeof(st), hipMemcpyDeviceToHost, ctx->stream));
-  FSE_HIP(hipStreamSynchronize(ctx->stream));
-  if (st.flags & DEV_SINGULAR) {
-    ctx->err = "singular Jacobian in the dense LU";
-    return FSE_E_SINGULAR;
+  return FSE_OK;
+}
+
+fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
+  if (ctx->piv_n < N) {
+    if (ctx->piv_d) (void)hipFree(ctx->piv_d);
+    ctx->piv_d = nullptr;
+    ctx->piv_n = 0;
+    if (hipMalloc((void **)&ctx->piv_d, sizeof(int32_t) * N) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the pivots";
+      return FSE_E_NOMEM;
+    }
+    ctx->piv_n = N;
   }
+  FSE_TRY(dense_lu_factor(ctx, A, N, ctx->piv_d));
+  FSE_TRY(dense_lu_apply(ctx, A, N, ctx->piv_d, rhs));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
 

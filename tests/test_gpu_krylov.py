@@ -1,0 +1,129 @@
+"""GPU matrix-free Newton-Krylov (Eq. 22 applied to vectors, GMRES, harmonic-block
+preconditioner) against the oracle.
+
+Bar: J v within 1e-10 normwise relative of the oracle's matrix-free product (the same discrete
+derivative); a GMRES correction meets ||R + J dZ|| <= rtol ||R|| with the oracle's dense J;
+on a linear system the preconditioned solve takes one iteration and lands on the closed form;
+the Newton-Krylov torus of the beam equals the dense-Newton torus.
+"""
+import numpy as np
+import pytest
+
+from _closed_forms import discrete_linear_torus
+from fse_inputs import Torus, tiny_system, workload
+from oracle import krylov as okry
+from oracle import shooting as osh
+
+pytestmark = pytest.mark.gpu
+GOLDEN = (1 + 5 ** 0.5) / 2
+RTOL = 1e-10
+
+
+def fse():
+    import paper_2508_06302_amd as m
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def _case(d, nonlinear=True, seed=2):
+    s = tiny_system(n=3, seed=seed, nonlinear=nonlinear, cubic=1.0, quad=0.3, e=d)
+    om = np.array([0.8, 0.8 * GOLDEN, 0.8 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=d, K=[np.arange(1, 4)] * (d - 1), S=[8] * (d - 1), S1=48)
+    tb = osh.TorusTables(tr)
+    return s, tr, tb, om
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_jacobian_apply_matches_oracle(d):
+    s, tr, tb, om = _case(d)
+    rng = np.random.default_rng(4)
+    Z0 = 0.2 * rng.normal(size=(6, tb.U))
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    R, rn = fse().fse_shooting_residual_matfree(ctx, om, Z0)
+    assert rel(R.cpu().numpy(), ref["R"]) < RTOL
+    for _ in range(3):
+        v = rng.normal(size=(6, tb.U))
+        Jv = fse().fse_jacobian_apply(ctx, v).cpu().numpy()
+        assert rel(Jv, okry.jacobian_apply(ref, v)) < RTOL
+
+
+def test_jacobian_apply_c1_and_error_path():
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    ref = osh.evaluate(wl.system, wl.torus, wl.omega, Z0, sens=True, tables=tb)
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    with pytest.raises(fse().FseError, match="FSE_E_INVAL"):
+        fse().fse_jacobian_apply(ctx, np.ones_like(Z0))
+    fse().fse_shooting_residual_matfree(ctx, wl.omega, Z0)
+    v = np.random.default_rng(8).normal(size=Z0.shape) * np.abs(Z0).max()
+    assert rel(fse().fse_jacobian_apply(ctx, v).cpu().numpy(), okry.jacobian_apply(ref, v)) < RTOL
+
+
+def test_preconditioned_step_is_exact_for_a_linear_system():
+    import torch
+    s, tr, tb, om = _case(2, nonlinear=False)
+    Zs = discrete_linear_torus(s, om, tr.S1, tb.table, tb.U)
+    ctx = fse().fse_init_torus(s, tr)
+    Zg = torch.zeros((6, tb.U), dtype=torch.float64, device="cuda")
+    rn, its, relres = fse().fse_newton_krylov_step(ctx, om, Zg, rtol=1e-12, restart=20, maxit=100)
+    log(f"linear: GMRES iterations {its}, relative residual {relres:.2e}")
+    assert its == 1 and relres < 1e-12
+    assert np.abs(Zg.cpu().numpy() - Zs).max() < 1e-11 * np.abs(Zs).max()
+
+
+@pytest.mark.parametrize("precond", [True, False])
+def test_krylov_correction_meets_its_tolerance(precond):
+    import torch
+    s, tr, tb, om = _case(2)
+    Z0 = 0.2 * np.random.default_rng(6).normal(size=(6, tb.U))
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    J = osh.jacobian(ref)
+    R = ref["R"].ravel()
+    ctx = fse().fse_init_torus(s, tr)
+    for rtol in (1e-4, 1e-10):
+        Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+        rn, its, relres = fse().fse_newton_krylov_step(ctx, om, Zg, rtol=rtol, restart=10, maxit=400,
+                                                       precond=precond)
+        dZ = Zg.cpu().numpy().ravel() - Z0.ravel()
+        lin = np.linalg.norm(R + J @ dZ) / np.linalg.norm(R)
+        log(f"precond={precond} rtol={rtol:g}: GMRES iterations {its}, reported {relres:.2e}, "
+            f"with the oracle's J {lin:.2e}")
+        assert abs(rn - np.linalg.norm(R)) < RTOL * np.linalg.norm(R)
+        assert lin <= 1.001 * rtol
+        assert relres <= rtol
+
+
+def test_c2_newton_krylov_reaches_the_dense_newton_torus():
+    """Beam at 0.3 N from the linear start: Newton-Krylov with the harmonic-block
+    preconditioner converges to the torus of the dense-LU Newton solve."""
+    import torch
+    wl = workload("C2")
+    ctx = fse().fse_init_torus(wl.system, wl.torus)
+    U, St, bw, kt = fse().fse_get_layout(ctx)
+    fse().fse_set_forcing(ctx, [0.3, 0.3])
+    Z0 = torch.tensor(wl.initial_iterate(kt) * 0.3, dtype=torch.float64, device="cuda")
+    Zd = Z0.clone()
+    it_d, rn_d = fse().fse_newton_solve(ctx, wl.omega.copy(), Zd, tol=1e-10, maxit=15)
+    Zk = Z0.clone()
+    hist, gits = [], []
+    for _ in range(12):
+        rn, its, relres = fse().fse_newton_krylov_step(ctx, wl.omega, Zk, rtol=1e-10, restart=30, maxit=300)
+        hist.append(rn)
+        gits.append(its)
+        if rn < 1e-10:
+            break
+    log(f"dense Newton: {it_d} iterations; Newton-Krylov ||R|| history {['%.1e' % h for h in hist]}, "
+        f"GMRES iterations {gits}")
+    assert hist[-1] < 1e-10
+    assert rel(Zk.cpu().numpy(), Zd.cpu().numpy()) < 1e-8
