@@ -1,0 +1,86 @@
+"""FSE-Shooting in the hyper-time domain (oracle; test infrastructure only).
+
+Sec. 3.4 of the paper writes the same shooting conditions with the trajectory initial
+states themselves as unknowns: with zbar(0) the [2n][S~] samples of the initial torus,
+    R(zbar(0), omega) = (I (x) Gamma R(rho) Gamma^-1) zbar(2 pi) - zbar(0)     (Eq. FSES_T),
+where zbar(2 pi) are the states after one period of phi_1 (App. E, the same integrator).
+The S~ x S~ operator A = Gamma R(rho) Gamma^-1 shifts the sampled torus by -2 pi rho through
+its Fourier interpolant.  Its Jacobian is
+    J[(i, s), (j, t)] = A[s, t] Phi_t[i, j] - delta,
+with Phi_t the sensitivity matrix of trajectory t (Eqs. E8-E9).  Unknowns are ordered
+state-major, (i, s) -> i S~ + s.  Only d = e is built: the unknown-frequency rows of the
+multi-frequency form have no counterpart here yet.
+
+Pins (tests/test_oracle_hypertime.py): for zbar(0) = Gamma Z(0), the hyper-time residual is
+Gamma applied to the multi-frequency residual (Gamma^-1 Gamma = I); the Jacobian against
+central differences; a linear system's closed-form torus, sampled, solves it, and one Newton
+step reaches it; on a nonlinear system the hyper-time Newton solution is the sampled
+multi-frequency torus.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import newmark
+from . import shooting
+from . import torus as tor
+
+
+def operator(tables, omega):
+    """A = Gamma R(rho) Gamma^-1 (S~ x S~)."""
+    omega = np.asarray(omega, dtype=float)
+    Rm = tor.rotation(tables.table, omega[1:] / omega[0]) if tables.torus.d > 1 else np.eye(1)
+    return tables.G @ Rm @ tables.Gi
+
+
+def evaluate(sysm, torus, omega, zbar0, sens=False, tables=None, tol=1e-12, maxit=30):
+    """Integrate every trajectory from the samples zbar0 [2n][S~]; returns zbarT, R, A and
+    Phi [S~][2n][2n] if sens."""
+    tb = tables or shooting.TorusTables(torus)
+    omega = np.asarray(omega, dtype=float)
+    z0 = np.asarray(zbar0, dtype=float)
+    zT = np.empty_like(z0)
+    Phi = np.empty((tb.Stilde, z0.shape[0], z0.shape[0])) if sens else None
+    for s in range(tb.Stilde):
+        out = newmark.integrate(sysm, omega, torus.S1, tb.phases[:, s], z0[:, s], sens=sens, tol=tol,
+                                maxit=maxit)
+        zT[:, s] = out["zT"]
+        if sens:
+            Phi[s] = out["Phi"]
+    A = operator(tb, omega)
+    res = {"zbarT": zT, "A": A, "R": zT @ A.T - z0, "tables": tb}
+    if sens:
+        res["Phi"] = Phi
+    return res
+
+
+def jacobian(res):
+    """J[(i, s), (j, t)] = A[s, t] Phi_t[i, j] - delta."""
+    A, Phi = res["A"], res["Phi"]
+    St, n2 = A.shape[0], Phi.shape[1]
+    J4 = np.einsum("st,tij->isjt", A, Phi)
+    J = J4.reshape(n2 * St, n2 * St)
+    return J - np.eye(n2 * St)
+
+
+def newton_step(sysm, torus, omega, zbar0, tables=None, tol=1e-12):
+    """zbar0 -> zbar0 - J^-1 R; returns (zbar_new, ||R||_2 before)."""
+    res = evaluate(sysm, torus, omega, zbar0, sens=True, tables=tables, tol=tol)
+    J = jacobian(res)
+    dz = np.linalg.solve(J, -res["R"].ravel())
+    return zbar0 + dz.reshape(np.shape(zbar0)), float(np.linalg.norm(res["R"]))
+
+
+def solve(sysm, torus, omega, zbar0, tol_R=1e-8, max_newton=20, tables=None):
+    """Newton iterations until ||R||_2 < tol_R; returns (zbar0, history of ||R||_2)."""
+    z = np.array(zbar0, dtype=float)
+    hist = []
+    for _ in range(max_newton):
+        z_new, r = newton_step(sysm, torus, omega, z, tables=tables)
+        hist.append(r)
+        if r < tol_R:
+            return z, hist
+        z = z_new
+    res = evaluate(sysm, torus, omega, z, tables=tables)
+    hist.append(float(np.linalg.norm(res["R"])))
+    return z, hist

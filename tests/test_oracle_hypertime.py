@@ -1,0 +1,66 @@
+"""Pins of the oracle's hyper-time FSE-Shooting (Sec. 3.4, Eq. FSES_T)."""
+import numpy as np
+import pytest
+
+from _closed_forms import discrete_linear_torus
+from fse_inputs import Torus, tiny_system
+from oracle import hypertime as ht
+from oracle import shooting
+
+GOLDEN = (1 + 5 ** 0.5) / 2
+
+
+def _case(d, nonlinear=True, seed=2, S=8):
+    s = tiny_system(n=2, seed=seed, nonlinear=nonlinear, cubic=1.0, quad=0.3, e=d)
+    om = np.array([0.8, 0.8 * GOLDEN, 0.8 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=d, K=[np.arange(1, 3)] * (d - 1), S=[S] * (d - 1), S1=32)
+    return s, tr, shooting.TorusTables(tr), om
+
+
+@pytest.mark.parametrize("d,S", [(2, 5), (2, 8), (3, 6)])
+def test_residual_is_gamma_times_the_multifrequency_residual(d, S):
+    """zbar(0) = Gamma Z(0): R_ht = Gamma R_mf (Gamma^-1 Gamma = I), with S~ = U~ and S~ > U~."""
+    s, tr, tb, om = _case(d, S=S)
+    Z0 = 0.2 * np.random.default_rng(3).normal(size=(4, tb.U))
+    mf = shooting.evaluate(s, tr, om, Z0, tables=tb)
+    h = ht.evaluate(s, tr, om, Z0 @ tb.G.T, tables=tb)
+    assert np.allclose(h["R"], mf["R"] @ tb.G.T, rtol=1e-12, atol=1e-13)
+    # A is a projection onto the band-limited samples, rotated: A^k = Gamma R^k Gamma^-1
+    A = h["A"]
+    assert np.allclose(A @ A, tb.G @ (mf["Rrot"] @ mf["Rrot"]) @ tb.Gi, atol=1e-12)
+
+
+def test_jacobian_matches_finite_differences():
+    s, tr, tb, om = _case(2, S=5)
+    z0 = 0.2 * np.random.default_rng(4).normal(size=(4, tb.Stilde))
+    res = ht.evaluate(s, tr, om, z0, sens=True, tables=tb)
+    J = ht.jacobian(res)
+    h = 1e-6
+    fd = np.empty_like(J)
+    for c in range(J.shape[1]):
+        e = np.zeros(J.shape[1])
+        e[c] = h
+        rp = ht.evaluate(s, tr, om, z0 + e.reshape(z0.shape), tables=tb)["R"].ravel()
+        rm = ht.evaluate(s, tr, om, z0 - e.reshape(z0.shape), tables=tb)["R"].ravel()
+        fd[:, c] = (rp - rm) / (2 * h)
+    assert np.allclose(J, fd, rtol=1e-6, atol=1e-7)
+
+
+def test_linear_closed_form_torus_sampled_is_the_solution():
+    s, tr, tb, om = _case(2, nonlinear=False, S=8)
+    Zs = discrete_linear_torus(s, om, tr.S1, tb.table, tb.U)
+    zs = Zs @ tb.G.T
+    res = ht.evaluate(s, tr, om, zs, tables=tb)
+    assert np.linalg.norm(res["R"]) < 1e-12 * np.linalg.norm(zs)
+    z1, r0 = ht.newton_step(s, tr, om, np.zeros_like(zs), tables=tb)
+    assert r0 > 1e-3
+    assert np.abs(z1 - zs).max() < 1e-12 * np.abs(zs).max()
+
+
+def test_nonlinear_solution_is_the_sampled_multifrequency_torus():
+    s, tr, tb, om = _case(2, S=8)
+    s.F *= 0.5
+    Zm, _, hm = shooting.solve(s, tr, om, np.zeros((4, tb.U)), tol_R=1e-13, tables=tb)
+    zh, hh = ht.solve(s, tr, om, np.zeros((4, tb.Stilde)), tol_R=1e-13, tables=tb)
+    assert hm[-1] < 1e-13 and hh[-1] < 1e-13
+    assert np.abs(zh - Zm @ tb.G.T).max() < 1e-10 * np.abs(zh).max()
