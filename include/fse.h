@@ -239,6 +239,24 @@ fse_status fse_newton_krylov_step(fse_ctx *ctx, const double *omega, double *Z0,
                                   int32_t maxit, int32_t precond, double *res_norm, int32_t *gmres_iters,
                                   double *gmres_relres);
 
+/* ---------------------------------------------------------------- hyper-time domain
+ * FSE-Shooting with the sampled initial states as unknowns (Sec. 3.4, Eq. FSES_T):
+ *     R(zbar(0), omega) = (I (x) Gamma R(rho) Gamma^-1) zbar(2 pi) - zbar(0),
+ * zbar(0), zbar(2 pi) and R laid out [2n][S~] per point; unknowns (i, s) -> i S~ + s.
+ * d = e only (FSE_E_UNSUPPORTED otherwise). */
+
+/* omega HOST [B][d], zbar0 device [B][2n][S~]; outputs R device [B][2n][S~], rnorm HOST [B]
+ * (may be NULL), J device [B][2nS~][2nS~] row-major or NULL (then no sensitivities are
+ * propagated): J[(i, s), (j, t)] = (Gamma R Gamma^-1)[s, t] Phi_t[i, j] - delta.  Errors as
+ * fse_integrate_batch. */
+fse_status fse_hypertime_residual_jacobian(fse_ctx *ctx, int32_t B, const double *omega, const double *zbar0,
+                                           double *R, double *rnorm, double *J);
+
+/* One Newton update of the hyper-time unknowns (zbar0 device [2n][S~], in place) with a dense
+ * LU of the (2nS~)^2 Jacobian held by the context; res_norm HOST = ||R||_2 before the update
+ * (may be NULL).  FSE_E_SINGULAR on a zero pivot. */
+fse_status fse_hypertime_newton_step(fse_ctx *ctx, const double *omega, double *zbar0, double *res_norm);
+
 /* ---------------------------------------------------------------- learned predictor
  * Initial iterates for new continuation parameters from the converged tori of earlier
  * points: a POD basis of the converged Z(0) (method of snapshots: Gram matrix in FP64,

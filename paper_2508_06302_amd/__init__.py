@@ -18,7 +18,8 @@ __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integ
            "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
            "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
-           "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step", "fse_get_tuning", "FSE_PREC_FP64",
+           "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step",
+           "fse_hypertime_residual_jacobian", "fse_hypertime_newton_step", "fse_get_tuning", "FSE_PREC_FP64",
            "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
@@ -375,6 +376,35 @@ def fse_newton_krylov_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxi
                                              int(restart), int(maxit), int(bool(precond)), C.byref(rn),
                                              C.byref(its), C.byref(rel)))
     return rn.value, its.value, rel.value
+
+
+def fse_hypertime_residual_jacobian(ctx: Context, omega, zbar0, want_J=False):
+    """Hyper-time shooting (samples as unknowns): omega [B][d], zbar0 [B][2n][S~] ->
+    (R torch cuda [B][2n][S~], ||R|| [B], J [B][2nS~][2nS~] or None)."""
+    torch = _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(-1, ctx.d))
+    B = om.shape[0]
+    z = _dev(zbar0, (B, 2 * ctx.n, ctx.Stilde))
+    R = torch.empty_like(z)
+    rn = np.zeros(B)
+    Nh = 2 * ctx.n * ctx.Stilde
+    J = torch.empty((B, Nh, Nh), dtype=torch.float64, device="cuda") if want_J else None
+    ctx.check(ctx.lib.fse_hypertime_residual_jacobian(ctx.h, B, _p(om, C.c_double), C.c_void_p(z.data_ptr()),
+                                                      C.c_void_p(R.data_ptr()), _p(rn, C.c_double),
+                                                      C.c_void_p(J.data_ptr()) if J is not None else None))
+    return R, rn, J
+
+
+def fse_hypertime_newton_step(ctx: Context, omega, zbar0):
+    """zbar0 (torch cuda [2n][S~], updated in place) <- one dense Newton step -> ||R|| before."""
+    _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    rn = C.c_double()
+    ctx.check(ctx.lib.fse_hypertime_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(zbar0.data_ptr()),
+                                                C.byref(rn)))
+    return rn.value
 
 
 class Learned:

@@ -391,7 +391,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)
@@ -457,7 +457,10 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
   }
   FSE_TRY(upload_omega(ctx, B, omega));
   FSE_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
-  FSE_TRY(launch_idft(ctx, B, Z0));
+  if (ctx->samples_in)
+    FSE_TRY(launch_samples_in(ctx, B, Z0));  // Z0 holds the samples zbar(0) [B][2n][S~]
+  else
+    FSE_TRY(launch_idft(ctx, B, Z0));
   FSE_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
   const bool fused = ctx->use_fused && fused_supported(ctx);
   if (!fused && Phi && ctx->prec == FSE_PREC_MIXED_FP32) {
@@ -668,6 +671,9 @@ fse_status ensure_newton_buffers(fse_ctx *ctx) {
 }
 
 }  // namespace
+
+extern "C++" fse_status ensure_dense_matrix(fse_ctx *ctx, size_t Nb) { return ensure_matrix(ctx, Nb); }
+
 
 fse_status fse_newton_step(fse_ctx *ctx, double *omega, double *Z0, double *res_norm) {
   if (!ctx || !Z0 || !omega) return FSE_E_INVAL;

@@ -120,6 +120,10 @@ struct fse_ctx {
   double *kr = nullptr;             // Krylov basis, work vectors, preconditioner blocks
   size_t kr_elems = 0;
   int32_t *kr_piv = nullptr;        // pivots of the preconditioner blocks
+  // hyper-time FSE-Shooting (k_hypertime.hip)
+  bool samples_in = false;          // the next integration starts from samples, not coefficients
+  double *ht = nullptr;             // Gamma R Gamma^-1 per point, R Gamma^-1, residual
+  size_t ht_elems = 0;
 
   // packed tensors for LDS staging: t2 (j | k << 16), t3 (j | k << 16, l)
   uint32_t *f2_pk = nullptr, *f3_pk = nullptr;
@@ -147,6 +151,10 @@ struct fse_ctx {
 fse_status integrate_points(fse_ctx *ctx, int B, const double *omega, const double *Z0, double *zT, double *Phi);
 // the internal sensitivity buffer PhiQU [Wmax][2n][2n]
 fse_status ensure_phi_buffer(fse_ctx *ctx);
+// the dense Newton workspace Jw, at least Nb x Nb
+fse_status ensure_dense_matrix(fse_ctx *ctx, size_t Nb);
+// initial states of every trajectory straight from samples zbar(0) [B][2n][S~] (k_hypertime.hip)
+fse_status launch_samples_in(fse_ctx *ctx, int B, const double *zbar0);
 
 // ----------------------------------------------------------------------------- launches
 // Trajectory integration (k_traj.hip)
