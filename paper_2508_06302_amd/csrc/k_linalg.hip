@@ -328,25 +328,31 @@ constexpr int kUnpermLds = 16384;
 __global__ __launch_bounds__(1024) void k_lu_unpermute(double *__restrict__ x, int N,
                                                        const int32_t *__restrict__ piv) {
   extern __shared__ double xs[];
-  const bool staged = N <= kUnpermLds;
-  if (staged) {
+  if (N <= kUnpermLds) {
+    // the two memories get separate code so that no pointer may point to either
     for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = x[i];
     __syncthreads();
-  }
-  double *v = staged ? xs : x;
-  if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      for (int k = N - 1; k >= 0; --k) {
+        const int p = piv[k];
+        if (p != k) {
+          const double t = xs[k];
+          xs[k] = xs[p];
+          xs[p] = t;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = xs[i];
+  } else if (threadIdx.x == 0) {
     for (int k = N - 1; k >= 0; --k) {
       const int p = piv[k];
       if (p != k) {
-        const double t = v[k];
-        v[k] = v[p];
-        v[p] = t;
+        const double t = x[k];
+        x[k] = x[p];
+        x[p] = t;
       }
     }
-  }
-  if (staged) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < N; i += blockDim.x) x[i] = xs[i];
   }
 }
 

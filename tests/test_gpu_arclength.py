@@ -155,3 +155,24 @@ def test_arclength_error_paths():
     with pytest.raises(fse().FseError) as ex:
         fse().fse_arclength(ctx, np.array([0.6]), np.full((2, 1), 5.0), 0.1, 3, tol=1e-12, maxit=0)
     assert ex.value.iters[0] == -1
+
+
+def test_unsupported_and_invalid_calls():
+    """d > e is rejected by the arclength, Newton-Krylov and hyper-time calls (their bordered
+    rows are not held to the oracle); batch sizes beyond the context are rejected."""
+    s, tr, tb, om, Z0 = _case(2, 1)
+    ctx = fse().fse_init_torus(s, tr)
+    m = fse()
+    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
+        m.fse_arclength(ctx, om, Z0, 0.1, 3)
+    import torch
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
+        m.fse_newton_krylov_step(ctx, om, Zg)
+    zb = np.zeros((2 * s.n, tb.Stilde))
+    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
+        m.fse_hypertime_residual_jacobian(ctx, om[None], zb[None])
+    s2, tr2, tb2, om2, Z2 = _case(2, 2)
+    ctx2 = m.fse_init_torus(s2, tr2)
+    with pytest.raises(m.FseError, match="FSE_E_INVAL"):
+        m.fse_residual_dp(ctx2, np.stack([om2, om2]), np.stack([Z2, Z2]))
