@@ -316,6 +316,17 @@ fse_status fse_learned_train(fse_learned *m, int32_t m_snap, const double *P, co
 fse_status fse_learned_predict(fse_learned *m, const double *p, double *Z);
 void fse_learned_destroy(fse_learned *m);
 
+/* Raw network outputs for B <= 256 normalised inputs: x HOST [B][n_in], y HOST [B][rank]
+ * (FP32).  bf16 != 0 runs the three layers as bfloat16 matrix-core products
+ * (v_mfma_f32_16x16x16_bf16): weights and each layer's input rounded to bfloat16, nearest with
+ * ties to even, products accumulated in FP32, bias and GELU in FP32.  bf16 = 0 is the FP32
+ * network used in training. */
+fse_status fse_learned_forward(fse_learned *m, int32_t B, const float *x, int32_t bf16, float *y);
+
+/* Predictions for P <= 256 points at once (the batched form of fse_learned_predict):
+ * params HOST [P][n_in], Z device [P][2n][U]; bf16 as in fse_learned_forward. */
+fse_status fse_learned_predict_batch(fse_learned *m, int32_t P, const double *params, int32_t bf16, double *Z);
+
 /* fse_continuation with a second predictor: from point first_learned on, the learned
  * prediction for features[j] (HOST [P][n_in], e.g. (omega_1, omega_2 / omega_1, f)) and the
  * secant prediction are both evaluated (one residual each) and Newton starts from the one

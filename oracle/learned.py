@@ -9,6 +9,9 @@ values:
   pod_snapshots   orthonormal basis; reconstruction error of the snapshots
                   equals the discarded singular values (test vs numpy SVD)
   mlp_*           forward in FP64; gradients vs central finite differences
+  bf16_round      round-to-nearest-even to bfloat16 (8 significand bits), pinned by
+                  hand-worked values; mlp_forward_bf16 is mlp_forward with every layer's
+                  weights and inputs rounded to bfloat16 (the reduced-precision inference)
 """
 from __future__ import annotations
 
@@ -71,6 +74,25 @@ def mlp_forward(params, x):
         cache.append((h, z))
         h = gelu(z) if li < len(params) - 1 else z
     return h, cache
+
+
+def bf16_round(x):
+    """Round FP32 values to bfloat16 (keep the top 16 bits of the FP32 pattern, ties to
+    even), returned as float64.  Inputs are first rounded to FP32."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_forward_bf16(params, x):
+    """mlp_forward with the weights and each layer's input rounded to bfloat16; products
+    summed exactly (FP64), biases kept FP32."""
+    h = np.asarray(x, dtype=float)
+    for li, (W, b) in enumerate(params):
+        z = bf16_round(h) @ bf16_round(W).T + np.asarray(b, dtype=np.float32).astype(float)
+        h = gelu(z) if li < len(params) - 1 else z
+    return h
 
 
 def mlp_loss(params, x, t):

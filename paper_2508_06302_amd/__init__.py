@@ -485,6 +485,27 @@ class Learned:
         ctx.check(ctx.lib.fse_learned_predict(self.h, _p(pp, C.c_double), C.c_void_p(Z.data_ptr())))
         return Z
 
+    def forward(self, x, bf16=False):
+        """Raw network outputs y [B][rank] (FP32 host) for normalised inputs x [B][n_in]."""
+        _torch()
+        self.ctx.bind_stream()
+        xf = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(-1, self.n_in))
+        y = np.zeros((xf.shape[0], self.rank), np.float32)
+        self.ctx.check(self.ctx.lib.fse_learned_forward(self.h, xf.shape[0], _p(xf, C.c_float), int(bool(bf16)),
+                                                        _p(y, C.c_float)))
+        return y
+
+    def predict_batch(self, params, bf16=False):
+        """Predictions Z [P][2n][U] (torch cuda) for parameters [P][n_in] in one batch."""
+        torch = _torch()
+        ctx = self.ctx
+        ctx.bind_stream()
+        pp = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, self.n_in))
+        Z = torch.empty((pp.shape[0], 2 * ctx.n, ctx.U), dtype=torch.float64, device="cuda")
+        ctx.check(ctx.lib.fse_learned_predict_batch(self.h, pp.shape[0], _p(pp, C.c_double), int(bool(bf16)),
+                                                    C.c_void_p(Z.data_ptr())))
+        return Z
+
     def __del__(self):
         try:
             if self.h:

@@ -19,6 +19,7 @@ EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_
            "fse_learned_num_params", "fse_learned_inputs", "fse_learned_set_params",
            "fse_learned_get_params", "fse_learned_fit_pod", "fse_learned_get_pod",
            "fse_learned_loss_grad", "fse_learned_fit", "fse_learned_train", "fse_learned_predict",
+           "fse_learned_forward", "fse_learned_predict_batch",
            "fse_learned_destroy", "fse_get_tuning", "fse_last_timing", "fse_last_error", "fse_destroy"]
 
 i32p = C.POINTER(C.c_int32)
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.fse_learned_fit.argtypes = [vp, C.c_int32, f32p, f32p, C.c_int32, C.c_double, C.c_double, f64p]
     lib.fse_learned_train.argtypes = [vp, C.c_int32, f64p, vp, C.c_int32, C.c_double, C.c_double, f64p]
     lib.fse_learned_predict.argtypes = [vp, f64p, vp]
+    lib.fse_learned_forward.argtypes = [vp, C.c_int32, f32p, C.c_int32, f32p]
+    lib.fse_learned_predict_batch.argtypes = [vp, C.c_int32, f64p, C.c_int32, vp]
     lib.fse_learned_destroy.argtypes = [vp]
     lib.fse_learned_destroy.restype = None
     lib.fse_get_tuning.argtypes = [vp, i32p, f32p]

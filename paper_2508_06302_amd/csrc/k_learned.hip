@@ -257,6 +257,62 @@ __global__ __launch_bounds__(256) void k_pod_coef(int m, int N, int rank, const 
   if (lane == 0) coef[pr] = s;
 }
 
+// ------------------------------------------------------------------ BF16 MFMA inference
+// Dense layer Y[m][n] = act(sum_k X[m][k] W[n][k] + b[n]) with X and W rounded to bfloat16
+// (nearest, ties to even) as they are loaded and the products accumulated in FP32 by
+// v_mfma_f32_16x16x16_bf16.  One wave per 16 x 16 output tile, four waves along n.  Operand
+// layout of that instruction: lane l supplies A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16], i < 4, and receives C[4 (l / 16) + i][l % 16].
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_dense_bf16(int M, int N, int K, const float *__restrict__ X,
+                                                    const float *__restrict__ W, const float *__restrict__ bias,
+                                                    int gelu, float *__restrict__ Y) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 16, n0 = (blockIdx.x * 4 + wave) * 16;
+  if (n0 >= N) return;  // the whole wave leaves together
+  const int r = lane & 15, kg = (lane >> 4) * 4;
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = k0 + kg + i;
+      a[i] = (m0 + r < M && k < K) ? f32_to_bf16(X[(size_t)(m0 + r) * K + k]) : (short)0;
+      b[i] = (n0 + r < N && k < K) ? f32_to_bf16(W[(size_t)(n0 + r) * K + k]) : (short)0;
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + kg + i, n = n0 + r;
+    if (m < M && n < N) {
+      float v = acc[i] + bias[n];
+      Y[(size_t)m * N + n] = gelu ? gelu_f(v) : v;
+    }
+  }
+}
+
+// Z[p][i] = mean[i] + sum_r modes[i][r] c[p][r]
+__global__ void k_pod_expand_batch(int P, int N, int rank, const double *__restrict__ mean,
+                                   const double *__restrict__ modes, const double *__restrict__ c,
+                                   double *__restrict__ Z) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)P * N) return;
+  const int p = (int)(idx / N), i = (int)(idx % N);
+  double s = mean[i];
+  for (int r = 0; r < rank; ++r) s += modes[(size_t)i * rank + r] * c[(size_t)p * rank + r];
+  Z[idx] = s;
+}
+
 // Z[i] = mean[i] + sum_r modes[i][r] c[r]
 __global__ void k_pod_expand(int N, int rank, const double *__restrict__ mean, const double *__restrict__ modes,
                              const double *__restrict__ c, double *__restrict__ Z) {
@@ -296,6 +352,19 @@ void forward(fse_learned *m, int B) {
   gemm(m, B, H, H, m->a1, H, 1, W2, 1, H, m->z2, H, b2, false);
   hipLaunchKernelGGL(k_gelu, dim3((B * H + 255) / 256), dim3(256), 0, s, B * H, m->z2, m->a2);
   gemm(m, B, R, H, m->a2, H, 1, W3, 1, H, m->y, R, b3, false);
+}
+
+// forward pass for B rows of m->x with BF16 MFMA layers: a1, a2, y
+void forward_bf16(fse_learned *m, int B) {
+  const int H = m->H, nin = m->n_in, R = m->rank;
+  const float *W1 = m->par + m->off[0], *b1 = m->par + m->off[1];
+  const float *W2 = m->par + m->off[2], *b2 = m->par + m->off[3];
+  const float *W3 = m->par + m->off[4], *b3 = m->par + m->off[5];
+  hipStream_t s = m->ctx->stream;
+  const dim3 blk(256);
+  hipLaunchKernelGGL(k_dense_bf16, dim3((H + 63) / 64, (B + 15) / 16), blk, 0, s, B, H, nin, m->x, W1, b1, 1, m->a1);
+  hipLaunchKernelGGL(k_dense_bf16, dim3((H + 63) / 64, (B + 15) / 16), blk, 0, s, B, H, H, m->a1, W2, b2, 1, m->a2);
+  hipLaunchKernelGGL(k_dense_bf16, dim3((R + 63) / 64, (B + 15) / 16), blk, 0, s, B, R, H, m->a2, W3, b3, 0, m->y);
 }
 
 // loss and gradients for B rows (targets in m->tg) into m->grd
@@ -590,6 +659,63 @@ fse_status fse_learned_predict(fse_learned *m, const double *p, double *Z) {
                      Z);
   FSE_HIP(hipGetLastError());
   FSE_HIP(hipStreamSynchronize(s));
+  return FSE_OK;
+}
+
+fse_status fse_learned_forward(fse_learned *m, int32_t B, const float *x, int32_t bf16, float *y) {
+  if (!m || !x || !y || B < 1 || B > kMaxB) return FSE_E_INVAL;
+  fse_ctx *ctx = m->ctx;
+  hipStream_t s = ctx->stream;
+  FSE_HIP(hipMemcpyAsync(m->x, x, sizeof(float) * B * m->n_in, hipMemcpyHostToDevice, s));
+  if (bf16)
+    forward_bf16(m, B);
+  else
+    forward(m, B);
+  FSE_HIP(hipGetLastError());
+  FSE_HIP(hipMemcpyAsync(y, m->y, sizeof(float) * B * m->rank, hipMemcpyDeviceToHost, s));
+  FSE_HIP(hipStreamSynchronize(s));
+  return FSE_OK;
+}
+
+fse_status fse_learned_predict_batch(fse_learned *m, int32_t P, const double *params, int32_t bf16, double *Z) {
+  if (!m || !params || !Z || P < 1 || P > kMaxB) return FSE_E_INVAL;
+  if (!m->trained) {
+    m->ctx->err = "the learned predictor is not trained";
+    return FSE_E_INVAL;
+  }
+  fse_ctx *ctx = m->ctx;
+  hipStream_t s = ctx->stream;
+  const int nin = m->n_in, R = m->rank;
+  std::vector<float> xf((size_t)P * nin), yf((size_t)P * R);
+  for (int p = 0; p < P; ++p)
+    for (int k = 0; k < nin; ++k)
+      xf[(size_t)p * nin + k] = (float)((params[(size_t)p * nin + k] - m->mu_p[k]) / m->sd_p[k]);
+  FSE_HIP(hipMemcpyAsync(m->x, xf.data(), sizeof(float) * xf.size(), hipMemcpyHostToDevice, s));
+  if (bf16)
+    forward_bf16(m, P);
+  else
+    forward(m, P);
+  FSE_HIP(hipGetLastError());
+  FSE_HIP(hipMemcpyAsync(yf.data(), m->y, sizeof(float) * yf.size(), hipMemcpyDeviceToHost, s));
+  FSE_HIP(hipStreamSynchronize(s));
+  std::vector<double> cv((size_t)P * R);
+  for (int p = 0; p < P; ++p)
+    for (int r = 0; r < R; ++r) cv[(size_t)p * R + r] = m->mu_c[r] + m->sd_c[r] * (double)yf[(size_t)p * R + r];
+  double *cd = nullptr;
+  if (hipMalloc((void **)&cd, sizeof(double) * cv.size()) != hipSuccess) {
+    ctx->err = "hipMalloc failed for the batch coefficients";
+    return FSE_E_NOMEM;
+  }
+  hipError_t e = hipMemcpyAsync(cd, cv.data(), sizeof(double) * cv.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    const size_t tot = (size_t)P * m->N;
+    hipLaunchKernelGGL(k_pod_expand_batch, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, P, m->N, R, m->mean,
+                       m->modes, cd, Z);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(cd);
+  FSE_HIP(e);
   return FSE_OK;
 }
 

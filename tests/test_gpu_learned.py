@@ -170,3 +170,55 @@ def test_learned_predictor_gains_over_secant():
             f"of the points)")
     assert results["shuffled"][1] < results["shuffled"][0]
     assert results["serpentine"][1] <= results["serpentine"][0] + 0.05
+
+
+@pytest.mark.parametrize("sizes,B", [((3, 256, 256, 64), 100), ((3, 40, 40, 10), 7)])
+def test_bf16_mfma_forward_matches_the_bf16_oracle(sizes, B):
+    """BF16 matrix-core inference: equal to the oracle's forward with bfloat16-rounded
+    weights and layer inputs up to FP32 accumulation (which can move a layer input to the
+    neighbouring bfloat16), and within bfloat16 accuracy of the FP32 network (ragged tiles:
+    B and the widths are not multiples of 16)."""
+    s, tr, ctx = _ctx(K=6, S=16)
+    lp = fse().fse_learned_create(ctx, n_in=sizes[0], hidden=sizes[1], rank=sizes[3])
+    params = olearn.mlp_init(sizes, seed=11)
+    flat = _flat(params).astype(np.float32)
+    lp.set_params(flat)
+    p32 = _unflat(flat, sizes)
+    x = np.random.default_rng(13).normal(size=(B, sizes[0])).astype(np.float32)
+    yb = lp.forward(x, bf16=True).astype(np.float64)
+    yf = lp.forward(x, bf16=False).astype(np.float64)
+    ob = olearn.mlp_forward_bf16(p32, x.astype(np.float64))
+    of, _ = olearn.mlp_forward(p32, x.astype(np.float64))
+    eb = np.linalg.norm(yb - ob) / np.linalg.norm(ob)
+    ef = np.linalg.norm(yb - of) / np.linalg.norm(of)
+    log(f"sizes {sizes} B={B}: bf16 MFMA vs bf16 oracle {eb:.2e}, vs FP32 network {ef:.2e}, "
+        f"FP32 path vs oracle {np.linalg.norm(yf - of) / np.linalg.norm(of):.2e}")
+    # FP32 sums may round a layer input to the neighbouring bfloat16 now and then
+    assert eb < 1e-3
+    assert ef < 3e-2
+
+
+def test_batch_prediction_matches_single_predictions():
+    """predict_batch (FP32) equals predict point by point; the BF16 batch agrees to
+    bfloat16 accuracy on the POD coefficients."""
+    s, tr, ctx = _ctx(K=6, S=16)
+    N = 2 * ctx.n * ctx.U
+    rng = np.random.default_rng(21)
+    P = np.column_stack([np.linspace(0.4, 0.6, 24), np.full(24, GOLDEN), np.linspace(0.1, 0.3, 24)])
+    X = np.array([np.sin(3 * p[0]) * np.cos(np.arange(N) * p[2]) + p[2] * np.arange(N) / N for p in P])
+    lp = fse().fse_learned_create(ctx, n_in=3, hidden=32, rank=8)
+    lp.set_params(_flat(olearn.mlp_init((3, 32, 32, 8), seed=3)).astype(np.float32))
+    lp.fit_pod(X)
+    lp.train(P, X, epochs=200, lr=1e-3, wd=1e-5)
+    Q = P[::5] + 0.003
+    Zb = lp.predict_batch(Q).cpu().numpy()
+    Zs = np.stack([lp.predict(q).cpu().numpy() for q in Q])
+    assert np.abs(Zb - Zs).max() <= 1e-12 * np.abs(Zs).max()
+    Zh = lp.predict_batch(Q, bf16=True).cpu().numpy()
+    mean, modes = lp.get_pod()
+    mean, modes = mean.cpu().numpy(), modes.cpu().numpy()
+    cb = (Zh.reshape(len(Q), -1) - mean) @ modes
+    cs = (Zs.reshape(len(Q), -1) - mean) @ modes
+    err = np.linalg.norm(cb - cs) / np.linalg.norm(cs)
+    log(f"BF16 batch vs FP32 predictions: POD coefficients rel diff {err:.2e}")
+    assert err < 3e-2

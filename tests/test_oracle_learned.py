@@ -54,3 +54,19 @@ def test_gelu_reference_values():
     # GELU(x) = x Phi(x): Phi(1) = 0.841344746..., Phi(-1) = 0.158655253...
     assert np.isclose(learned.gelu(np.array(1.0)), 0.8413447460685429, rtol=1e-14)
     assert np.isclose(learned.gelu(np.array(-1.0)), -0.15865525393145707, rtol=1e-14)
+
+
+def test_bf16_rounding_hand_worked_values():
+    """bfloat16 keeps 8 significand bits: spacing 2^-7 on [1, 2)."""
+    from oracle.learned import bf16_round
+    cases = {1.0: 1.0, 1.0 + 2.0 ** -7: 1.0 + 2.0 ** -7,
+             1.0 + 2.0 ** -8: 1.0,                       # tie, even stays
+             1.0 + 3 * 2.0 ** -8: 1.0 + 2.0 ** -6,       # tie, odd rounds up
+             1.0 + 2.0 ** -8 + 2.0 ** -12: 1.0 + 2.0 ** -7,
+             -3.0: -3.0, 0.0: 0.0, 65536.0 + 128.0: 65536.0, 65536.0 + 384.0: 65536.0 + 512.0}
+    for x, r in cases.items():
+        assert bf16_round(x) == r, (x, bf16_round(x), r)
+    v = np.random.default_rng(0).normal(size=1000)
+    rv = bf16_round(v)
+    assert np.all(np.abs(rv - v) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-7))
+    assert np.array_equal(bf16_round(rv), rv)
