@@ -14,6 +14,10 @@
 
 namespace {
 
+// LDS-qualified element type: the serial factor and solve routines below are not always
+// inlined, and a generic pointer argument would make every access a flat instruction.
+typedef __attribute__((address_space(3))) double lds_double;
+
 // Order LDS traffic between the lanes of one wave (LDS operations of a wave are
 // executed in issue order; this keeps the compiler from reordering across it).
 __device__ inline void wave_sync() {
@@ -27,15 +31,28 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// Polynomial forces staged in LDS: row pointers, packed indices and values.
-struct TensLds {
-  const int *p2, *p3;
-  const uint32_t *i2, *i3;
-  const double *v2, *v3;
+// Polynomial forces: row pointers, packed indices and values.  TensLds points to LDS (the
+// staged copy of the fused kernel), TensGlb to global memory; the address space is part of the
+// type so that no access goes through a generic pointer.
+typedef __attribute__((address_space(3))) int lds_int;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(1))) const int glb_int;
+typedef __attribute__((address_space(1))) const uint32_t glb_u32;
+typedef __attribute__((address_space(1))) const double glb_double;
+
+template <typename I, typename W, typename D>
+struct TensT {
+  const I *p2, *p3;
+  const W *i2, *i3;
+  const D *v2, *v3;
 };
+using TensLds = TensT<lds_int, lds_u32, lds_double>;
+using TensGlb = TensT<glb_int, glb_u32, glb_double>;
 
 // f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l over row i (four partial sums)
-__device__ inline double fnl_row(const TensLds &t, const double *q, int i) {
+template <typename TL>
+__device__ inline double fnl_row(const TL &t, const double *q_, int i) {
+  const lds_double *q = (const lds_double *)q_;  // q is in LDS for every caller
   double f[4] = {0.0, 0.0, 0.0, 0.0};
   const int a0 = t.p2[i], a1 = t.p2[i + 1];
   int p = a0;
@@ -70,11 +87,15 @@ __device__ inline double fnl_row(const TensLds &t, const double *q, int i) {
 // rows: the lane of row i owns the entries (i, i - r), so no two lanes write the same
 // word.  K_t(i, m) = d f_i / d q_m collects the terms of row i whose index set holds m
 // (entries with m > i are the transposes of lower entries of a symmetric tangent).
-template <int BW>
-__device__ void assemble_T(const TensLds &t, int n, const double *__restrict__ Sp, const double *q,
+template <int BW, typename TL>
+__device__ void assemble_T(const TL t, int n, const double *__restrict__ Sp_, const double *q_,
                            double *Fp, int lane) {
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  double *F = Fp + BW * bp;
+  // q and the factor are in LDS and the band in global memory for every caller
+  typedef __attribute__((address_space(1))) const double gcdouble;
+  gcdouble *Sp = (gcdouble *)Sp_;
+  const lds_double *q = (const lds_double *)q_;
+  lds_double *F = (lds_double *)Fp + BW * bp;
   for (int i = lane; i < n; i += 64) {
 #pragma unroll
     for (int r = 0; r <= BW; ++r) {
@@ -102,9 +123,9 @@ __device__ void assemble_T(const TensLds &t, int n, const double *__restrict__ S
 // In-place banded LDL^T by one lane with a register window (padded storage, see
 // file header).  Returns false on a zero or non-finite pivot.
 template <int BW>
-__device__ bool ldlt_serial_shift(double *Fp, int n) {
+__device__ bool ldlt_serial_shift(lds_double *Fp, int n) {
   constexpr int bp = BW + 1;
-  double *F = Fp + BW * bp;
+  lds_double *F = Fp + BW * bp;
   double Wn[BW + 1][BW + 1];
 #pragma unroll
   for (int r = 0; r <= BW; ++r)
@@ -142,9 +163,9 @@ __device__ bool ldlt_serial_shift(double *Fp, int n) {
 // are loaded while the current row is reduced, and the term with the most recent
 // unknown is applied last, so each row adds one dependent FMA to the critical path.
 template <int BW>
-__device__ void ldlt_solve_shift(const double *Fp, int n, double *x) {
+__device__ void ldlt_solve_shift(const lds_double *Fp, int n, lds_double *x) {
   constexpr int bp = BW + 1;
-  const double *F = Fp + BW * bp;
+  const lds_double *F = Fp + BW * bp;
   double yw[BW], cf[BW + 1], cn[BW + 1];
 #pragma unroll
   for (int t = 0; t < BW; ++t) yw[t] = 0.0;
@@ -209,9 +230,9 @@ __device__ void ldlt_solve_shift(const double *Fp, int n, double *x) {
 // never moves between registers.  The row entering the window after column j (row
 // j + P) is loaded at the end of column j, one column ahead of its first use.
 template <int BW>
-__device__ bool ldlt_serial_ring(double *Fp, int n) {
+__device__ bool ldlt_serial_ring(lds_double *Fp, int n) {
   constexpr int P = BW + 1, bp = BW + 1;
-  double *F = Fp + BW * bp;
+  lds_double *F = Fp + BW * bp;
   double G[P][P];
 #pragma unroll
   for (int r = 0; r < P; ++r)
@@ -256,9 +277,9 @@ __device__ bool ldlt_serial_ring(double *Fp, int n) {
 // k retires, P steps before they are needed.  The term of the newest unknown is
 // applied last, so each row adds one dependent FMA to the critical path.
 template <int BW>
-__device__ void ldlt_solve_ring(const double *Fp, int n, double *x) {
+__device__ void ldlt_solve_ring(const lds_double *Fp, int n, lds_double *x) {
   constexpr int P = BW + 1, bp = BW + 1;
-  const double *F = Fp + BW * bp;
+  const lds_double *F = Fp + BW * bp;
   double y[P], cf[P][P], xv[P];
   // forward: row i = k, coefficients L(i, i - t) = F[(i - t) bp + t]
 #pragma unroll
@@ -325,20 +346,25 @@ __device__ void ldlt_solve_ring(const double *Fp, int n, double *x) {
   }
 }
 
+// Both take LDS pointers (passed as generic pointers): the cast makes every access inside an
+// LDS instruction, whether or not the call is inlined.
 template <int BW>
 __device__ bool ldlt_serial(double *Fp, int n) {
+  lds_double *F = (lds_double *)Fp;
   if constexpr (BW <= 6)
-    return ldlt_serial_ring<BW>(Fp, n);
+    return ldlt_serial_ring<BW>(F, n);
   else
-    return ldlt_serial_shift<BW>(Fp, n);
+    return ldlt_serial_shift<BW>(F, n);
 }
 
 template <int BW>
 __device__ void ldlt_solve_serial(const double *Fp, int n, double *x) {
+  const lds_double *F = (const lds_double *)Fp;
+  lds_double *xl = (lds_double *)x;
   if constexpr (BW <= 6)
-    ldlt_solve_ring<BW>(Fp, n, x);
+    ldlt_solve_ring<BW>(F, n, xl);
   else
-    ldlt_solve_shift<BW>(Fp, n, x);
+    ldlt_solve_shift<BW>(F, n, xl);
 }
 
 }  // namespace

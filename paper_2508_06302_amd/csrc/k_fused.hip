@@ -110,9 +110,16 @@ constexpr double kChordBound = 1e-2;
 // forward-substituted with the unit lower factor.  Pass B walks back down: D^-1 and the
 // backward substitution, then the Newmark update of [Q; U; A].
 template <int BW, typename CT>
-__device__ void sens_step(const double *F, const double *__restrict__ Mwp, const double *__restrict__ Dwp,
-                          int n, int n2, double c0, double c1, double c2, CT *__restrict__ Qc,
-                          CT *__restrict__ Uc, CT *__restrict__ Ac, CT *__restrict__ Yc) {
+__device__ void sens_step(const double *F_, const double *__restrict__ Mwp_, const double *__restrict__ Dwp_,
+                          int n, int n2, double c0, double c1, double c2, CT *__restrict__ Qc_,
+                          CT *__restrict__ Uc_, CT *__restrict__ Ac_, CT *__restrict__ Yc_) {
+  // The factor lives in LDS and the column state and bands in global memory; typed pointers
+  // keep every access an LDS or a global instruction where the call is not inlined.
+  typedef __attribute__((address_space(1))) CT gCT;
+  typedef __attribute__((address_space(1))) const double gcdouble;
+  const lds_double *F = (const lds_double *)F_;
+  gcdouble *Mwp = (gcdouble *)Mwp_, *Dwp = (gcdouble *)Dwp_;
+  gCT *Qc = (gCT *)Qc_, *Uc = (gCT *)Uc_, *Ac = (gCT *)Ac_, *Yc = (gCT *)Yc_;
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
   constexpr int NR = kRB + 2 * BW;
   double v1[NR], v2[NR], yw[BW];
@@ -164,8 +171,8 @@ __device__ void sens_step(const double *F, const double *__restrict__ Mwp, const
       const int i = i0 + d;
       double acc = 0.0;
       if (i < n) {
-        const double *mr = Mwp + (size_t)i * W2;
-        const double *dr = Dwp + (size_t)i * W2;
+        gcdouble *mr = Mwp + (size_t)i * W2;
+        gcdouble *dr = Dwp + (size_t)i * W2;
 #pragma unroll
         for (int t = 0; t < W2; ++t) acc += mr[t] * v1[d + t] + dr[t] * v2[d + t];
 #pragma unroll
@@ -277,7 +284,8 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
   int *tp3 = tp2 + (n + 1);
   uint32_t *ti2 = reinterpret_cast<uint32_t *>(tp3 + (n + 1));
   uint32_t *ti3 = ti2 + a.nnz2;
-  const TensLds tl{tp2, tp3, ti2, ti3, tv2, tv3};
+  const TensLds tl{(const lds_int *)tp2, (const lds_int *)tp3, (const lds_u32 *)ti2, (const lds_u32 *)ti3,
+                   (const lds_double *)tv2, (const lds_double *)tv3};
   __shared__ int s_fail_step;
   __shared__ int s_flags;
 

@@ -21,7 +21,7 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // work-group per trajectory: wave 0 forms the right-hand side and solves step k while
 // wave 1 stages the factor and displacements of step k + 1 into the other LDS buffer.
 template <int BW>
-__global__ __launch_bounds__(64) void k_wfactor(TrajParams P, TensLds tl, const double *__restrict__ Sp_all,
+__global__ __launch_bounds__(64) void k_wfactor(TrajParams P, TensGlb tl, const double *__restrict__ Sp_all,
                                                 const double *__restrict__ qhist, int ldw,
                                                 double *__restrict__ Fall, DevStatus *st) {
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(64) void k_wfactor(TrajParams P, TensLds tl, const 
 }
 
 template <int BW>
-__global__ __launch_bounds__(128) void k_wsolve(TrajParams P, TensLds tl, const double *__restrict__ Mb,
+__global__ __launch_bounds__(128) void k_wsolve(TrajParams P, TensGlb tl, const double *__restrict__ Mb,
                                                 const double *__restrict__ Db, const double *__restrict__ Kb,
                                                 const double *__restrict__ Floads, const double *__restrict__ Mwp_all,
                                                 const double *__restrict__ omega, const int32_t *__restrict__ sidx,
@@ -203,7 +203,8 @@ fse_status launch_wsens_bw(fse_ctx *ctx, const TrajParams &P, double *dzT) {
     }
     ctx->wfac_elems = need;
   }
-  const TensLds tl{ctx->f2_ptr, ctx->f3_ptr, ctx->f2_pk, ctx->f3_pk, ctx->f2_v, ctx->f3_v};
+  const TensGlb tl{(glb_int *)ctx->f2_ptr, (glb_int *)ctx->f3_ptr, (glb_u32 *)ctx->f2_pk, (glb_u32 *)ctx->f3_pk,
+                   (glb_double *)ctx->f2_v, (glb_double *)ctx->f3_v};
   const size_t lds_f = sizeof(double) * (fb + n);
   hipLaunchKernelGGL(k_wfactor<BW>, dim3(P.S1, P.W), dim3(64), lds_f, ctx->stream, P, tl, ctx->Sp, ctx->qhist,
                      ctx->Wmax, ctx->wfac, ctx->status_d);
