@@ -87,20 +87,22 @@ __device__ inline double fnl_row(const TL &t, const double *q_, int i) {
 // rows: the lane of row i owns the entries (i, i - r), so no two lanes write the same
 // word.  K_t(i, m) = d f_i / d q_m collects the terms of row i whose index set holds m
 // (entries with m > i are the transposes of lower entries of a symmetric tangent).
-template <int BW, typename TL>
+template <int BW, bool BandLds = false, typename TL>
 __device__ void assemble_T(const TL t, int n, const double *__restrict__ Sp_, const double *q_,
                            double *Fp, int lane) {
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  // q and the factor are in LDS and the band in global memory for every caller
+  // q and the factor are in LDS; the band S is in global memory, or in LDS (BandLds)
   typedef __attribute__((address_space(1))) const double gcdouble;
-  gcdouble *Sp = (gcdouble *)Sp_;
   const lds_double *q = (const lds_double *)q_;
   lds_double *F = (lds_double *)Fp + BW * bp;
   for (int i = lane; i < n; i += 64) {
 #pragma unroll
     for (int r = 0; r <= BW; ++r) {
       const int m = i - r;
-      if (m >= 0) F[m * bp + r] = Sp[(size_t)i * W2 + (BW - r)];
+      if (m >= 0) {
+        const size_t e = (size_t)i * W2 + (BW - r);
+        F[m * bp + r] = BandLds ? ((const lds_double *)Sp_)[e] : ((gcdouble *)Sp_)[e];
+      }
     }
     for (int p = t.p2[i]; p < t.p2[i + 1]; ++p) {
       const uint32_t x = t.i2[p];
@@ -343,6 +345,148 @@ __device__ void ldlt_solve_ring(const lds_double *Fp, int n, lds_double *x) {
 #pragma unroll
       for (int t = 0; t <= BW; ++t) cf[u][t] = F[ir * bp + t];
     }
+  }
+}
+
+// Chord factor in FP32 (half bandwidths up to 6).  The chord matrix of the per-step
+// Newton iteration (Eq. E6) only has to approximate the tangent: the residual stays FP64,
+// so a factor rounded to FP32 changes the contraction of the iteration, not its fixed
+// point.  Storage: rows of 8 floats, [j][0] = 1 / d_j, [j][t] = L(j + t, j) for
+// t = 1..BW, the rest zero; the buffer and the right-hand side are padded with zero rows
+// to chord_rows(n) = round8(n) + 16, so the sweeps run over whole blocks of 8 rows and
+// every prefetch stays inside the buffer without guards.
+typedef __attribute__((address_space(3))) float lds_float;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+
+__host__ __device__ constexpr int chord_rows(int n) { return ((n + 7) & ~7) + 16; }
+
+// FP64 factor (padded column storage) -> FP32 rows, lanes of one wave over rows < n; the
+// padding rows are zeroed once by the caller and never written here.
+template <int BW>
+__device__ void chord_to_f32(const double *Fp, int n, float *C_, int lane) {
+  static_assert(BW <= 7, "FP32 chord rows hold 8 entries");
+  constexpr int bp = BW + 1;
+  const lds_double *F = (const lds_double *)Fp + BW * bp;
+  lds_f32x4 *C = (lds_f32x4 *)C_;
+  for (int j = lane; j < n; j += 64) {
+    float v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = t <= BW ? (float)F[j * bp + t] : 0.0f;
+    C[2 * j] = f32x4{v[0], v[1], v[2], v[3]};
+    C[2 * j + 1] = f32x4{v[4], v[5], v[6], v[7]};
+  }
+}
+
+// Solve (L D L^T) x = x in FP32 by one lane.  Forward sweep right-looking: row j retires
+// y_j from its accumulator and subtracts L(j + t, j) y_j from the next BW accumulators,
+// so each row adds one dependent FMA to the critical path.  Backward sweep left-looking
+// over the same rows: x_i = y_i / d_i - sum_t L(i + t, i) x_{i + t}, the x_{i + 1} term
+// last.  Rows of the factor are loaded 8 rows ahead, x in blocks of 8 (two b128).
+template <int BW>
+__device__ __attribute__((noinline)) void chord_solve_f32(const float *C_, int n_, float *x_) {
+  static_assert(BW <= 6, "the forward ring has 8 slots");
+  const int n = __builtin_amdgcn_readfirstlane(n_);
+  const int nb = (n + 7) & ~7;
+  const lds_f32x4 *C = (const lds_f32x4 *)C_;
+  lds_f32x4 *X = (lds_f32x4 *)x_;
+  float acc[8], cf[8][8], xn[8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const f32x4 a = X[h], b = X[2 + h];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[4 * h + e] = a[e];
+      xn[4 * h + e] = b[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const f32x4 a = C[2 * u], b = C[2 * u + 1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cf[u][e] = a[e];
+      cf[u][4 + e] = b[e];
+    }
+  }
+  for (int j0 = 0; j0 < nb; j0 += 8) {
+    float ys[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float y = acc[u];
+      ys[u] = y;
+#pragma unroll
+      for (int t = 1; t <= BW; ++t) acc[(u + t) & 7] = fmaf(-cf[u][t], y, acc[(u + t) & 7]);
+      acc[u] = xn[u];
+      const f32x4 a = C[2 * (j0 + u + 8)], b = C[2 * (j0 + u + 8) + 1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cf[u][e] = a[e];
+        cf[u][4 + e] = b[e];
+      }
+    }
+    X[j0 / 4] = f32x4{ys[0], ys[1], ys[2], ys[3]};
+    X[j0 / 4 + 1] = f32x4{ys[4], ys[5], ys[6], ys[7]};
+    const f32x4 a = X[j0 / 4 + 4], b = X[j0 / 4 + 5];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xn[e] = a[e];
+      xn[4 + e] = b[e];
+    }
+  }
+  // backward: block i0 = nb - 8, nb - 16, ..., rows i0 + 7 down to i0; xr[i & 7] holds x_i
+  float xr[8], yv[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) xr[e] = 0.0f;
+  {
+    const f32x4 a = X[(nb - 8) / 4], b = X[(nb - 8) / 4 + 1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      yv[e] = a[e];
+      yv[4 + e] = b[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = nb - 1 - u;
+    const f32x4 a = C[2 * i], b = C[2 * i + 1];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cf[u][e] = a[e];
+      cf[u][4 + e] = b[e];
+    }
+  }
+  for (int i0 = nb - 8; i0 >= 0; i0 -= 8) {
+    float yn[8];
+    const int ip = i0 >= 8 ? i0 - 8 : 0;
+    {
+      const f32x4 a = X[ip / 4], b = X[ip / 4 + 1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        yn[e] = a[e];
+        yn[4 + e] = b[e];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int s = 7 - u;  // i = i0 + s, i & 7 = s
+      float acc2 = cf[u][0] * yv[s];
+#pragma unroll
+      for (int t = BW; t >= 2; --t) acc2 = fmaf(-cf[u][t], xr[(s + t) & 7], acc2);
+      const float xi = fmaf(-cf[u][1], xr[(s + 1) & 7], acc2);
+      xr[s] = xi;
+      const int ic = i0 + s - 8 >= 0 ? i0 + s - 8 : 0;
+      const f32x4 a = C[2 * ic], b = C[2 * ic + 1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        cf[u][e] = a[e];
+        cf[u][4 + e] = b[e];
+      }
+    }
+    X[i0 / 4] = f32x4{xr[0], xr[1], xr[2], xr[3]};
+    X[i0 / 4 + 1] = f32x4{xr[4], xr[5], xr[6], xr[7]};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) yv[e] = yn[e];
   }
 }
 

@@ -246,7 +246,9 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
                                                const double *__restrict__ Dwp_all,
                                                const double *__restrict__ Kp) {
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
-  extern __shared__ double smem[];
+  // the chord factor is kept in FP32 for half bandwidths up to 6 (one-lane FP32 solve)
+  constexpr bool kChord32 = BW <= 6;
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   const TrajParams &P = a.P;
   const int n = P.n, n2 = 2 * n;
   const int w = blockIdx.y;
@@ -260,37 +262,54 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
   const double *__restrict__ Dwp = Dwp_all + (size_t)b * n * W2;
 
   const size_t fb = (size_t)(n + BW) * bp;   // one padded factor buffer
+  const int n1 = n + 1;                      // state vector stride
   double *FM = smem;                         // factor of w1^2 M
   double *KtB = FM + fb;                     // lower band of K + K_t(q0) (same padding)
+  // FM and KtB serve the prologue and step 0 only; from step 1 on they hold an LDS copy of
+  // the per-point band S [n][2BW+1] (n (2BW+1) <= 2 fb), read by every residual and assembly
+  double *Sl = FM;
+  const lds_double *SlL = (const lds_double *)Sl;
   double *FT0 = KtB + fb;                    // factors of T(q_k), double buffered
   double *FT1 = FT0 + fb;
-  double *CB0 = FT1 + fb;                    // chord factors T(predicted q), double buffered
-  double *CB1 = CB0 + fb;
+  double *CB0 = FT1 + fb;                    // chord factor T(predicted q): FP64 work buffer,
+  double *CB1 = kChord32 ? CB0 : CB0 + fb;   // double buffered unless the chord is FP32
   double *FR = CB1 + fb;                     // state-wave refresh factor
   double *q = FR + fb;
-  double *u = q + n;
-  double *acc = u + n;
-  double *qn = acc + n;
-  double *bv = qn + n;
-  double *r = bv + n;
-  double *qs0 = r + n;                       // q_k handed to the factor wave
-  double *qs1 = qs0 + n;
-  double *pq0 = qs1 + n;                     // two-step predictions handed to the chord wave
-  double *pq1 = pq0 + n;
-  double *cs = pq1 + n;                      // forcing cosines [8]
+  double *u = q + n1;
+  double *acc = u + n1;
+  double *qn = acc + n1;
+  double *bv = qn + n1;
+  double *r = bv + n1;
+  double *qs0 = r + n1;                      // q_k handed to the factor wave
+  double *qs1 = qs0 + n1;
+  double *pq0 = qs1 + n1;                    // two-step predictions handed to the chord wave
+  double *pq1 = pq0 + n1;
+  double *cs = pq1 + n1;                     // forcing cosines [8]
   double *tv2 = cs + 8;                      // staged polynomial forces
   double *tv3 = tv2 + a.nnz2;
   int *tp2 = reinterpret_cast<int *>(tv3 + a.nnz3);
   int *tp3 = tp2 + (n + 1);
   uint32_t *ti2 = reinterpret_cast<uint32_t *>(tp3 + (n + 1));
   uint32_t *ti3 = ti2 + a.nnz2;
+  // FP32 chord factors (double buffered) and right-hand side, 16-byte aligned
+  const int crows = chord_rows(n);
+  char *const lds0 = reinterpret_cast<char *>(smem);
+  const size_t cfo = ((size_t)(reinterpret_cast<char *>(ti3 + 2 * a.nnz3) - lds0) + 15) & ~(size_t)15;
+  float *CF0 = reinterpret_cast<float *>(lds0 + cfo);
+  float *CF1 = CF0 + 8 * crows;
+  float *RF = CF1 + 8 * crows;
   const TensLds tl{(const lds_int *)tp2, (const lds_int *)tp3, (const lds_u32 *)ti2, (const lds_u32 *)ti3,
                    (const lds_double *)tv2, (const lds_double *)tv3};
+  // the FP32 chord buffers need 16-byte alignment (b128 accesses); without it the chord
+  // iterations use the FP64 factor
+  const bool chord32 = kChord32 && (reinterpret_cast<uintptr_t>(CF0) & 15) == 0;
   __shared__ int s_fail_step;
   __shared__ int s_flags;
 
   // ============================================================ prologue
-  for (int e = threadIdx.x; e < (int)(7 * fb); e += blockDim.x) smem[e] = 0.0;
+  for (int e = threadIdx.x; e < (int)(FR + fb - smem); e += blockDim.x) smem[e] = 0.0;
+  if constexpr (kChord32)
+    for (int e = threadIdx.x; e < 17 * crows; e += blockDim.x) CF0[e] = 0.0f;
   for (int e = threadIdx.x; e <= n; e += blockDim.x) {
     tp2[e] = a.f2_ptr[e];
     tp3[e] = a.f3_ptr[e];
@@ -370,6 +389,10 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
     assemble_T<BW>(tl, n, Sp, qn, CB0, lane);
     wave_sync();
     if (lane == 0 && !ldlt_serial<BW>(CB0, n)) s_flags |= DEV_SINGULAR;
+    if constexpr (kChord32) {
+      wave_sync();
+      chord_to_f32<BW>(CB0, n, CF0, lane);
+    }
   }
   __syncthreads();
 
@@ -388,9 +411,14 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
     if (wave == 0 && k < P.S1) {
       // ---------------- state step k: q_k -> q_{k+1}; chord matrix CB[k&1] = T(q^_{k+1})
       const double *Fc = (k & 1) ? CB1 : CB0;
+      const float *Fc32 = (k & 1) ? CF1 : CF0;
       double *qsn = ((k + 1) & 1) ? qs1 : qs0;
       double *pqn = ((k + 1) & 1) ? pq1 : pq0;
       const double phi1 = (double)(k + 1) * P.h;
+      const bool slds = k >= 1;  // the band copy is in place (this wave writes it in step 1)
+      if (k == 1) {
+        for (int e = lane; e < n * W2; e += 64) Sl[e] = Sp[e];
+      }
       if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s);
       wave_sync();
       for (int i = lane; i < n; i += 64) {
@@ -425,27 +453,47 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
         ++itc;
         if (full) {
           // full Newton: exact tangent at the current iterate
-          assemble_T<BW>(tl, n, Sp, qn, FR, lane);
+          if (slds)
+            assemble_T<BW, true>(tl, n, Sl, qn, FR, lane);
+          else
+            assemble_T<BW>(tl, n, Sp, qn, FR, lane);
           wave_sync();
           if (lane == 0 && !ldlt_serial<BW>(FR, n)) s_flags |= DEV_SINGULAR;
           wave_sync();
         }
+        // the FP32 chord solve serves the chord iterations; full Newton and the refreshed
+        // tangent use the FP64 factor
+        const bool c32 = chord32 && !full && Fcur == Fc;
         for (int i = lane; i < n; i += 64) {
           double v = fnl_row(tl, qn, i) - bv[i];
 #pragma unroll
           for (int t = 0; t < W2; ++t) {
             const int j = i - BW + t;
             if (j < 0 || j >= n) continue;
-            v += Sp[(size_t)i * W2 + t] * qn[j];
+            const size_t e = (size_t)i * W2 + t;
+            v += (slds ? SlL[e] : Sp[e]) * qn[j];
           }
           r[i] = v;
+          if (c32) RF[i] = (float)v;
         }
+        // padding rows of the FP32 right-hand side stay zero even after a non-finite residual
+        if (c32)
+          for (int i = n + lane; i < crows; i += 64) RF[i] = 0.0f;
         wave_sync();
-        if (lane == 0) ldlt_solve_serial<BW>(full ? FR : Fcur, n, r);
+        if (lane == 0) {
+          bool done = false;
+          if constexpr (kChord32) {
+            if (c32) {
+              chord_solve_f32<BW>(Fc32, n, RF);
+              done = true;
+            }
+          }
+          if (!done) ldlt_solve_serial<BW>(full ? FR : Fcur, n, r);
+        }
         wave_sync();
         double nd = 0.0, nq = 0.0;
         for (int i = lane; i < n; i += 64) {
-          const double dq = r[i];
+          const double dq = c32 ? (double)RF[i] : r[i];
           const double v = qn[i] - dq;
           qn[i] = v;
           nd = fmax(nd, fabs(dq));
@@ -477,7 +525,10 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
           conv = true;  // stagnation with a fresh tangent: the noise floor lies above tol
         } else if (finite && !refreshed) {
           // poor contraction: refresh the chord matrix at the current iterate and go on
-          assemble_T<BW>(tl, n, Sp, qn, FR, lane);
+          if (slds)
+            assemble_T<BW, true>(tl, n, Sl, qn, FR, lane);
+          else
+            assemble_T<BW>(tl, n, Sp, qn, FR, lane);
           wave_sync();
           if (lane == 0 && !ldlt_serial<BW>(FR, n)) s_flags |= DEV_SINGULAR;
           wave_sync();
@@ -516,15 +567,25 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
       // ---------------- chord step k: T(q^_{k+2}) -> CB[(k+1)&1]
       double *Cn = ((k + 1) & 1) ? CB1 : CB0;
       const double *qp = (k & 1) ? pq1 : pq0;
-      assemble_T<BW>(tl, n, Sp, qp, Cn, lane);
+      if (k >= 2)
+        assemble_T<BW, true>(tl, n, Sl, qp, Cn, lane);
+      else
+        assemble_T<BW>(tl, n, Sp, qp, Cn, lane);
       wave_sync();
       if (lane == 0 && !ldlt_serial<BW>(Cn, n)) s_flags |= DEV_SINGULAR;
       wave_sync();
+      if constexpr (kChord32) {
+        chord_to_f32<BW>(Cn, n, ((k + 1) & 1) ? CF1 : CF0, lane);
+        wave_sync();
+      }
     } else if (wave == 2 && k >= 1 && k <= P.S1) {
       // ---------------- factor step k: T(q_k) -> FT[k&1]
       double *Fn = (k & 1) ? FT1 : FT0;
       const double *qk = (k & 1) ? qs1 : qs0;
-      assemble_T<BW>(tl, n, Sp, qk, Fn, lane);
+      if (k >= 2)
+        assemble_T<BW, true>(tl, n, Sl, qk, Fn, lane);
+      else
+        assemble_T<BW>(tl, n, Sp, qk, Fn, lane);
       wave_sync();
       if (lane == 0 && !ldlt_serial<BW>(Fn, n)) s_flags |= DEV_SINGULAR;
       wave_sync();
@@ -607,8 +668,12 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
 
 template <int BW>
 size_t fused_lds_bytes(int n, int nnz2, int nnz3) {
-  return sizeof(double) * ((size_t)7 * (n + BW) * (BW + 1) + 10 * (size_t)n + 8 + nnz2 + nnz3) +
-         sizeof(int) * (2 * ((size_t)n + 1) + nnz2 + 2 * (size_t)nnz3);
+  constexpr bool kChord32 = BW <= 6;
+  const size_t base = sizeof(double) * ((size_t)(kChord32 ? 6 : 7) * (n + BW) * (BW + 1) + 10 * ((size_t)n + 1) + 8 +
+                                        nnz2 + nnz3) +
+                      sizeof(int) * (2 * ((size_t)n + 1) + nnz2 + 2 * (size_t)nnz3);
+  const size_t f32 = kChord32 ? sizeof(float) * 17 * (size_t)chord_rows(n) : 0;
+  return ((base + 15) & ~(size_t)15) + f32;
 }
 
 template <int BW>
