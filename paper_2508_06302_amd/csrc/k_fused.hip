@@ -96,7 +96,9 @@ __device__ inline double forcing_cos(const FusedArgs &a, int f, double phi1, con
   return cos(ph + om[f] / om[0] * phi1);
 }
 
-constexpr int kRB = 8;   // rows per block in the sensitivity sweeps
+// rows per block in the sensitivity sweeps: every block is one round trip of loads, so
+// larger blocks keep more bytes in flight; 16 where the registers allow it
+template <int BW> constexpr int rows_per_block() { return BW == 6 ? 16 : 8; }
 // Chord stop: an update below kChordFloor tol |q| ends the step; otherwise the linear
 // error bound must fall below kChordBound tol |q|.
 constexpr double kChordFloor = 1e-3;
@@ -121,6 +123,7 @@ __device__ void sens_step(const double *F_, const double *__restrict__ Mwp_, con
   gcdouble *Mwp = (gcdouble *)Mwp_, *Dwp = (gcdouble *)Dwp_;
   gCT *Qc = (gCT *)Qc_, *Uc = (gCT *)Uc_, *Ac = (gCT *)Ac_, *Yc = (gCT *)Yc_;
   constexpr int bp = BW + 1, W2 = 2 * BW + 1;
+  constexpr int kRB = rows_per_block<BW>();
   constexpr int NR = kRB + 2 * BW;
   double v1[NR], v2[NR], yw[BW];
 #pragma unroll
