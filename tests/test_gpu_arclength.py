@@ -128,6 +128,39 @@ def test_arclength_duffing_through_both_folds():
     assert np.count_nonzero(np.sign(dp[1:]) != np.sign(dp[:-1])) == 2
 
 
+def test_stability_changes_at_the_folds_along_the_branch():
+    """Stability along the continued branch (App. C with App. F): the largest Lyapunov
+    exponent of every GPU arclength point equals the oracle's (1e-6), is -D/2 on the stable
+    branches of the damped Duffing oscillator, and changes sign exactly where omega_1 turns
+    (a fold: one Floquet multiplier crosses +1)."""
+    from oracle import lyapunov as oly
+    s = duffing()
+    tr = Torus(d=1, e=1, K=[], S=[], S1=64)
+    tb = osh.TorusTables(tr)
+    om0 = np.array([0.6])
+    Z0, _, _ = osh.solve(s, tr, om0, np.zeros((2, 1)), tol_R=1e-13, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    Z, om, steps, it, rn = fse().fse_arclength(ctx, om0, Z0, 0.15, 26, tol=1e-12, maxit=8)
+    sig = np.zeros(len(om))
+    for j in range(len(om)):
+        sg = fse().fse_lyapunov(ctx, om[j], Z[j], N_Ly=200)
+        sig[j] = np.max(sg)
+        if j % 5 == 0:
+            ref = osh.evaluate(s, tr, om[j], Z[j].cpu().numpy(), sens=True, tables=tb)
+            sref = oly.exponents(ref["Phi"], om[j], tb, N_Ly=200)[1]
+            assert np.abs(np.sort(sg)[::-1] - sref).max() < 1e-6, j
+    log(f"sigma_max along the branch {np.round(sig, 4).tolist()}")
+    dp = np.diff(om[:, 0])
+    folds = np.nonzero(np.sign(dp[1:]) != np.sign(dp[:-1]))[0] + 1
+    flips = np.nonzero(np.sign(sig[1:]) != np.sign(sig[:-1]))[0]
+    assert len(folds) == 2 and len(flips) == 2
+    # the sign flips between the fold point and its neighbour on the unstable side
+    assert all(f in (fl, fl + 1) for f, fl in zip(folds, flips)), (folds, flips)
+    assert sig[0] < 0 and sig[-1] < 0 and np.all(sig[folds[0] + 1:folds[1]] > 0)
+    stable = np.r_[0:folds[0] - 1, folds[1] + 2:len(sig)]
+    assert np.abs(sig[stable] + 0.05).max() < 2e-3  # -D/2 with D = 0.1
+
+
 def test_arclength_quasi_periodic_d2_matches_oracle():
     """3-DOF system, d = e = 2 (forcing ratio the golden mean): six points of the
     quasi-periodic branch in omega_1, GPU against the oracle."""
