@@ -56,6 +56,8 @@ class Torus:
     K: list                 # d-1 int arrays of positive harmonic orders k_j (ascending)
     S: list                 # d-1 sample counts S_j
     S1: int                 # Newmark steps per 2*pi of phi_1
+    beta: float = 0.25      # Newmark parameters; App. E uses the average acceleration (1/4, 1/2)
+    gamma: float = 0.5
 
     @property
     def U(self) -> int:

@@ -151,6 +151,14 @@ fse_status fse_newton_step(fse_ctx *ctx, double *omega, double *Z0, double *res_
 fse_status fse_newton_solve(fse_ctx *ctx, double *omega, double *Z0, double tol,
                             int32_t maxit, int32_t *iters, double *res_norm);
 
+/* Newmark rule of the trajectory integration (App. E uses the average acceleration,
+ * beta = 1/4, gamma = 1/2, the default; other values are the general rule named in the
+ * paper's outlook): q_{k+1} = q_k + h u_k + h^2 ((1/2 - beta) a_k + beta a_{k+1}),
+ * u_{k+1} = u_k + h ((1 - gamma) a_k + gamma a_{k+1}).  Unconditionally stable for
+ * 2 beta >= gamma >= 1/2; gamma > 1/2 damps numerically.  Applies to every later call
+ * (states, sensitivities, d/d omega).  FSE_E_INVAL unless beta > 0 and gamma > 0, finite. */
+fse_status fse_set_newmark(fse_ctx *ctx, double beta, double gamma);
+
 /* Forcing amplitudes: the load vectors of Eq. (25) become amp_i F_i, with the F given
  * to fse_init_torus as amplitude 1 (the paper's examples list the amplitudes f_i in
  * Sec. 4, Tables 1-4).  amp: HOST [e].  Applies to every later call. */

@@ -43,7 +43,8 @@ def evaluate(sysm, torus, omega, zbar0, sens=False, tables=None, tol=1e-12, maxi
     Phi = np.empty((tb.Stilde, z0.shape[0], z0.shape[0])) if sens else None
     for s in range(tb.Stilde):
         out = newmark.integrate(sysm, omega, torus.S1, tb.phases[:, s], z0[:, s], sens=sens, tol=tol,
-                                maxit=maxit)
+                                maxit=maxit, beta=getattr(torus, "beta", 0.25),
+                                gamma=getattr(torus, "gamma", 0.5))
         zT[:, s] = out["zT"]
         if sens:
             Phi[s] = out["Phi"]

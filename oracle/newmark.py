@@ -95,12 +95,18 @@ def _solve(A, B):
 
 def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
               omega_sens: bool = False, tol: float = 1e-12, maxit: int = 30,
-              q_scale: float = 0.0, history: bool = False):
+              q_scale: float = 0.0, history: bool = False, beta: float = 0.25, gamma: float = 0.5,
+              general: bool = False):
     """Integrate one trajectory from phi_1 = 0 to 2 pi in S1 Newmark steps.
 
     Returns dict with zT = [q; u](2 pi), Phi (2n x 2n) if sens, dz_domega
     (2n x e) if omega_sens, iters (Newton iterations per step), q_hist if history.
+    (beta, gamma) other than the average-acceleration (1/4, 1/2) of App. E, or general=True,
+    take the general Newmark rule (integrate_general).
     """
+    if general or beta != 0.25 or gamma != 0.5:
+        return integrate_general(sysm, omega, S1, phases, z0, sens=sens, omega_sens=omega_sens, tol=tol,
+                                 maxit=maxit, q_scale=q_scale, history=history, beta=beta, gamma=gamma)
     M, D, K = sysm.M, sysm.D, sysm.K
     n = sysm.n
     omega = np.asarray(omega, dtype=float)
@@ -173,6 +179,111 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
             Qwn = _solve(T, rhs)
             Uwn = c2 * (Qwn - Qw) - Uw
             Awn = c0 * (Qwn - Qw) - c1 * Uw - Aw
+            Qw, Uw, Aw = Qwn, Uwn, Awn
+        q, u, a = qn, un, an
+        if history:
+            qh.append(q.copy())
+    out = {"zT": np.concatenate([q, u]), "iters": iters, "aT": a}
+    if sens:
+        out["Phi"] = np.vstack([Q, U])
+    if omega_sens:
+        out["dz_domega"] = np.vstack([Qw, Uw])
+    if history:
+        out["q_hist"] = np.array(qh)
+    return out
+
+
+def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omega_sens: bool = False,
+                      tol: float = 1e-12, maxit: int = 30, q_scale: float = 0.0, history: bool = False,
+                      beta: float = 0.25, gamma: float = 0.5):
+    """The same trajectory with the general Newmark rule (the paper's future-work item 3;
+    App. E is its case beta = 1/4, gamma = 1/2).  Newmark's two relations, in phi_1:
+        q_{k+1} = q_k + h u_k + h^2 ((1/2 - beta) a_k + beta a_{k+1}),
+        u_{k+1} = u_k + h ((1 - gamma) a_k + gamma a_{k+1}),
+    so with p_k = q_k + h u_k + h^2 (1/2 - beta) a_k and v_k = u_k + h (1 - gamma) a_k,
+        a_{k+1} = (q_{k+1} - p_k) / (beta h^2),  u_{k+1} = v_k + gamma h a_{k+1},
+    and the equation of motion at phi_{k+1} is solved for q_{k+1} by full-tangent Newton with
+    the tangent T = w1^2 M / (beta h^2) + w1 D gamma / (beta h) + K + K_t(q_{k+1}).  The
+    sensitivities differentiate these relations at the converged step: T dq_{k+1} =
+    w1^2 M dp / (beta h^2) + w1 D (gamma / (beta h) dp - dv), and the same for d/d omega with
+    the explicit terms -(2 w1 M a_{k+1} + D u_{k+1}) (omega_1 only) and d e / d omega."""
+    M, D, K = sysm.M, sysm.D, sysm.K
+    n = sysm.n
+    omega = np.asarray(omega, dtype=float)
+    w1 = omega[0]
+    h = 2.0 * math.pi / S1
+    ca = 1.0 / (beta * h * h)          # d a_{k+1} / d q_{k+1}
+    cu = gamma / (beta * h)            # d u_{k+1} / d q_{k+1}
+    Mw = w1 ** 2 * M
+    S = ca * Mw + cu * w1 * D + K
+    q = np.array(z0[:n], dtype=float)
+    u = np.array(z0[n:], dtype=float)
+    a = _solve(Mw, forcing(sysm, omega, phases, 0.0) - w1 * D @ u - K @ q - internal_force(sysm, q))
+    if sens:
+        Q = np.hstack([np.eye(n), np.zeros((n, n))])
+        U = np.hstack([np.zeros((n, n)), np.eye(n)])
+        A = -_solve(Mw, np.hstack([K + tangent(sysm, q), w1 * D]))
+    ne = sysm.e
+    if omega_sens:
+        Qw = np.zeros((n, ne))
+        Uw = np.zeros((n, ne))
+        Aw = np.zeros((n, ne))
+        for i in range(1, ne + 1):
+            rhs = forcing_domega(sysm, omega, phases, 0.0, i)
+            if i == 1:
+                rhs = rhs - D @ u - 2.0 * w1 * M @ a
+            Aw[:, i - 1] = _solve(Mw, rhs)
+    iters = np.zeros(S1, dtype=np.int64)
+    qh = [q.copy()] if history else None
+
+    def accel_vel(qn, p, v):
+        an = (qn - p) / (beta * h * h)
+        return an, v + gamma * h * an
+
+    for k in range(S1):
+        phi_next = (k + 1) * h
+        e1 = forcing(sysm, omega, phases, phi_next)
+        p = q + h * u + h * h * (0.5 - beta) * a
+        v = u + h * (1.0 - gamma) * a
+        qn = q + h * u + 0.5 * h * h * a
+        prev = math.inf
+        ok = False
+        for it in range(maxit):
+            an, un = accel_vel(qn, p, v)
+            r = Mw @ an + w1 * D @ un + K @ qn + internal_force(sysm, qn) - e1
+            dq = _solve(S + tangent(sysm, qn), r)
+            qn = qn - dq
+            nd = float(np.max(np.abs(dq)))
+            scale = max(float(np.max(np.abs(qn))), q_scale)
+            iters[k] = it + 1
+            if nd <= tol * scale or (nd <= 1e3 * tol * scale and nd > 0.5 * prev):
+                ok = True
+                break
+            prev = nd
+        if not ok:
+            raise StepNewtonError(f"step Newton did not converge at step {k}")
+        an, un = accel_vel(qn, p, v)
+        if sens or omega_sens:
+            T = S + tangent(sysm, qn)
+        if sens:
+            dP = Q + h * U + h * h * (0.5 - beta) * A
+            dV = U + h * (1.0 - gamma) * A
+            Qn = _solve(T, ca * Mw @ dP + w1 * D @ (cu * dP - dV))
+            An = (Qn - dP) / (beta * h * h)
+            Un = dV + gamma * h * An
+            Q, U, A = Qn, Un, An
+        if omega_sens:
+            dP = Qw + h * Uw + h * h * (0.5 - beta) * Aw
+            dV = Uw + h * (1.0 - gamma) * Aw
+            rhs = ca * Mw @ dP + w1 * D @ (cu * dP - dV)
+            for i in range(1, ne + 1):
+                col = forcing_domega(sysm, omega, phases, phi_next, i)
+                if i == 1:
+                    col = col - 2.0 * w1 * M @ an - D @ un
+                rhs[:, i - 1] += col
+            Qwn = _solve(T, rhs)
+            Awn = (Qwn - dP) / (beta * h * h)
+            Uwn = dV + gamma * h * Awn
             Qw, Uw, Aw = Qwn, Uwn, Awn
         q, u, a = qn, un, an
         if history:

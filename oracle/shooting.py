@@ -52,7 +52,8 @@ def evaluate(sysm, torus, omega, Z0, sens=False, omega_sens=False, tables=None,
     sel = range(tb.Stilde) if samples is None else samples
     for s in sel:
         out = newmark.integrate(sysm, omega, torus.S1, tb.phases[:, s], zbar0[:, s],
-                                sens=sens, omega_sens=omega_sens, tol=tol, maxit=maxit)
+                                sens=sens, omega_sens=omega_sens, tol=tol, maxit=maxit,
+                                beta=getattr(torus, "beta", 0.25), gamma=getattr(torus, "gamma", 0.5))
         zbarT[:, s] = out["zT"]
         iters[s] = out["iters"]
         if sens:

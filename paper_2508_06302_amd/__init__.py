@@ -15,7 +15,7 @@ from . import _lib
 
 __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
-           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing",
+           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing", "fse_set_newmark",
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
            "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
            "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step",
@@ -122,6 +122,9 @@ def fse_init_torus(system, torus, max_batch=1, precision=FSE_PREC_FP64, step_tol
     ctx = Context(h, lib, n, torus.d, U.value, St.value, bw.value, kt[:, : torus.d - 1])
     ctx.e = int(F.shape[0])
     ctx.bind_stream()
+    beta, gamma = getattr(torus, "beta", 0.25), getattr(torus, "gamma", 0.5)
+    if (beta, gamma) != (0.25, 0.5):
+        fse_set_newmark(ctx, beta, gamma)
     return ctx
 
 
@@ -256,6 +259,10 @@ def fse_get_tuning(ctx: Context):
     ms = np.zeros(2, np.float32)
     ctx.check(ctx.lib.fse_get_tuning(ctx.h, C.byref(ncw), _p(ms, C.c_float)))
     return ncw.value, ms
+
+
+def fse_set_newmark(ctx: Context, beta, gamma):
+    ctx.check(ctx.lib.fse_set_newmark(ctx.h, float(beta), float(gamma)))
 
 
 def fse_set_forcing(ctx: Context, amp):

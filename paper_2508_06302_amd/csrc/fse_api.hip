@@ -515,6 +515,17 @@ fse_status integrate_points(fse_ctx *ctx, int B, const double *omega, const doub
 fse_status ensure_phi_buffer(fse_ctx *ctx) { return ensure_phi(ctx); }
 
 // ============================================================================= C-ABI
+void newmark_coefficients(const fse_ctx *ctx, TrajParams &p) {
+  const double b = ctx->nm_beta, g = ctx->nm_gamma, h = 2.0 * M_PI / ctx->S1;
+  p.h = h;
+  p.c0 = 1.0 / (b * h * h);
+  p.c1 = 1.0 / (b * h);
+  p.c2 = g / (b * h);
+  p.c3 = 1.0 / (2.0 * b) - 1.0;
+  p.d1 = g / b - 1.0;
+  p.d2 = h * (g / (2.0 * b) - 1.0);
+}
+
 extern "C" {
 
 fse_status fse_init_torus(const fse_system *sys, const fse_torus_desc *desc, fse_ctx **out) {
@@ -756,6 +767,17 @@ fse_status fse_newton_solve(fse_ctx *ctx, double *omega, double *Z0, double tol,
     ctx->err = "Newton did not reach the residual tolerance";
     return FSE_E_NOCONV;
   }
+  return FSE_OK;
+}
+
+fse_status fse_set_newmark(fse_ctx *ctx, double beta, double gamma) {
+  if (!ctx) return FSE_E_INVAL;
+  if (!(beta > 0.0) || !(gamma > 0.0) || !std::isfinite(beta) || !std::isfinite(gamma)) {
+    ctx->err = "Newmark parameters must be finite with beta > 0 and gamma > 0";
+    return FSE_E_INVAL;
+  }
+  ctx->nm_beta = beta;
+  ctx->nm_gamma = gamma;
   return FSE_OK;
 }
 

@@ -43,11 +43,16 @@ struct DevStatus {
 };
 
 // Per-call problem parameters passed to the trajectory kernels by value.
+// Newmark step coefficients (h = 2 pi / S1; beta, gamma of the rule, 1/4 and 1/2 in App. E):
+// a_{k+1} = c0 (q_{k+1} - q_k) - c1 u_k - c3 a_k,  u_{k+1} = c2 (q_{k+1} - q_k) - d1 u_k - d2 a_k,
+// c0 = 1/(beta h^2), c1 = 1/(beta h), c2 = gamma/(beta h), c3 = 1/(2 beta) - 1,
+// d1 = gamma/beta - 1, d2 = h (gamma/(2 beta) - 1); the step matrix is w1^2 c0 M + w1 c2 D + K
+// and its right-hand side e + w1^2 M (c0 q + c1 u + c3 a) + w1 D (c2 q + d1 u + d2 a).
 struct TrajParams {
   int n, bw, S1, e, d, St, W;   // sizes; W = B * St trajectories
   int maxit;
   double tol;
-  double h, c0, c1, c2;
+  double h, c0, c1, c2, c3, d1, d2;
 };
 
 struct fse_ctx {
@@ -59,6 +64,7 @@ struct fse_ctx {
   int n = 0, e = 0, d = 0, S1 = 0, U = 0, L = 0, St = 0, bw = 0;
   int Bmax = 1, prec = 0, maxit = 30;
   double tol = 1e-12;
+  double nm_beta = 0.25, nm_gamma = 0.5;  // Newmark rule
   int Wmax = 0;
   int nnz2 = 0, nnz3 = 0;
 
@@ -177,6 +183,7 @@ fse_status launch_dRdp_rot(fse_ctx *ctx, int B, const double *omega, const doubl
 fse_status launch_set_pcol(fse_ctx *ctx, double *A, size_t ldA, const double *col);
 // Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16
 bool fused_supported(const fse_ctx *ctx);
+void newmark_coefficients(const fse_ctx *ctx, TrajParams &p);  // h, c0 .. d2
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);
 // compile-time half bandwidth (4, 6, 8, 12 or 16) the fused kernels use for this system
 int fused_band_bucket(const fse_ctx *ctx);

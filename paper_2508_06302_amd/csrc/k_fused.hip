@@ -108,12 +108,13 @@ constexpr double kChordBound = 1e-2;
 // [Q; U; A] and the solve scratch Y are stored as CT (double, or float for the mixed
 // path); arithmetic is FP64.  Pass A walks the rows upwards in blocks of kRB: the block's
 // rows of Q, U, A are loaded together (the 2 BW rows of overlap stay in registers), the
-// right-hand side w1^2 M (c0 Q + c1 U + A) + w1 D (c2 Q + U) is formed and immediately
+// right-hand side w1^2 M (c0 Q + c1 U + c3 A) + w1 D (c2 Q + d1 U + d2 A) is formed and immediately
 // forward-substituted with the unit lower factor.  Pass B walks back down: D^-1 and the
 // backward substitution, then the Newmark update of [Q; U; A].
 template <int BW, typename CT>
 __device__ void sens_step(const double *F_, const double *__restrict__ Mwp_, const double *__restrict__ Dwp_,
-                          int n, int n2, double c0, double c1, double c2, CT *__restrict__ Qc_,
+                          int n, int n2, double c0, double c1, double c2, double c3, double d1, double d2,
+                          CT *__restrict__ Qc_,
                           CT *__restrict__ Uc_, CT *__restrict__ Ac_, CT *__restrict__ Yc_) {
   // The factor lives in LDS and the column state and bands in global memory; typed pointers
   // keep every access an LDS or a global instruction where the call is not inlined.
@@ -145,8 +146,8 @@ __device__ void sens_step(const double *F_, const double *__restrict__ Mwp_, con
       const bool in = t < n;
       const double Qj = in ? (double)Qn[t] : 0.0, Uj = in ? (double)Un[t] : 0.0;
       const double Aj = in ? (double)An[t] : 0.0;
-      v1[BW + t] = c0 * Qj + c1 * Uj + Aj;
-      v2[BW + t] = c2 * Qj + Uj;
+      v1[BW + t] = c0 * Qj + c1 * Uj + c3 * Aj;
+      v2[BW + t] = c2 * Qj + d1 * Uj + d2 * Aj;
     }
   }
   for (int i0 = 0; i0 < n; i0 += kRB) {
@@ -165,8 +166,8 @@ __device__ void sens_step(const double *F_, const double *__restrict__ Mwp_, con
       const bool in = i0 + BW + d < n;
       const double Qj = in ? (double)Qn[d] : 0.0, Uj = in ? (double)Un[d] : 0.0;
       const double Aj = in ? (double)An[d] : 0.0;
-      v1[2 * BW + d] = c0 * Qj + c1 * Uj + Aj;
-      v2[2 * BW + d] = c2 * Qj + Uj;
+      v1[2 * BW + d] = c0 * Qj + c1 * Uj + c3 * Aj;
+      v2[2 * BW + d] = c2 * Qj + d1 * Uj + d2 * Aj;
     }
     double yb[kRB];
 #pragma unroll
@@ -236,8 +237,8 @@ __device__ void sens_step(const double *F_, const double *__restrict__ Mwp_, con
       const int i = i0 + d;
       if (i >= n) continue;
       const double dQ = yb[d] - qb[d];
-      Uc[(size_t)i * n2] = (CT)(c2 * dQ - ub[d]);
-      Ac[(size_t)i * n2] = (CT)(c0 * dQ - c1 * ub[d] - ab[d]);
+      Uc[(size_t)i * n2] = (CT)(c2 * dQ - d1 * ub[d] - d2 * ab[d]);
+      Ac[(size_t)i * n2] = (CT)(c0 * dQ - c1 * ub[d] - c3 * ab[d]);
       Qc[(size_t)i * n2] = (CT)yb[d];
     }
   }
@@ -431,8 +432,8 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
         for (int t = 0; t < W2; ++t) {
           const int j = i - BW + t;
           if (j < 0 || j >= n) continue;
-          v += Mwp[(size_t)i * W2 + t] * (P.c0 * q[j] + P.c1 * u[j] + acc[j]) +
-               Dwp[(size_t)i * W2 + t] * (P.c2 * q[j] + u[j]);
+          v += Mwp[(size_t)i * W2 + t] * (P.c0 * q[j] + P.c1 * u[j] + P.c3 * acc[j]) +
+               Dwp[(size_t)i * W2 + t] * (P.c2 * q[j] + P.d1 * u[j] + P.d2 * acc[j]);
         }
         bv[i] = v;
         qn[i] = q[i] + P.h * u[i] + 0.5 * P.h * P.h * acc[i];
@@ -555,8 +556,8 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
       tot_it += it;
       for (int i = lane; i < n; i += 64) {
         const double dqk = qn[i] - q[i];
-        const double un = P.c2 * dqk - u[i];
-        const double an = P.c0 * dqk - P.c1 * u[i] - acc[i];
+        const double un = P.c2 * dqk - P.d1 * u[i] - P.d2 * acc[i];
+        const double an = P.c0 * dqk - P.c1 * u[i] - P.c3 * acc[i];
         u[i] = un;
         acc[i] = an;
         q[i] = qn[i];
@@ -634,7 +635,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
     } else if (colw && k >= 2) {
       // ---------------- sensitivity step k-2 -> k-1 with the factor of T(q_{k-1})
       const double *F = (((k - 1) & 1) ? FT1 : FT0) + BW * bp;
-      sens_step<BW, CT>(F, Mwp, Dwp, n, n2, P.c0, P.c1, P.c2, Qc, Uc, Ac, Yc);
+      sens_step<BW, CT>(F, Mwp, Dwp, n, n2, P.c0, P.c1, P.c2, P.c3, P.d1, P.d2, Qc, Uc, Ac, Yc);
     }
     __syncthreads();
   }
@@ -796,10 +797,7 @@ fse_status launch_fused(fse_ctx *ctx, int B, double *Phi) {
   p.W = B * ctx->St;
   p.maxit = ctx->maxit;
   p.tol = ctx->tol;
-  p.h = 2.0 * M_PI / ctx->S1;
-  p.c0 = 4.0 / (p.h * p.h);
-  p.c1 = 4.0 / p.h;
-  p.c2 = 2.0 / p.h;
+  newmark_coefficients(ctx, p);
   if (Phi && !ctx->PhiA) {
     const size_t sz = sizeof(double) * ctx->Wmax * (size_t)ctx->n * 2 * ctx->n;
     if (hipMalloc((void **)&ctx->PhiA, sz) != hipSuccess || hipMalloc((void **)&ctx->sens_scr, sz) != hipSuccess) {

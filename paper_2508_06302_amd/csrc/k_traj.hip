@@ -266,8 +266,8 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
       for (int t = 0; t < W2; ++t) {
         const int j = j0 + t;
         if (j < 0 || j >= n) continue;
-        v += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * q[j] + P.c1 * u[j] + a[j]) +
-             w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * q[j] + u[j]);
+        v += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * q[j] + P.c1 * u[j] + P.c3 * a[j]) +
+             w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * q[j] + P.d1 * u[j] + P.d2 * a[j]);
       }
       bv[i] = v;
       qn[i] = q[i] + P.h * u[i] + 0.5 * P.h * P.h * a[i];
@@ -328,8 +328,8 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
     // Eq. (E5) and the history for the sensitivity pass
     for (int i = tid; i < n; i += nt) {
       const double dqk = qn[i] - q[i];
-      const double un = P.c2 * dqk - u[i];
-      const double an = P.c0 * dqk - P.c1 * u[i] - a[i];
+      const double un = P.c2 * dqk - P.d1 * u[i] - P.d2 * a[i];
+      const double an = P.c0 * dqk - P.c1 * u[i] - P.c3 * a[i];
       u[i] = un;
       a[i] = an;
       q[i] = qn[i];
@@ -446,8 +446,8 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
           const int j = j0 + t;
           if (j < 0 || j >= n) continue;
           const double Qj = Qc[(size_t)j * n2], Uj = Uc[(size_t)j * n2], Aj = Ac[(size_t)j * n2];
-          rhs += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * Qj + P.c1 * Uj + Aj) +
-                 w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * Qj + Uj);
+          rhs += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * Qj + P.c1 * Uj + P.c3 * Aj) +
+                 w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * Qj + P.d1 * Uj + P.d2 * Aj);
         }
         const int t0 = i < bw ? i : bw;
         for (int t = 1; t <= t0; ++t) rhs -= Lf[(i - t) * bp + t] * Yc[(size_t)(i - t) * n2];
@@ -460,8 +460,8 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
         Yc[(size_t)i * n2] = x;
         const double Qo = Qc[(size_t)i * n2], Uo = Uc[(size_t)i * n2], Ao = Ac[(size_t)i * n2];
         const double dQ = x - Qo;
-        Uc[(size_t)i * n2] = P.c2 * dQ - Uo;
-        Ac[(size_t)i * n2] = P.c0 * dQ - P.c1 * Uo - Ao;
+        Uc[(size_t)i * n2] = P.c2 * dQ - P.d1 * Uo - P.d2 * Ao;
+        Ac[(size_t)i * n2] = P.c0 * dQ - P.c1 * Uo - P.c3 * Ao;
         Qc[(size_t)i * n2] = x;
       }
     }
@@ -559,9 +559,9 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
         const int j = i - bw + t;
         if (j < 0 || j >= n) continue;
         const double Mij = sy.Mb[(size_t)i * W2 + t], Dij = sy.Db[(size_t)i * W2 + t];
-        v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + Uw[j]);
+        v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + P.c3 * Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + P.d1 * Uw[j] + P.d2 * Aw[j]);
         v += -(2.0 * w1 * P.c0 * Mij + P.c2 * Dij) * qn[j] +
-             2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + a[j]) + Dij * (P.c2 * q[j] + u[j]);
+             2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + P.c3 * a[j]) + Dij * (P.c2 * q[j] + P.d1 * u[j] + P.d2 * a[j]);
       }
       x[i] = v;
     }
@@ -579,14 +579,14 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
     band_solve(Lf, n, bw, x, red);
     for (int i = tid; i < n; i += nt) {
       const double dQ = x[i] - Qw[i];
-      const double uwn = P.c2 * dQ - Uw[i];
-      const double awn = P.c0 * dQ - P.c1 * Uw[i] - Aw[i];
+      const double uwn = P.c2 * dQ - P.d1 * Uw[i] - P.d2 * Aw[i];
+      const double awn = P.c0 * dQ - P.c1 * Uw[i] - P.c3 * Aw[i];
       Qw[i] = x[i];
       Uw[i] = uwn;
       Aw[i] = awn;
       const double dqk = qn[i] - q[i];
-      const double un = P.c2 * dqk - u[i];
-      const double an = P.c0 * dqk - P.c1 * u[i] - a[i];
+      const double un = P.c2 * dqk - P.d1 * u[i] - P.d2 * a[i];
+      const double an = P.c0 * dqk - P.c1 * u[i] - P.c3 * a[i];
       u[i] = un;
       a[i] = an;
       q[i] = qn[i];
@@ -742,10 +742,7 @@ TrajParams params(const fse_ctx *ctx, int B) {
   P.W = B * ctx->St;
   P.maxit = ctx->maxit;
   P.tol = ctx->tol;
-  P.h = 2.0 * M_PI / ctx->S1;
-  P.c0 = 4.0 / (P.h * P.h);
-  P.c1 = 4.0 / P.h;
-  P.c2 = 2.0 / P.h;
+  newmark_coefficients(ctx, P);
   return P;
 }
 

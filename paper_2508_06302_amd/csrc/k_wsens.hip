@@ -151,9 +151,9 @@ __global__ __launch_bounds__(128) void k_wsolve(TrajParams P, TensGlb tl, const 
           const int j = i - bw + t;
           if (j < 0 || j >= n) continue;
           const double Mij = Mb[(size_t)i * W2u + t], Dij = Db[(size_t)i * W2u + t];
-          v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + Uw[j]);
+          v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + P.c3 * Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + P.d1 * Uw[j] + P.d2 * Aw[j]);
           v += -(2.0 * w1 * P.c0 * Mij + P.c2 * Dij) * qn[j] +
-               2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + a[j]) + Dij * (P.c2 * q[j] + u[j]);
+               2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + P.c3 * a[j]) + Dij * (P.c2 * q[j] + P.d1 * u[j] + P.d2 * a[j]);
         }
         x[i] = v;
       }
@@ -162,14 +162,14 @@ __global__ __launch_bounds__(128) void k_wsolve(TrajParams P, TensGlb tl, const 
       wave_sync();
       for (int i = lane; i < n; i += 64) {
         const double dQ = x[i] - Qw[i];
-        const double uwn = P.c2 * dQ - Uw[i];
-        const double awn = P.c0 * dQ - P.c1 * Uw[i] - Aw[i];
+        const double uwn = P.c2 * dQ - P.d1 * Uw[i] - P.d2 * Aw[i];
+        const double awn = P.c0 * dQ - P.c1 * Uw[i] - P.c3 * Aw[i];
         Qw[i] = x[i];
         Uw[i] = uwn;
         Aw[i] = awn;
         const double dqk = qn[i] - q[i];
-        const double un = P.c2 * dqk - u[i];
-        const double an = P.c0 * dqk - P.c1 * u[i] - a[i];
+        const double un = P.c2 * dqk - P.d1 * u[i] - P.d2 * a[i];
+        const double an = P.c0 * dqk - P.c1 * u[i] - P.c3 * a[i];
         u[i] = un;
         a[i] = an;
         q[i] = qn[i];
@@ -238,10 +238,7 @@ fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT) {
   p.W = B * ctx->St;
   p.maxit = ctx->maxit;
   p.tol = ctx->tol;
-  p.h = 2.0 * M_PI / ctx->S1;
-  p.c0 = 4.0 / (p.h * p.h);
-  p.c1 = 4.0 / p.h;
-  p.c2 = 2.0 / p.h;
+  newmark_coefficients(ctx, p);
   switch (BWb) {
     case 4: return launch_wsens_bw<4>(ctx, p, dzT);
     case 6: return launch_wsens_bw<6>(ctx, p, dzT);

@@ -123,3 +123,85 @@ def test_omega_sensitivity_matches_finite_differences(i):
     zp = newmark.integrate(s, omega + e, 40, phases, z0)["zT"]
     zm = newmark.integrate(s, omega - e, 40, phases, z0)["zT"]
     assert np.allclose(out["dz_domega"][:, i - 1], (zp - zm) / (2 * h), rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------- general Newmark (beta, gamma)
+GENERAL = [(1.0 / 6.0, 0.5), (0.3, 0.5), (0.3025, 0.6), (0.4, 0.7)]
+
+
+@pytest.mark.parametrize("sens", [False, True])
+def test_general_rule_at_quarter_half_is_the_average_acceleration_rule(sens):
+    """The general branch, forced at (1/4, 1/2), reproduces App. E's branch (states,
+    sensitivities and omega-derivatives) on a nonlinear two-frequency system."""
+    s = tiny_system(n=3, seed=5, cubic=1.0, quad=0.3)
+    omega = np.array([1.2, 1.2 * 1.4142])
+    phases = np.array([2.1])
+    z0 = 0.2 * np.random.default_rng(1).normal(size=6)
+    a = newmark.integrate(s, omega, 40, phases, z0, sens=sens, omega_sens=sens)
+    b = newmark.integrate(s, omega, 40, phases, z0, sens=sens, omega_sens=sens, general=True)
+    assert np.allclose(a["zT"], b["zT"], rtol=1e-12, atol=1e-14)
+    if sens:
+        assert np.allclose(a["Phi"], b["Phi"], rtol=1e-11, atol=1e-13)
+        assert np.allclose(a["dz_domega"], b["dz_domega"], rtol=1e-11, atol=1e-13)
+
+
+@pytest.mark.parametrize("beta,gamma", GENERAL)
+def test_general_rule_obeys_the_three_term_recurrence(beta, gamma):
+    """Undamped oscillator q'' + W^2 q = 0: eliminating u and a from Newmark's relations gives
+    the textbook three-term recurrence (1 + b x) q_{k+1} - (2 - (1/2 - 2b + g) x) q_k
+    + (1 + (1/2 + b - g) x) q_{k-1} = 0, x = (W h)^2.  The oracle's displacements are
+    c1 l1^k + c2 l2^k with l1, l2 the roots of its characteristic polynomial."""
+    Omega, S1 = 1.7, 48
+    sysm = linear_oscillator(Omega=Omega)
+    out = newmark.integrate(sysm, [1.0], S1, np.zeros(0), np.array([0.6, -0.4]), beta=beta, gamma=gamma,
+                            history=True)
+    qk = out["q_hist"][:, 0]
+    h = 2 * math.pi / S1
+    x = (Omega * h) ** 2
+    lam = np.roots([1 + beta * x, -(2 - (0.5 - 2 * beta + gamma) * x), 1 + (0.5 + beta - gamma) * x])
+    V = np.array([[1.0, 1.0], lam]).astype(complex)
+    c = np.linalg.solve(V, qk[:2].astype(complex))
+    model = (c[None, :] * lam[None, :] ** np.arange(len(qk))[:, None]).sum(axis=1)
+    assert np.abs(model.imag).max() < 1e-12
+    assert np.abs(model.real - qk).max() < 1e-12 * np.abs(qk).max()
+    # no numerical damping at gamma = 1/2, decay above it (|l|^2 = product of the roots)
+    rho2 = (1 + (0.5 + beta - gamma) * x) / (1 + beta * x)
+    assert abs(np.abs(lam).max() ** 2 - rho2) < 1e-14 if gamma > 0.5 else abs(rho2 - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("beta,gamma,order", [(0.3, 0.5, 2), (1.0 / 6.0, 0.5, 2), (0.3025, 0.6, 1)])
+def test_general_rule_order_of_accuracy(beta, gamma, order):
+    """Error against the exact cos(W t) after one period halves like h^2 for gamma = 1/2 and
+    like h for gamma != 1/2 (Newmark's classical accuracy result)."""
+    Omega = 1.3
+    sysm = linear_oscillator(Omega=Omega)
+    errs = []
+    for S1 in (200, 400, 800):
+        out = newmark.integrate(sysm, [1.0], S1, np.zeros(0), np.array([1.0, 0.0]), beta=beta, gamma=gamma)
+        errs.append(abs(out["zT"][0] - math.cos(Omega * 2 * math.pi)))
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(r - order) < 0.15 for r in rates), rates
+
+
+@pytest.mark.parametrize("beta,gamma", [(0.3025, 0.6), (1.0 / 6.0, 0.5)])
+def test_general_rule_sensitivities_match_finite_differences(beta, gamma):
+    s = tiny_system(n=3, seed=7, cubic=2.0, quad=0.5)
+    omega = np.array([1.1, 1.1 * 1.618])
+    phases = np.array([0.9])
+    z0 = 0.3 * np.random.default_rng(7).normal(size=6)
+    out = newmark.integrate(s, omega, 48, phases, z0, sens=True, omega_sens=True, beta=beta, gamma=gamma)
+    hh = 1e-6
+    J = np.zeros((6, 6))
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = hh
+        zp = newmark.integrate(s, omega, 48, phases, z0 + e, beta=beta, gamma=gamma)["zT"]
+        zm = newmark.integrate(s, omega, 48, phases, z0 - e, beta=beta, gamma=gamma)["zT"]
+        J[:, j] = (zp - zm) / (2 * hh)
+    assert np.allclose(out["Phi"], J, rtol=1e-6, atol=1e-7)
+    for i in range(2):
+        e = np.zeros(2)
+        e[i] = hh
+        zp = newmark.integrate(s, omega + e, 48, phases, z0, beta=beta, gamma=gamma)["zT"]
+        zm = newmark.integrate(s, omega - e, 48, phases, z0, beta=beta, gamma=gamma)["zT"]
+        assert np.allclose(out["dz_domega"][:, i], (zp - zm) / (2 * hh), rtol=1e-6, atol=1e-7)
