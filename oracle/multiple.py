@@ -1,0 +1,96 @@
+"""Multiple FSE-Shooting (oracle; test infrastructure only).
+
+The paper recommends a multiple FSE-Shooting method for robustness and a larger convergence
+domain (Sec. 5, first recommendation) without giving its form; this is the classical
+multiple-shooting reading of Sec. 3.  The period of phi_1 is cut into M segments of S1/M
+Newmark steps.  The unknowns are the M sections of the torus at phi_1 = 2 pi m / M,
+Z^(m) [2n][U~] in the basis of Eq. (13) over the phases phi~ of the other frequencies at
+that moment.  Segment m integrates the trajectories that start on section m at the grid
+phases phi~_s (inverse DFT, Eq. 20), with the forcing of frequency 1 starting at phase
+2 pi m / M (the others at phi_{i,s}, Eq. E1).  After 2 pi / M of phi_1 they reach phases
+phi~_s + 2 pi rho / M, so invariance gives, as Eq. (16) does for the whole period,
+    R_m = (I (x) R(rho / M)) Gamma^-1 zbar^(m)(2 pi / M) - Z^((m + 1) mod M),
+and M = 1 is FSE-Shooting itself.  The Jacobian is block-cyclic: d R_m / d Z^(m) is the
+Eq. (22) operator of segment m without its identity, d R_m / d Z^(m+1) = -I.
+
+Pins (tests/test_oracle_multiple.py): M = 1 equals the single-shooting residual and
+Jacobian; on a linear system one Newton step lands on the closed-form discrete torus, whose
+section m is the section-0 torus with the harmonic of frequency 1 turned by 2 pi m / M;
+central finite differences of R; on a nonlinear system the converged section 0 agrees with
+the single-shooting torus to the Fourier truncation.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import newmark
+from . import shooting
+from . import torus as tor
+
+
+def evaluate(sysm, torus, omega, Zs, M, sens=False, tables=None, tol=1e-12, maxit=30):
+    """Zs [M][2n][U~] -> residual R [M][2n][U~] (and Phi [M][S~][2n][2n] if sens)."""
+    if torus.S1 % M:
+        raise ValueError("S1 must be a multiple of the number of segments")
+    tb = tables or shooting.TorusTables(torus)
+    omega = np.asarray(omega, dtype=float)
+    n = sysm.n
+    Zs = np.asarray(Zs, dtype=float).reshape(M, 2 * n, tb.U)
+    steps = torus.S1 // M
+    Rm = tor.rotation(tb.table, omega[1:] / omega[0] / M) if torus.d > 1 else np.eye(1)
+    R = np.empty_like(Zs)
+    Phi = np.empty((M, tb.Stilde, 2 * n, 2 * n)) if sens else None
+    for m in range(M):
+        zbar0 = Zs[m] @ tb.G.T
+        zbarT = np.empty_like(zbar0)
+        for s in range(tb.Stilde):
+            out = newmark.integrate(sysm, omega, torus.S1, tb.phases[:, s], zbar0[:, s], sens=sens, tol=tol,
+                                    maxit=maxit, beta=getattr(torus, "beta", 0.25),
+                                    gamma=getattr(torus, "gamma", 0.5), steps=steps,
+                                    phi0=2.0 * math.pi * m / M)
+            zbarT[:, s] = out["zT"]
+            if sens:
+                Phi[m, s] = out["Phi"]
+        R[m] = (zbarT @ tb.Gi.T) @ Rm.T - Zs[(m + 1) % M]
+    res = {"R": R, "Rrot": Rm, "tables": tb, "M": M}
+    if sens:
+        res["Phi"] = Phi
+    return res
+
+
+def jacobian(res):
+    """Block-cyclic dR/dZ, unknowns ordered [Z^(0); ...; Z^(M-1)], each state-major."""
+    tb, M, Phi = res["tables"], res["M"], res["Phi"]
+    n2 = Phi.shape[2]
+    N = n2 * tb.U
+    A = res["Rrot"] @ tb.Gi
+    J = np.zeros((M * N, M * N))
+    for m in range(M):
+        blk = np.einsum("ls,sij,sk->iljk", A, Phi[m], tb.G, optimize=True).reshape(N, N)
+        J[m * N:(m + 1) * N, m * N:(m + 1) * N] += blk
+        m1 = (m + 1) % M
+        J[m * N:(m + 1) * N, m1 * N:(m1 + 1) * N] -= np.eye(N)
+    return J
+
+
+def newton_step(sysm, torus, omega, Zs, M, tables=None):
+    """Zs -> Zs - J^-1 R; returns (Zs_new, ||R||_2 before)."""
+    res = evaluate(sysm, torus, omega, Zs, M, sens=True, tables=tables)
+    dz = np.linalg.solve(jacobian(res), -res["R"].ravel())
+    return np.asarray(Zs, dtype=float) + dz.reshape(res["R"].shape), float(np.linalg.norm(res["R"]))
+
+
+def solve(sysm, torus, omega, Zs, M, tol_R=1e-8, max_newton=20, tables=None):
+    """Newton iterations until ||R||_2 < tol_R; returns (Zs, history of ||R||_2)."""
+    Z = np.array(Zs, dtype=float)
+    hist = []
+    for _ in range(max_newton):
+        Zn, r = newton_step(sysm, torus, omega, Z, M, tables=tables)
+        hist.append(r)
+        if r < tol_R:
+            return Z, hist
+        Z = Zn
+    hist.append(float(np.linalg.norm(evaluate(sysm, torus, omega, Z, M, tables=tables)["R"])))
+    return Z, hist

@@ -62,12 +62,13 @@ def tangent(sysm, q: np.ndarray) -> np.ndarray:
     return Kt
 
 
-def forcing(sysm, omega, phases, phi1: float) -> np.ndarray:
+def forcing(sysm, omega, phases, phi1: float, phi0: float = 0.0) -> np.ndarray:
     """e(phi_1, phi^_s + rho^ phi_1) of Eq. (E1).
 
-    Forcing i = 1 has argument phi_1; forcing i = 2..e has phi_{i,s} + rho_i phi_1.
+    Forcing i = 1 has argument phi0 + phi_1; forcing i = 2..e has phi_{i,s} + rho_i phi_1
+    (phi0 = 0 on the section phi_1 = 0; a segment of multiple shooting starts at phi0).
     """
-    e = sysm.F[0] * math.cos(phi1)
+    e = sysm.F[0] * math.cos(phi0 + phi1)
     for i in range(2, sysm.e + 1):
         rho_i = omega[i - 1] / omega[0]
         e = e + sysm.F[i - 1] * math.cos(phases[i - 2] + rho_i * phi1)
@@ -96,17 +97,20 @@ def _solve(A, B):
 def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
               omega_sens: bool = False, tol: float = 1e-12, maxit: int = 30,
               q_scale: float = 0.0, history: bool = False, beta: float = 0.25, gamma: float = 0.5,
-              general: bool = False):
+              general: bool = False, steps: int = None, phi0: float = 0.0):
     """Integrate one trajectory from phi_1 = 0 to 2 pi in S1 Newmark steps.
 
     Returns dict with zT = [q; u](2 pi), Phi (2n x 2n) if sens, dz_domega
     (2n x e) if omega_sens, iters (Newton iterations per step), q_hist if history.
     (beta, gamma) other than the average-acceleration (1/4, 1/2) of App. E, or general=True,
-    take the general Newmark rule (integrate_general).
+    take the general Newmark rule (integrate_general).  steps < S1 integrates that many
+    steps of h = 2 pi / S1 from the section phi_1 = phi0 (a segment of multiple shooting).
     """
     if general or beta != 0.25 or gamma != 0.5:
         return integrate_general(sysm, omega, S1, phases, z0, sens=sens, omega_sens=omega_sens, tol=tol,
-                                 maxit=maxit, q_scale=q_scale, history=history, beta=beta, gamma=gamma)
+                                 maxit=maxit, q_scale=q_scale, history=history, beta=beta, gamma=gamma,
+                                 steps=steps, phi0=phi0)
+    steps = S1 if steps is None else steps
     M, D, K = sysm.M, sysm.D, sysm.K
     n = sysm.n
     omega = np.asarray(omega, dtype=float)
@@ -117,7 +121,7 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
     q = np.array(z0[:n], dtype=float)
     u = np.array(z0[n:], dtype=float)
     Mw = w1 ** 2 * M
-    a = _solve(Mw, forcing(sysm, omega, phases, 0.0) - w1 * D @ u - K @ q
+    a = _solve(Mw, forcing(sysm, omega, phases, 0.0, phi0) - w1 * D @ u - K @ q
                - internal_force(sysm, q))
     if sens:
         Q = np.hstack([np.eye(n), np.zeros((n, n))])
@@ -134,11 +138,11 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
             if i == 1:
                 rhs = rhs - D @ u - 2.0 * w1 * M @ a
             Aw[:, i - 1] = _solve(Mw, rhs)
-    iters = np.zeros(S1, dtype=np.int64)
+    iters = np.zeros(steps, dtype=np.int64)
     qh = [q.copy()] if history else None
-    for k in range(S1):
+    for k in range(steps):
         phi_next = (k + 1) * h
-        e1 = forcing(sysm, omega, phases, phi_next)
+        e1 = forcing(sysm, omega, phases, phi_next, phi0)
         b = e1 + Mw @ (c0 * q + c1 * u + a) + w1 * D @ (c2 * q + u)
         qn = q + h * u + 0.5 * h * h * a
         prev = math.inf
@@ -195,7 +199,7 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
 
 def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omega_sens: bool = False,
                       tol: float = 1e-12, maxit: int = 30, q_scale: float = 0.0, history: bool = False,
-                      beta: float = 0.25, gamma: float = 0.5):
+                      beta: float = 0.25, gamma: float = 0.5, steps: int = None, phi0: float = 0.0):
     """The same trajectory with the general Newmark rule (the paper's future-work item 3;
     App. E is its case beta = 1/4, gamma = 1/2).  Newmark's two relations, in phi_1:
         q_{k+1} = q_k + h u_k + h^2 ((1/2 - beta) a_k + beta a_{k+1}),
@@ -209,6 +213,7 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
     the explicit terms -(2 w1 M a_{k+1} + D u_{k+1}) (omega_1 only) and d e / d omega."""
     M, D, K = sysm.M, sysm.D, sysm.K
     n = sysm.n
+    steps = S1 if steps is None else steps
     omega = np.asarray(omega, dtype=float)
     w1 = omega[0]
     h = 2.0 * math.pi / S1
@@ -218,7 +223,7 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
     S = ca * Mw + cu * w1 * D + K
     q = np.array(z0[:n], dtype=float)
     u = np.array(z0[n:], dtype=float)
-    a = _solve(Mw, forcing(sysm, omega, phases, 0.0) - w1 * D @ u - K @ q - internal_force(sysm, q))
+    a = _solve(Mw, forcing(sysm, omega, phases, 0.0, phi0) - w1 * D @ u - K @ q - internal_force(sysm, q))
     if sens:
         Q = np.hstack([np.eye(n), np.zeros((n, n))])
         U = np.hstack([np.zeros((n, n)), np.eye(n)])
@@ -233,16 +238,16 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
             if i == 1:
                 rhs = rhs - D @ u - 2.0 * w1 * M @ a
             Aw[:, i - 1] = _solve(Mw, rhs)
-    iters = np.zeros(S1, dtype=np.int64)
+    iters = np.zeros(steps, dtype=np.int64)
     qh = [q.copy()] if history else None
 
     def accel_vel(qn, p, v):
         an = (qn - p) / (beta * h * h)
         return an, v + gamma * h * an
 
-    for k in range(S1):
+    for k in range(steps):
         phi_next = (k + 1) * h
-        e1 = forcing(sysm, omega, phases, phi_next)
+        e1 = forcing(sysm, omega, phases, phi_next, phi0)
         p = q + h * u + h * h * (0.5 - beta) * a
         v = u + h * (1.0 - gamma) * a
         qn = q + h * u + 0.5 * h * h * a
