@@ -266,6 +266,28 @@ fse_status fse_hypertime_residual_jacobian(fse_ctx *ctx, int32_t B, const double
  * (may be NULL).  FSE_E_SINGULAR on a zero pivot. */
 fse_status fse_hypertime_newton_step(fse_ctx *ctx, const double *omega, double *zbar0, double *res_norm);
 
+/* ---------------------------------------------------------------- multiple FSE-Shooting
+ * The paper's first recommendation for future work (Sec. 5), in the classical multiple-
+ * shooting form of Sec. 3: the period of phi_1 is cut into M segments of S1 / M steps and the
+ * unknowns are the sections Z^(m) [2n][U~] of the torus at phi_1 = 2 pi m / M (basis of
+ * Eq. 13 over the phases of the other frequencies at that moment).  Segment m starts on
+ * section m with the forcing of frequency 1 at phase 2 pi m / M; with Eq. (16) per segment
+ *     R_m = (I (x) R(rho / M)) Gamma^-1 zbar^(m)(2 pi / M) - Z^((m + 1) mod M).
+ * M = 1 is FSE-Shooting.  d = e only (FSE_E_UNSUPPORTED otherwise); 1 <= M <= max_batch and
+ * S1 a multiple of M (FSE_E_INVAL otherwise).  The segments run as one batch of M points. */
+
+/* omega HOST [d], Zs device [M][2n][U~]; outputs R device [M][2n][U~], rnorm HOST (||R||_2
+ * over all segments, may be NULL), J device [M 2nU~][M 2nU~] row-major or NULL: diagonal
+ * block m the Eq. (22) operator of segment m without -I, block (m, m + 1 mod M) = -I, the
+ * rest zero.  Errors as fse_integrate_batch. */
+fse_status fse_multiple_residual_jacobian(fse_ctx *ctx, int32_t M, const double *omega, const double *Zs,
+                                          double *R, double *rnorm, double *J);
+
+/* One Newton update of all sections (Zs device [M][2n][U~], in place) with a dense LU of the
+ * block-cyclic Jacobian held by the context; res_norm HOST = ||R||_2 before the update (may
+ * be NULL).  FSE_E_SINGULAR on a zero pivot. */
+fse_status fse_multiple_newton_step(fse_ctx *ctx, int32_t M, const double *omega, double *Zs, double *res_norm);
+
 /* ---------------------------------------------------------------- learned predictor
  * Initial iterates for new continuation parameters from the converged tori of earlier
  * points: a POD basis of the converged Z(0) (method of snapshots: Gram matrix in FP64,

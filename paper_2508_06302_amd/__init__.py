@@ -19,7 +19,8 @@ __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integ
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
            "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
            "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step",
-           "fse_hypertime_residual_jacobian", "fse_hypertime_newton_step", "fse_get_tuning", "FSE_PREC_FP64",
+           "fse_hypertime_residual_jacobian", "fse_hypertime_newton_step", "fse_multiple_residual_jacobian",
+           "fse_multiple_newton_step", "fse_get_tuning", "FSE_PREC_FP64",
            "FSE_PREC_MIXED_FP32"]
 
 FSE_PREC_FP64 = 0
@@ -401,6 +402,34 @@ def fse_hypertime_residual_jacobian(ctx: Context, omega, zbar0, want_J=False):
                                                       C.c_void_p(R.data_ptr()), _p(rn, C.c_double),
                                                       C.c_void_p(J.data_ptr()) if J is not None else None))
     return R, rn, J
+
+
+def fse_multiple_residual_jacobian(ctx: Context, M, omega, Zs, want_J=False):
+    """Multiple shooting over M segments: omega [d], Zs [M][2n][U] -> (R torch cuda [M][2n][U],
+    ||R||_2, J [M 2nU][M 2nU] or None)."""
+    torch = _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    z = _dev(Zs, (int(M), 2 * ctx.n, ctx.U))
+    R = torch.empty_like(z)
+    rn = C.c_double()
+    NM = int(M) * 2 * ctx.n * ctx.U
+    J = torch.empty((NM, NM), dtype=torch.float64, device="cuda") if want_J else None
+    ctx.check(ctx.lib.fse_multiple_residual_jacobian(ctx.h, int(M), _p(om, C.c_double), C.c_void_p(z.data_ptr()),
+                                                     C.c_void_p(R.data_ptr()), C.byref(rn),
+                                                     C.c_void_p(J.data_ptr()) if J is not None else None))
+    return R, rn.value, J
+
+
+def fse_multiple_newton_step(ctx: Context, M, omega, Zs):
+    """Zs (torch cuda [M][2n][U], updated in place) <- one dense Newton step -> ||R|| before."""
+    _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    rn = C.c_double()
+    ctx.check(ctx.lib.fse_multiple_newton_step(ctx.h, int(M), _p(om, C.c_double), C.c_void_p(Zs.data_ptr()),
+                                               C.byref(rn)))
+    return rn.value
 
 
 def fse_hypertime_newton_step(ctx: Context, omega, zbar0):

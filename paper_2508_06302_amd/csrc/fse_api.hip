@@ -391,7 +391,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)

@@ -53,6 +53,7 @@ struct TrajParams {
   int maxit;
   double tol;
   double h, c0, c1, c2, c3, d1, d2;
+  double phib;  // phase of forcing 1 at the start, per point index b (multiple shooting segments)
 };
 
 struct fse_ctx {
@@ -65,6 +66,8 @@ struct fse_ctx {
   int Bmax = 1, prec = 0, maxit = 30;
   double tol = 1e-12;
   double nm_beta = 0.25, nm_gamma = 0.5;  // Newmark rule
+  int seg_steps = 0;                      // > 0: integrate that many steps (multiple shooting)
+  double seg_phase = 0.0;                 // forcing-1 phase at the start = seg_phase * point index
   int Wmax = 0;
   int nnz2 = 0, nnz3 = 0;
 
@@ -130,6 +133,9 @@ struct fse_ctx {
   bool samples_in = false;          // the next integration starts from samples, not coefficients
   double *ht = nullptr;             // Gamma R Gamma^-1 per point, R Gamma^-1, residual
   size_t ht_elems = 0;
+  // multiple FSE-Shooting (k_multiple.hip)
+  double *mult = nullptr;           // next sections, residual [2][M][2n][U]
+  size_t mult_elems = 0;
 
   // packed tensors for LDS staging: t2 (j | k << 16), t3 (j | k << 16, l)
   uint32_t *f2_pk = nullptr, *f3_pk = nullptr;

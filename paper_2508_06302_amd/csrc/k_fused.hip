@@ -90,8 +90,9 @@ __global__ void k_point_bands(TrajParams P, const double *__restrict__ Mb, const
   if (b == 0) Kp[idx] = k;
 }
 
-__device__ inline double forcing_cos(const FusedArgs &a, int f, double phi1, const double *om, int s) {
-  if (f == 0) return cos(phi1);
+__device__ inline double forcing_cos(const FusedArgs &a, int f, double phi1, const double *om, int s,
+                                    double phi0) {
+  if (f == 0) return cos(phi0 + phi1);
   const double ph = kTwoPi * (double)a.sidx[(f - 1) * a.P.St + s] / (double)a.Sdim[f - 1];
   return cos(ph + om[f] / om[0] * phi1);
 }
@@ -360,7 +361,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
     }
   }
   if (wave == 0) {
-    if (lane < P.e) cs[lane] = forcing_cos(a, lane, 0.0, om, s);
+    if (lane < P.e) cs[lane] = forcing_cos(a, lane, 0.0, om, s, P.phib * b);
     wave_sync();
     // a0 right-hand side: e0 - w1 D u0 - K q0 - f_nl(q0)
     for (int i = lane; i < n; i += 64) {
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
       if (k == 1) {
         for (int e = lane; e < n * W2; e += 64) Sl[e] = Sp[e];
       }
-      if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s);
+      if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s, P.phib * b);
       wave_sync();
       for (int i = lane; i < n; i += 64) {
         double v = 0.0;
@@ -790,7 +791,8 @@ fse_status launch_fused(fse_ctx *ctx, int B, double *Phi) {
   TrajParams p;
   p.n = ctx->n;
   p.bw = ctx->bw;
-  p.S1 = ctx->S1;
+  p.S1 = ctx->seg_steps > 0 ? ctx->seg_steps : ctx->S1;
+  p.phib = ctx->seg_phase;
   p.e = ctx->e;
   p.d = ctx->d;
   p.St = ctx->St;

@@ -162,8 +162,8 @@ __device__ inline double kt_entry(const SysDev &sy, const double *q, int pos) {
 // Forcing cosines at phi_1 for sample s (Eq. E1): forcing 0 has argument phi_1,
 // forcing f >= 1 has phi_{f+1,s} + rho_{f+1} phi_1.
 __device__ inline double forcing_cos(int f, double phi1, const double *om, const int32_t *sidx,
-                                     const int32_t *Sdim, int St, int s) {
-  if (f == 0) return cos(phi1);
+                                     const int32_t *Sdim, int St, int s, double phi0) {
+  if (f == 0) return cos(phi0 + phi1);
   const double ph = kTwoPi * (double)sidx[(f - 1) * St + s] / (double)Sdim[f - 1];
   return cos(ph + om[f] / om[0] * phi1);
 }
@@ -229,7 +229,7 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
     q[i] = qhist[(size_t)i * ldw + w];
     u[i] = u0[(size_t)i * ldw + w];
   }
-  if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s);
+  if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s, P.phib * b);
   __syncthreads();
   // consistent initial acceleration: (w1^2 M) a0 = e0 - w1 D u0 - K q0 - f_nl(q0)
   for (int i = tid; i < n; i += nt) {
@@ -256,7 +256,7 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
   bool failed = false;
   for (int k = 0; k < P.S1; ++k) {
     const double phi1 = (double)(k + 1) * P.h;
-    if (tid < P.e) cs[tid] = forcing_cos(tid, phi1, om, sidx, Sdim, P.St, s);
+    if (tid < P.e) cs[tid] = forcing_cos(tid, phi1, om, sidx, Sdim, P.St, s, P.phib * b);
     __syncthreads();
     // b_k (Eq. E7) and the predictor
     for (int i = tid; i < n; i += nt) {
@@ -511,7 +511,7 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
     q[i] = qhist[(size_t)i * ldw + w];
     u[i] = u0[(size_t)i * ldw + w];
   }
-  if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s);
+  if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s, P.phib * b);
   __syncthreads();
   // consistent initial acceleration (w1^2 M) a0 = e0 - w1 D u0 - K q0 - f_nl(q0)
   for (int i = tid; i < n; i += nt) {
@@ -735,7 +735,8 @@ TrajParams params(const fse_ctx *ctx, int B) {
   TrajParams P;
   P.n = ctx->n;
   P.bw = ctx->bw;
-  P.S1 = ctx->S1;
+  P.S1 = ctx->seg_steps > 0 ? ctx->seg_steps : ctx->S1;
+  P.phib = ctx->seg_phase;
   P.e = ctx->e;
   P.d = ctx->d;
   P.St = ctx->St;

@@ -232,6 +232,7 @@ fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT) {
   p.n = ctx->n;
   p.bw = ctx->bw;
   p.S1 = ctx->S1;
+  p.phib = 0.0;
   p.e = ctx->e;
   p.d = ctx->d;
   p.St = ctx->St;

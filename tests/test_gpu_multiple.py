@@ -1,0 +1,139 @@
+"""GPU multiple FSE-Shooting (M segments of the period of phi_1) against the oracle.
+
+Bar: R and the block-cyclic J within 1e-10 normwise relative of the oracle (same discrete
+map); M = 1 equals the FSE-Shooting residual and Jacobian; one Newton step on a linear
+system lands on the closed-form discrete sections; nonlinear Newton solutions equal the
+oracle's; the C1 cantilever converges with two segments.
+"""
+import numpy as np
+import pytest
+
+from _closed_forms import discrete_linear_sections
+from fse_inputs import Torus, tiny_system, workload
+from oracle import multiple as omult
+from oracle import shooting as osh
+
+pytestmark = pytest.mark.gpu
+GOLDEN = (1 + 5 ** 0.5) / 2
+RTOL = 1e-10
+
+
+def fse():
+    import paper_2508_06302_amd as m
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def _case(nonlinear=True, seed=2, S=8, S1=48, n=2):
+    s = tiny_system(n=n, seed=seed, nonlinear=nonlinear, cubic=1.0, quad=0.3, e=2)
+    om = np.array([0.8, 0.8 * GOLDEN])
+    tr = Torus(d=2, e=2, K=[np.arange(1, 3)], S=[S], S1=S1)
+    return s, tr, osh.TorusTables(tr), om
+
+
+@pytest.mark.parametrize("kernels", ["fused", "generic"])
+@pytest.mark.parametrize("M", [2, 3])
+def test_residual_and_jacobian_match_oracle(M, kernels, monkeypatch):
+    monkeypatch.setenv("FSE_KERNELS", kernels)
+    s, tr, tb, om = _case()
+    Zs = 0.2 * np.random.default_rng(M).normal(size=(M, 4, tb.U))
+    ref = omult.evaluate(s, tr, om, Zs, M, sens=True, tables=tb)
+    ctx = fse().fse_init_torus(s, tr, max_batch=4)
+    R, rn, J = fse().fse_multiple_residual_jacobian(ctx, M, om, Zs, want_J=True)
+    log(f"M={M} {kernels}: R rel {rel(R.cpu().numpy(), ref['R']):.2e}")
+    assert rel(R.cpu().numpy(), ref["R"]) < RTOL
+    assert abs(rn - np.linalg.norm(ref["R"])) < RTOL * np.linalg.norm(ref["R"])
+    assert rel(J.cpu().numpy(), omult.jacobian(ref)) < RTOL
+
+
+def test_one_segment_is_fse_shooting():
+    s, tr, tb, om = _case()
+    Z = 0.2 * np.random.default_rng(3).normal(size=(4, tb.U))
+    ctx = fse().fse_init_torus(s, tr)
+    R1, rn1, J1 = fse().fse_multiple_residual_jacobian(ctx, 1, om, Z[None], want_J=True)
+    R, rn, J = fse().fse_shooting_residual_jacobian(ctx, om[None], Z[None], want_J=True)
+    assert rel(R1[0].cpu().numpy(), R[0].cpu().numpy()) < 1e-14
+    assert rel(J1.cpu().numpy(), J[0].cpu().numpy()) < 1e-14
+
+
+@pytest.mark.parametrize("M", [2, 4])
+def test_linear_newton_step_lands_on_the_closed_form(M):
+    import torch
+    s, tr, tb, om = _case(nonlinear=False)
+    Zc = discrete_linear_sections(s, om, tr.S1, tb.table, tb.U, M)
+    ctx = fse().fse_init_torus(s, tr, max_batch=4)
+    Zg = torch.zeros((M, 4, tb.U), dtype=torch.float64, device="cuda")
+    r0 = fse().fse_multiple_newton_step(ctx, M, om, Zg)
+    assert r0 > 1e-3
+    assert np.abs(Zg.cpu().numpy() - Zc).max() < 1e-11 * np.abs(Zc).max()
+
+
+def test_nonlinear_newton_equals_the_oracle():
+    import torch
+    s, tr, tb, om = _case(S=8)
+    s.F *= 0.5
+    M = 2
+    Zo, ho = omult.solve(s, tr, om, np.zeros((M, 4, tb.U)), M, tol_R=1e-12, tables=tb)
+    ctx = fse().fse_init_torus(s, tr, max_batch=2)
+    Zg = torch.zeros((M, 4, tb.U), dtype=torch.float64, device="cuda")
+    hist = []
+    for _ in range(12):
+        r = fse().fse_multiple_newton_step(ctx, M, om, Zg)
+        hist.append(r)
+        if r < 1e-12:
+            break
+    log(f"multiple shooting M=2: ||R|| {['%.1e' % h for h in hist]}, oracle {['%.1e' % h for h in ho]}")
+    assert hist[-1] < 1e-12 and ho[-1] < 1e-12
+    assert rel(Zg.cpu().numpy(), Zo) < 1e-9
+
+
+def test_c1_cantilever_with_two_segments():
+    """C1 (10 DOF, S1 = 256): two segments from the seeded start converge; section 0 agrees with
+    the FSE-Shooting torus to the Fourier truncation and the oracle's residual at the GPU's
+    sections is below the bound."""
+    import torch
+    wl = workload("C1")
+    tb = osh.TorusTables(wl.torus)
+    Z0 = wl.initial_iterate(tb.table)
+    M = 2
+    ctx = fse().fse_init_torus(wl.system, wl.torus, max_batch=M)
+    Zs = torch.tensor(np.stack([Z0, Z0]), dtype=torch.float64, device="cuda")
+    hist = []
+    for _ in range(15):
+        r = fse().fse_multiple_newton_step(ctx, M, wl.omega, Zs)
+        hist.append(r)
+        if r < 1e-9:
+            break
+    log(f"C1 two segments: ||R|| {['%.1e' % h for h in hist]}")
+    assert hist[-1] < 1e-9
+    Zh = Zs.cpu().numpy()
+    assert np.linalg.norm(omult.evaluate(wl.system, wl.torus, wl.omega, Zh, M, tables=tb)["R"]) < 1e-8
+    Z1, _, _ = osh.solve(wl.system, wl.torus, wl.omega, Z0, tol_R=1e-10, tables=tb)
+    err = np.abs(Zh[0] - Z1).max() / np.abs(Z1).max()
+    log(f"  section 0 vs FSE-Shooting torus: {err:.2e}")
+    assert err < 1e-2
+
+
+def test_invalid_calls():
+    import torch
+    s, tr, tb, om = _case()
+    ctx = fse().fse_init_torus(s, tr, max_batch=2)
+    Z = torch.zeros((3, 4, tb.U), dtype=torch.float64, device="cuda")
+    with pytest.raises(fse().FseError, match="FSE_E_INVAL"):
+        fse().fse_multiple_newton_step(ctx, 3, om, Z)          # more segments than max_batch
+    ctx5 = fse().fse_init_torus(s, Torus(d=2, e=2, K=[np.arange(1, 3)], S=[8], S1=50), max_batch=4)
+    with pytest.raises(fse().FseError, match="FSE_E_INVAL"):
+        fse().fse_multiple_newton_step(ctx5, 4, om, Z[:2].repeat(2, 1, 1))   # 50 steps, 4 segments
+    su = tiny_system(n=2, seed=2, cubic=1.0, quad=0.3, e=1)
+    ctxu = fse().fse_init_torus(su, Torus(d=2, e=1, K=[np.arange(1, 3)], S=[8], S1=48), max_batch=2)
+    with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
+        fse().fse_multiple_residual_jacobian(ctxu, 2, om, Z[:2])

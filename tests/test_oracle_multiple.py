@@ -1,12 +1,10 @@
 """Pins of the oracle's multiple FSE-Shooting (the paper's first recommendation, classical
 multiple-shooting reading)."""
-import math
-
 import numpy as np
 import pytest
 
 from fse_inputs import Torus, tiny_system
-from fse_inputs.systems import place_harmonics
+from _closed_forms import discrete_linear_sections as _linear_sections
 from oracle import multiple as mult
 from oracle import shooting
 
@@ -18,27 +16,6 @@ def _case(nonlinear=True, seed=2, S=8, S1=48):
     om = np.array([0.8, 0.8 * GOLDEN])
     tr = Torus(d=2, e=2, K=[np.arange(1, 3)], S=[S], S1=S1)
     return s, tr, shooting.TorusTables(tr), om
-
-
-def _linear_sections(s, omega, S1, table, U, M):
-    """Closed-form steady state of the discrete (trapezoidal) Newmark map of a linear system
-    on the sections phi_1 = 2 pi m / M: the harmonic of frequency 1 at phase 2 pi m / M, the
-    others in the section's own phases (distorted frequency (2/h) tan(lambda h / 2))."""
-    h = 2 * math.pi / S1
-    w1 = omega[0]
-    out = []
-    for m in range(M):
-        harms = []
-        for i in range(s.e):
-            lam = omega[i] / w1
-            lt = (2 / h) * math.tan(lam * h / 2)
-            Qh = np.linalg.solve(s.K - w1 ** 2 * lt ** 2 * s.M + 1j * w1 * lt * s.D, s.F[i].astype(complex))
-            if i == 0:
-                Qh = Qh * np.exp(2j * math.pi * m / M)
-            k = (0,) if i == 0 else tuple(1 if j == i - 1 else 0 for j in range(len(omega) - 1))
-            harms.append((k, np.concatenate([Qh, 1j * lt * Qh])))
-        out.append(place_harmonics(table, harms, s.n, U))
-    return np.array(out)
 
 
 def test_one_segment_is_fse_shooting():
