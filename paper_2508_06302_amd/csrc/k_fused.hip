@@ -310,6 +310,9 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
   const bool chord32 = kChord32 && (reinterpret_cast<uintptr_t>(CF0) & 15) == 0;
   __shared__ int s_fail_step;
   __shared__ int s_flags;
+  // phase of forcing 1 at the start (multiple-shooting segments), read from LDS once per step
+  // so that no register carries it across the step loop
+  __shared__ double s_phi0;
 
   // ============================================================ prologue
   for (int e = threadIdx.x; e < (int)(FR + fb - smem); e += blockDim.x) smem[e] = 0.0;
@@ -331,6 +334,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
   if (threadIdx.x == 0) {
     s_fail_step = INT_MAX;
     s_flags = 0;
+    s_phi0 = P.phib * b;
   }
   __syncthreads();
   if (wave == 0 || wave == 2) {
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
     }
   }
   if (wave == 0) {
-    if (lane < P.e) cs[lane] = forcing_cos(a, lane, 0.0, om, s, P.phib * b);
+    if (lane < P.e) cs[lane] = forcing_cos(a, lane, 0.0, om, s, s_phi0);
     wave_sync();
     // a0 right-hand side: e0 - w1 D u0 - K q0 - f_nl(q0)
     for (int i = lane; i < n; i += 64) {
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(320) void k_fused(FusedArgs a, const double *__rest
       if (k == 1) {
         for (int e = lane; e < n * W2; e += 64) Sl[e] = Sp[e];
       }
-      if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s, P.phib * b);
+      if (lane < P.e) cs[lane] = forcing_cos(a, lane, phi1, om, s, s_phi0);
       wave_sync();
       for (int i = lane; i < n; i += 64) {
         double v = 0.0;
