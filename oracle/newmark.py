@@ -13,12 +13,20 @@ Readings where the paper is silent:
   * Newton predictor q_k + D u_k + D^2/2 a_k; stop when ||dq||_inf <= tol *
     max(||q||_inf, q_scale), or when the update stops shrinking while already
     below 1e3 tol (the FP64 noise floor); at most `maxit` iterations;
-  * the "adjoint system" of App. E is read as the variational (sensitivity) system.
+  * the "adjoint system" of App. E is read as the variational (sensitivity) system;
+  * f_nl may depend on qdot = omega_1 u (Eq. 1 allows it; the paper's examples do not):
+    a tensor factor index in [n, 2n) names qdot.  Its tangent C_t = d f_nl / d qdot adds
+    omega_1 gamma/(beta h) C_t to the step's iteration matrix and enters the
+    sensitivities as the state-dependent damping D + C_t (general rule only).
 
 Pins (tests/test_oracle_newmark.py): the closed-form average-acceleration
 response of an undamped oscillator (unit amplitude, phase 2 atan(Omega h/2) per
 step), discrete energy conservation, the discrete linear steady state, and
-central finite differences of the sensitivities and of the omega-derivatives.
+central finite differences of the sensitivities and of the omega-derivatives;
+with velocity-dependent forces (tests/test_oracle_velocity.py) finite differences
+of the sensitivities and of both tangents, and the forced van der Pol torus against
+the averaging result (limit-cycle frequency 1 - mu^2/16, amplitude 2) and its
+Lyapunov exponents (one zero, one near -mu).
 """
 from __future__ import annotations
 
@@ -31,21 +39,53 @@ class StepNewtonError(RuntimeError):
     pass
 
 
-def internal_force(sysm, q: np.ndarray) -> np.ndarray:
-    """f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l."""
+def has_velocity(sysm) -> bool:
+    """Forces that depend on qdot: a tensor factor index in [n, 2n) names qdot_{index - n}
+    (the f_nl(q, qdot) of Eq. 1; the paper's examples depend on q only)."""
+    n = sysm.n
+    return bool((len(sysm.t2_val) and sysm.t2_idx[:, 1:].max() >= n)
+                or (len(sysm.t3_val) and sysm.t3_idx[:, 1:].max() >= n))
+
+
+def _y(q, qd):
+    return q if qd is None else np.concatenate([q, qd])
+
+
+def internal_force(sysm, q: np.ndarray, qd: np.ndarray = None) -> np.ndarray:
+    """f_nl(q, qdot)_i = sum t2 y_j y_k + sum t3 y_j y_k y_l, y = [q; qdot]."""
     n = len(q)
+    y = _y(q, qd)
     f = np.zeros(n)
     if len(sysm.t2_val):
         i, j, k = sysm.t2_idx.T
-        f += np.bincount(i, weights=sysm.t2_val * q[j] * q[k], minlength=n)
+        f += np.bincount(i, weights=sysm.t2_val * y[j] * y[k], minlength=n)
     if len(sysm.t3_val):
         i, j, k, l = sysm.t3_idx.T
-        f += np.bincount(i, weights=sysm.t3_val * q[j] * q[k] * q[l], minlength=n)
+        f += np.bincount(i, weights=sysm.t3_val * y[j] * y[k] * y[l], minlength=n)
     return f
 
 
+def tangents(sysm, q: np.ndarray, qd: np.ndarray = None):
+    """(K_t, C_t) = (d f_nl / d q, d f_nl / d qdot), dense n x n each."""
+    n = len(q)
+    y = _y(q, qd)
+    G = np.zeros((n, len(y)))
+    if len(sysm.t2_val):
+        i, j, k = sysm.t2_idx.T
+        v = sysm.t2_val
+        np.add.at(G, (i, j), v * y[k])
+        np.add.at(G, (i, k), v * y[j])
+    if len(sysm.t3_val):
+        i, j, k, l = sysm.t3_idx.T
+        v = sysm.t3_val
+        np.add.at(G, (i, j), v * y[k] * y[l])
+        np.add.at(G, (i, k), v * y[j] * y[l])
+        np.add.at(G, (i, l), v * y[j] * y[k])
+    return G[:, :n], (G[:, n:] if qd is not None else np.zeros((n, n)))
+
+
 def tangent(sysm, q: np.ndarray) -> np.ndarray:
-    """K_t(q) = d f_nl / d q (dense)."""
+    """K_t(q) = d f_nl / d q (dense; forces of q only)."""
     n = len(q)
     Kt = np.zeros((n, n))
     if len(sysm.t2_val):
@@ -106,7 +146,7 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
     take the general Newmark rule (integrate_general).  steps < S1 integrates that many
     steps of h = 2 pi / S1 from the section phi_1 = phi0 (a segment of multiple shooting).
     """
-    if general or beta != 0.25 or gamma != 0.5:
+    if general or beta != 0.25 or gamma != 0.5 or has_velocity(sysm):
         return integrate_general(sysm, omega, S1, phases, z0, sens=sens, omega_sens=omega_sens, tol=tol,
                                  maxit=maxit, q_scale=q_scale, history=history, beta=beta, gamma=gamma,
                                  steps=steps, phi0=phi0)
@@ -223,11 +263,20 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
     S = ca * Mw + cu * w1 * D + K
     q = np.array(z0[:n], dtype=float)
     u = np.array(z0[n:], dtype=float)
-    a = _solve(Mw, forcing(sysm, omega, phases, 0.0, phi0) - w1 * D @ u - K @ q - internal_force(sysm, q))
+    vel = has_velocity(sysm)
+
+    def forces(qq, uu):
+        """f_nl, K_t and C_t at the state (q, u), qdot = w1 u."""
+        qd = w1 * uu if vel else None
+        Kt, Ct = tangents(sysm, qq, qd)
+        return internal_force(sysm, qq, qd), Kt, Ct
+
+    f0, Kt0, Ct0 = forces(q, u)
+    a = _solve(Mw, forcing(sysm, omega, phases, 0.0, phi0) - w1 * D @ u - K @ q - f0)
     if sens:
         Q = np.hstack([np.eye(n), np.zeros((n, n))])
         U = np.hstack([np.zeros((n, n)), np.eye(n)])
-        A = -_solve(Mw, np.hstack([K + tangent(sysm, q), w1 * D]))
+        A = -_solve(Mw, np.hstack([K + Kt0, w1 * (D + Ct0)]))
     ne = sysm.e
     if omega_sens:
         Qw = np.zeros((n, ne))
@@ -236,7 +285,7 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
         for i in range(1, ne + 1):
             rhs = forcing_domega(sysm, omega, phases, 0.0, i)
             if i == 1:
-                rhs = rhs - D @ u - 2.0 * w1 * M @ a
+                rhs = rhs - (D + Ct0) @ u - 2.0 * w1 * M @ a
             Aw[:, i - 1] = _solve(Mw, rhs)
     iters = np.zeros(steps, dtype=np.int64)
     qh = [q.copy()] if history else None
@@ -255,8 +304,9 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
         ok = False
         for it in range(maxit):
             an, un = accel_vel(qn, p, v)
-            r = Mw @ an + w1 * D @ un + K @ qn + internal_force(sysm, qn) - e1
-            dq = _solve(S + tangent(sysm, qn), r)
+            fq, Kt, Ct = forces(qn, un)
+            r = Mw @ an + w1 * D @ un + K @ qn + fq - e1
+            dq = _solve(S + Kt + w1 * cu * Ct, r)
             qn = qn - dq
             nd = float(np.max(np.abs(dq)))
             scale = max(float(np.max(np.abs(qn))), q_scale)
@@ -269,22 +319,24 @@ def integrate_general(sysm, omega, S1: int, phases, z0, sens: bool = False, omeg
             raise StepNewtonError(f"step Newton did not converge at step {k}")
         an, un = accel_vel(qn, p, v)
         if sens or omega_sens:
-            T = S + tangent(sysm, qn)
+            _, Kt, Ct = forces(qn, un)
+            T = S + Kt + w1 * cu * Ct
+            Deff = D + Ct  # the velocity-dependent forces linearise into a state-dependent damping
         if sens:
             dP = Q + h * U + h * h * (0.5 - beta) * A
             dV = U + h * (1.0 - gamma) * A
-            Qn = _solve(T, ca * Mw @ dP + w1 * D @ (cu * dP - dV))
+            Qn = _solve(T, ca * Mw @ dP + w1 * Deff @ (cu * dP - dV))
             An = (Qn - dP) / (beta * h * h)
             Un = dV + gamma * h * An
             Q, U, A = Qn, Un, An
         if omega_sens:
             dP = Qw + h * Uw + h * h * (0.5 - beta) * Aw
             dV = Uw + h * (1.0 - gamma) * Aw
-            rhs = ca * Mw @ dP + w1 * D @ (cu * dP - dV)
+            rhs = ca * Mw @ dP + w1 * Deff @ (cu * dP - dV)
             for i in range(1, ne + 1):
                 col = forcing_domega(sysm, omega, phases, phi_next, i)
                 if i == 1:
-                    col = col - 2.0 * w1 * M @ an - D @ un
+                    col = col - 2.0 * w1 * M @ an - Deff @ un
                 rhs[:, i - 1] += col
             Qwn = _solve(T, rhs)
             Awn = (Qwn - dP) / (beta * h * h)
