@@ -66,6 +66,12 @@ typedef enum {
  * index tuples (i,j,k) / (i,j,k,l) stored as rows of t2_idx / t3_idx.  The
  * tangent d f_nl / dq must be symmetric (forces derived from a potential,
  * as for the paper's von Karman and shell models); fse_init_torus checks it.
+ * Velocity-dependent forces f_nl(q, qdot) (Eq. 1): a factor index j, k or l
+ * in [n, 2n) names qdot_{index - n} (qdot = omega_1 dq/dphi_1); the output
+ * index i stays in [0, n).  Then d f_nl / d qdot must be symmetric as well
+ * (FSE_E_UNSUPPORTED otherwise), such systems run on the generic trajectory
+ * kernels, and fse_residual_dp / fse_arclength return FSE_E_UNSUPPORTED.
+ * Indices outside these ranges return FSE_E_INVAL.
  * F: [e][n] load amplitude vectors, forcing i has frequency omega_i. */
 typedef struct {
   int32_t n;

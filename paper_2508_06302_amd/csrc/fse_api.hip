@@ -221,24 +221,29 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     ctx->err = "invalid tensor or load arrays";
     return FSE_E_INVAL;
   }
+  // factor indices in [n, 2n) name qdot (velocity-dependent forces); the output index is a row
+  bool vel = false;
   for (int64_t p = 0; p < sys->nnz2; ++p) {
     const int32_t *ix = sys->t2_idx + 3 * p;
     for (int a = 0; a < 3; ++a)
-      if (ix[a] < 0 || ix[a] >= n) {
+      if (ix[a] < 0 || ix[a] >= (a == 0 ? n : 2 * n)) {
         ctx->err = "t2 index out of range";
         return FSE_E_INVAL;
       }
-    bw = std::max({bw, std::abs(ix[1] - ix[0]), std::abs(ix[2] - ix[0])});
+    vel = vel || ix[1] >= n || ix[2] >= n;
+    bw = std::max({bw, std::abs(ix[1] % n - ix[0]), std::abs(ix[2] % n - ix[0])});
   }
   for (int64_t p = 0; p < sys->nnz3; ++p) {
     const int32_t *ix = sys->t3_idx + 4 * p;
     for (int a = 0; a < 4; ++a)
-      if (ix[a] < 0 || ix[a] >= n) {
+      if (ix[a] < 0 || ix[a] >= (a == 0 ? n : 2 * n)) {
         ctx->err = "t3 index out of range";
         return FSE_E_INVAL;
       }
-    bw = std::max({bw, std::abs(ix[1] - ix[0]), std::abs(ix[2] - ix[0]), std::abs(ix[3] - ix[0])});
+    vel = vel || ix[1] >= n || ix[2] >= n || ix[3] >= n;
+    bw = std::max({bw, std::abs(ix[1] % n - ix[0]), std::abs(ix[2] % n - ix[0]), std::abs(ix[3] % n - ix[0])});
   }
+  ctx->has_vel = vel;
   ctx->bw = bw;
   std::vector<double> Mb, Db, Kb;
   FSE_TRY(csr_to_band(ctx, "M", M, n, bw, Mb));
@@ -275,11 +280,14 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
       v3[q] = sys->t3_val[p];
     }
   }
-  // tangent contributions to the lower band, position p = m*(bw+1) + (i-m)
+  // tangent contributions to the lower band, position p = m*(bw+1) + (i-m): d f / d q into
+  // con (K_t), d f / d qdot into conv (C_t); the other factors a, b index y = [q; qdot]
   const int bp = bw + 1;
-  std::vector<std::vector<std::pair<double, std::pair<int, int>>>> con((size_t)n * bp);
+  std::vector<std::vector<std::pair<double, std::pair<int, int>>>> con((size_t)n * bp), conv((size_t)n * bp);
   auto add = [&](int i, int m, double c, int a, int b) {
-    if (i >= m) con[(size_t)m * bp + (i - m)].push_back({c, {a, b}});
+    auto &dst = m < n ? con : conv;
+    const int mm = m % n;
+    if (i >= mm) dst[(size_t)mm * bp + (i - mm)].push_back({c, {a, b}});
   };
   for (int64_t p = 0; p < sys->nnz2; ++p) {
     const int32_t *ix = sys->t2_idx + 3 * p;
@@ -294,8 +302,8 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     add(ix[0], ix[2], v, ix[1], ix[3]);
     add(ix[0], ix[3], v, ix[1], ix[2]);
   }
-  std::vector<int32_t> ktp((size_t)n * bp + 1, 0), kti;
-  std::vector<double> ktc;
+  std::vector<int32_t> ktp((size_t)n * bp + 1, 0), kti, ctp((size_t)n * bp + 1, 0), cti;
+  std::vector<double> ktc, ctc;
   for (size_t q = 0; q < con.size(); ++q) {
     ktp[q + 1] = ktp[q] + (int32_t)con[q].size();
     for (auto &c : con[q]) {
@@ -303,12 +311,19 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
       kti.push_back(c.second.first);
       kti.push_back(c.second.second);
     }
+    ctp[q + 1] = ctp[q] + (int32_t)conv[q].size();
+    for (auto &c : conv[q]) {
+      ctc.push_back(c.first);
+      cti.push_back(c.second.first);
+      cti.push_back(c.second.second);
+    }
   }
-  // the tangent must be symmetric (potential forces): check at a random state
+  // both tangents must be symmetric (banded LDL^T): check at a random state y = [q; qdot];
+  // column keys m >= n are the C_t block
   if (sys->nnz2 + sys->nnz3 > 0) {
     std::mt19937_64 rng(12345);
     std::uniform_real_distribution<double> uni(-1.0, 1.0);
-    std::vector<double> q(n);
+    std::vector<double> q(2 * (size_t)n);
     for (auto &v : q) v = uni(rng);
     std::map<std::pair<int, int>, double> kt;
     for (int64_t p = 0; p < sys->nnz2; ++p) {
@@ -327,10 +342,11 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     double mx = 0.0;
     for (auto &kv : kt) mx = std::max(mx, std::abs(kv.second));
     for (auto &kv : kt) {
-      auto it = kt.find({kv.first.second, kv.first.first});
+      const int i = kv.first.first, m = kv.first.second, blk = m >= n ? n : 0;
+      auto it = kt.find({m - blk, i + blk});
       const double other = it == kt.end() ? 0.0 : it->second;
       if (std::abs(kv.second - other) > 1e-9 * mx) {
-        ctx->err = "tangent of f_nl is not symmetric (forces must derive from a potential)";
+        ctx->err = "tangent of f_nl is not symmetric (d f / d q and d f / d qdot must both be symmetric)";
         return FSE_E_UNSUPPORTED;
       }
     }
@@ -359,6 +375,12 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     FSE_TRY(upload(ctx, &ctx->f2_pk, pk2));
     FSE_TRY(upload(ctx, &ctx->f3_pk, pk3));
   }
+  if (vel) {
+    if (ctc.empty()) ctc.assign(1, 0.0), cti.assign(2, 0);
+    FSE_TRY(upload(ctx, &ctx->ct_ptr, ctp));
+    FSE_TRY(upload(ctx, &ctx->ct_idx, cti));
+    FSE_TRY(upload(ctx, &ctx->ct_c, ctc));
+  }
   FSE_TRY(upload(ctx, &ctx->kt_ptr, ktp));
   FSE_TRY(upload(ctx, &ctx->kt_idx, kti));
   FSE_TRY(upload(ctx, &ctx->kt_c, ktc));
@@ -373,6 +395,7 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   const size_t W = ctx->Wmax;
   FSE_TRY(alloc(ctx, (void **)&ctx->omega_d, sizeof(double) * ctx->Bmax * ctx->d));
   FSE_TRY(alloc(ctx, (void **)&ctx->qhist, sizeof(double) * (size_t)(ctx->S1 + 1) * n * W));
+  if (ctx->has_vel) FSE_TRY(alloc(ctx, (void **)&ctx->uhist, sizeof(double) * (size_t)(ctx->S1 + 1) * n * W));
   FSE_TRY(alloc(ctx, (void **)&ctx->u0, sizeof(double) * (size_t)n * W));
   FSE_TRY(alloc(ctx, (void **)&ctx->zTw, sizeof(double) * (size_t)2 * n * W));
   FSE_TRY(alloc(ctx, (void **)&ctx->status_d, sizeof(DevStatus)));
@@ -391,7 +414,8 @@ void free_all(fse_ctx *ctx) {
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
-                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult};
+                  ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult,
+                  ctx->ct_ptr, ctx->ct_idx, ctx->ct_c, ctx->uhist};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)

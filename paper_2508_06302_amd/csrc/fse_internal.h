@@ -85,6 +85,11 @@ struct fse_ctx {
   int32_t *f3_ptr = nullptr, *f3_jkl = nullptr; double *f3_v = nullptr;
   // tangent lower band: contributions per entry p = m*(bw+1) + (i-m)
   int32_t *kt_ptr = nullptr, *kt_idx = nullptr;  double *kt_c = nullptr;  // idx pairs (p, r or -1)
+  // velocity-dependent forces (factor indices n..2n-1 name qdot): C_t = d f / d qdot lists,
+  // same layout as kt_*, and the velocity history [S1+1][n][Wmax] for the sensitivity pass
+  bool has_vel = false;
+  int32_t *ct_ptr = nullptr, *ct_idx = nullptr;  double *ct_c = nullptr;
+  double *uhist = nullptr;
   // torus
   double *G_d = nullptr, *Gi_d = nullptr;
   int32_t *sidx_d = nullptr, *Sdim_d = nullptr, *ktable_d = nullptr;

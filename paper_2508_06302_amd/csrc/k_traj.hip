@@ -137,26 +137,43 @@ struct SysDev {
   const double *f3_v;
   const int32_t *kt_ptr, *kt_idx;
   const double *kt_c;
+  const int32_t *ct_ptr, *ct_idx;  // C_t = d f / d qdot lists, or null (forces of q only)
+  const double *ct_c;
+  int n;
 };
 
-// f_nl(q)_i = sum t2 q_j q_k + sum t3 q_j q_k q_l (row i of the CSR-by-output tensors)
-__device__ inline double fnl_row(const SysDev &sy, const double *q, int i) {
+// y = [q; qdot]: factor index j < n is q_j, j >= n is qdot_{j-n} (qd is read only then)
+__device__ inline double yv(const double *q, const double *qd, int n, int j) { return j < n ? q[j] : qd[j - n]; }
+
+// f_nl(q, qdot)_i = sum t2 y_j y_k + sum t3 y_j y_k y_l (row i of the CSR-by-output tensors)
+__device__ inline double fnl_row(const SysDev &sy, const double *q, const double *qd, int i) {
   double f = 0.0;
+  const int n = sy.n;
   for (int p = sy.f2_ptr[i]; p < sy.f2_ptr[i + 1]; ++p)
-    f += sy.f2_v[p] * q[sy.f2_jk[2 * p]] * q[sy.f2_jk[2 * p + 1]];
+    f += sy.f2_v[p] * yv(q, qd, n, sy.f2_jk[2 * p]) * yv(q, qd, n, sy.f2_jk[2 * p + 1]);
   for (int p = sy.f3_ptr[i]; p < sy.f3_ptr[i + 1]; ++p)
-    f += sy.f3_v[p] * q[sy.f3_jkl[3 * p]] * q[sy.f3_jkl[3 * p + 1]] * q[sy.f3_jkl[3 * p + 2]];
+    f += sy.f3_v[p] * yv(q, qd, n, sy.f3_jkl[3 * p]) * yv(q, qd, n, sy.f3_jkl[3 * p + 1]) *
+         yv(q, qd, n, sy.f3_jkl[3 * p + 2]);
   return f;
 }
 
-// K_t(q) at lower-band position pos = m*(bw+1) + (i-m)
-__device__ inline double kt_entry(const SysDev &sy, const double *q, int pos) {
+// one tangent list at lower-band position pos = m*(bw+1) + (i-m)
+__device__ inline double tangent_list(const int32_t *ptr, const int32_t *idx, const double *cf, int n,
+                                      const double *q, const double *qd, int pos) {
   double v = 0.0;
-  for (int p = sy.kt_ptr[pos]; p < sy.kt_ptr[pos + 1]; ++p) {
-    const int a = sy.kt_idx[2 * p], b = sy.kt_idx[2 * p + 1];
-    v += sy.kt_c[p] * q[a] * (b >= 0 ? q[b] : 1.0);
+  for (int p = ptr[pos]; p < ptr[pos + 1]; ++p) {
+    const int a = idx[2 * p], b = idx[2 * p + 1];
+    v += cf[p] * yv(q, qd, n, a) * (b >= 0 ? yv(q, qd, n, b) : 1.0);
   }
   return v;
+}
+
+// K_t(q, qdot) and C_t(q, qdot) (zero for forces of q only)
+__device__ inline double kt_entry(const SysDev &sy, const double *q, const double *qd, int pos) {
+  return tangent_list(sy.kt_ptr, sy.kt_idx, sy.kt_c, sy.n, q, qd, pos);
+}
+__device__ inline double ct_entry(const SysDev &sy, const double *q, const double *qd, int pos) {
+  return sy.ct_ptr ? tangent_list(sy.ct_ptr, sy.ct_idx, sy.ct_c, sy.n, q, qd, pos) : 0.0;
 }
 
 // Forcing cosines at phi_1 for sample s (Eq. E1): forcing 0 has argument phi_1,
@@ -202,12 +219,12 @@ __global__ void k_idft(const double *__restrict__ Z0, const double *__restrict__
 template <bool LDS>
 __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omega,
                         const int32_t *__restrict__ sidx, const int32_t *__restrict__ Sdim,
-                        double *__restrict__ qhist, const double *__restrict__ u0,
+                        double *__restrict__ qhist, double *__restrict__ uhist, const double *__restrict__ u0,
                         double *__restrict__ zT, int ldw, double *__restrict__ gscr,
                         DevStatus *st) {
   extern __shared__ double smem[];
   const int n = P.n, bw = P.bw, bp = bw + 1, w = blockIdx.x;
-  const size_t stride = (size_t)n * bp + 8 * (size_t)n + 80;
+  const size_t stride = (size_t)n * bp + 9 * (size_t)n + 80;
   double *base = LDS ? smem : gscr + (size_t)w * stride;
   double *Lf = base;
   double *q = Lf + (size_t)n * bp;
@@ -218,6 +235,8 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
   double *r = bv + n;
   double *cs = r + 2 * n;        // e cosines (<= 8)
   double *red = cs + 8;          // block reduction scratch (<= 64)
+  double *qd = red + 72;         // qdot = w1 u of the current iterate (velocity-dependent forces)
+  const bool vel = sy.ct_ptr != nullptr;
   const int b = w / P.St, s = w - b * P.St;
   const double *om = omega + b * P.d;
   const double w1 = om[0];
@@ -228,6 +247,10 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
   for (int i = tid; i < n; i += nt) {
     q[i] = qhist[(size_t)i * ldw + w];
     u[i] = u0[(size_t)i * ldw + w];
+    if (vel) {
+      qd[i] = w1 * u[i];
+      uhist[(size_t)i * ldw + w] = u[i];
+    }
   }
   if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s, P.phib * b);
   __syncthreads();
@@ -241,7 +264,7 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
       if (j < 0 || j >= n) continue;
       v -= w1 * sy.Db[(size_t)i * W2 + t] * u[j] + sy.Kb[(size_t)i * W2 + t] * q[j];
     }
-    a[i] = v - fnl_row(sy, q, i);
+    a[i] = v - fnl_row(sy, q, qd, i);
   }
   for (int pos = tid; pos < n * bp; pos += nt) {
     const int m = pos / bp, t = pos - m * bp, i = m + t;
@@ -277,9 +300,15 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
     bool conv = false;
     int it = 0;
     for (; it < P.maxit && !conv; ++it) {
-      // residual r = S qn + f_nl(qn) - b and tangent band S + K_t(qn)
+      // residual r = S qn + f_nl(qn, qdot) - b and tangent band S + K_t + w1 c2 C_t, with
+      // qdot = w1 u_{k+1}(qn) for velocity-dependent forces
+      if (vel) {
+        for (int i = tid; i < n; i += nt)
+          qd[i] = w1 * (P.c2 * (qn[i] - q[i]) - P.d1 * u[i] - P.d2 * a[i]);
+        __syncthreads();
+      }
       for (int i = tid; i < n; i += nt) {
-        double v = -bv[i] + fnl_row(sy, qn, i);
+        double v = -bv[i] + fnl_row(sy, qn, qd, i);
         const int j0 = i - bw;
         for (int t = 0; t < W2; ++t) {
           const int j = j0 + t;
@@ -295,7 +324,8 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
         double v = 0.0;
         if (i < n) {
           const size_t e = (size_t)i * W2 + (bw - t);
-          v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, pos);
+          v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, qd, pos);
+          if (vel) v += w1 * P.c2 * ct_entry(sy, qn, qd, pos);
         }
         Lf[pos] = v;
       }
@@ -334,6 +364,7 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
       a[i] = an;
       q[i] = qn[i];
       qhist[((size_t)(k + 1) * n + i) * ldw + w] = qn[i];
+      if (vel) uhist[((size_t)(k + 1) * n + i) * ldw + w] = un;
     }
     __syncthreads();
   }
@@ -359,7 +390,8 @@ __global__ void k_state(TrajParams P, SysDev sy, const double *__restrict__ omeg
 // is computed once per step per block, every thread sweeps its column.
 template <bool LDS>
 __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega,
-                       const double *__restrict__ qhist, int ldw, double *__restrict__ PhiQU,
+                       const double *__restrict__ qhist, const double *__restrict__ uhist, int ldw,
+                       double *__restrict__ PhiQU,
                        double *__restrict__ PhiA, double *__restrict__ Ysc,
                        double *__restrict__ gscr, DevStatus *st) {
   extern __shared__ double smem[];
@@ -367,11 +399,14 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
   const int w = blockIdx.y;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = c < n2;
-  const size_t stride = (size_t)2 * n * bp + n + 8;
+  const size_t stride = (size_t)3 * n * bp + 2 * n + 8;
   double *base = LDS ? smem : gscr + ((size_t)w * gridDim.x + blockIdx.x) * stride;
   double *Lf = base;
   double *Kt = Lf + (size_t)n * bp;
-  double *qv = Kt + (size_t)n * bp;
+  double *Ct = Kt + (size_t)n * bp;   // C_t lower band (velocity-dependent forces)
+  double *qv = Ct + (size_t)n * bp;
+  double *qdv = qv + n;               // qdot = w1 u of the replayed state
+  const bool vel = sy.ct_ptr != nullptr;
   const int b = w / P.St;
   const double w1 = omega[b * P.d];
   const double w1s = w1 * w1;
@@ -382,12 +417,16 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
   const int tid = threadIdx.x, nt = blockDim.x;
 
   // ---- initial sensitivities
-  for (int i = tid; i < n; i += nt) qv[i] = qhist[(size_t)i * ldw + w];
+  for (int i = tid; i < n; i += nt) {
+    qv[i] = qhist[(size_t)i * ldw + w];
+    if (vel) qdv[i] = w1 * uhist[(size_t)i * ldw + w];
+  }
   __syncthreads();
   for (int pos = tid; pos < n * bp; pos += nt) {
     const int m = pos / bp, t = pos - m * bp, i = m + t;
     Lf[pos] = i < n ? w1s * sy.Mb[(size_t)i * W2 + (bw - t)] : 0.0;
-    Kt[pos] = i < n ? kt_entry(sy, qv, pos) : 0.0;
+    Kt[pos] = i < n ? kt_entry(sy, qv, qdv, pos) : 0.0;
+    Ct[pos] = (i < n && vel) ? ct_entry(sy, qv, qdv, pos) : 0.0;
   }
   __syncthreads();
   band_ldlt(Lf, n, bw, st);
@@ -402,7 +441,10 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
         }
       } else {
         const int cc = c - n;
-        if (abs(i - cc) <= bw) v = -w1 * sy.Db[(size_t)i * W2 + (cc - i + bw)];
+        if (abs(i - cc) <= bw) {
+          v = -w1 * sy.Db[(size_t)i * W2 + (cc - i + bw)];
+          v -= w1 * (i >= cc ? Ct[cc * bp + (i - cc)] : Ct[i * bp + (cc - i)]);
+        }
       }
       Yc[(size_t)i * n2] = v;
     }
@@ -425,14 +467,22 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
 
   // ---- steps
   for (int k = 0; k < P.S1; ++k) {
-    for (int i = tid; i < n; i += nt) qv[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
+    for (int i = tid; i < n; i += nt) {
+      qv[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
+      if (vel) qdv[i] = w1 * uhist[((size_t)(k + 1) * n + i) * ldw + w];
+    }
     __syncthreads();
     for (int pos = tid; pos < n * bp; pos += nt) {
       const int m = pos / bp, t = pos - m * bp, i = m + t;
       double v = 0.0;
       if (i < n) {
         const size_t e = (size_t)i * W2 + (bw - t);
-        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qv, pos);
+        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qv, qdv, pos);
+        if (vel) {
+          const double ct = ct_entry(sy, qv, qdv, pos);
+          Ct[pos] = ct;
+          v += w1 * P.c2 * ct;
+        }
       }
       Lf[pos] = v;
     }
@@ -446,8 +496,11 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
           const int j = j0 + t;
           if (j < 0 || j >= n) continue;
           const double Qj = Qc[(size_t)j * n2], Uj = Uc[(size_t)j * n2], Aj = Ac[(size_t)j * n2];
+          // velocity-dependent forces linearise into the state-dependent damping D + C_t
+          const double dij = sy.Db[(size_t)i * W2 + t] +
+                             (vel ? (j <= i ? Ct[j * bp + (i - j)] : Ct[i * bp + (j - i)]) : 0.0);
           rhs += w1s * sy.Mb[(size_t)i * W2 + t] * (P.c0 * Qj + P.c1 * Uj + P.c3 * Aj) +
-                 w1 * sy.Db[(size_t)i * W2 + t] * (P.c2 * Qj + P.d1 * Uj + P.d2 * Aj);
+                 w1 * dij * (P.c2 * Qj + P.d1 * Uj + P.d2 * Aj);
         }
         const int t0 = i < bw ? i : bw;
         for (int t = 1; t <= t0; ++t) rhs -= Lf[(i - t) * bp + t] * Yc[(size_t)(i - t) * n2];
@@ -522,7 +575,7 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
       if (j < 0 || j >= n) continue;
       v -= w1 * sy.Db[(size_t)i * W2 + t] * u[j] + sy.Kb[(size_t)i * W2 + t] * q[j];
     }
-    a[i] = v - fnl_row(sy, q, i);
+    a[i] = v - fnl_row(sy, q, q, i);  // forces of q only here: the qdot slot is never read
   }
   for (int pos = tid; pos < n * bp; pos += nt) {
     const int m = pos / bp, t = pos - m * bp, i = m + t;
@@ -570,7 +623,7 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
       double v = 0.0;
       if (i < n) {
         const size_t e = (size_t)i * W2 + (bw - t);
-        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, pos);
+        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, qn, pos);
       }
       Lf[pos] = v;
     }
@@ -727,8 +780,9 @@ __global__ __launch_bounds__(256) void k_jac_gemm(const double *__restrict__ Phi
 }
 
 SysDev sysdev(const fse_ctx *ctx) {
-  return SysDev{ctx->Mb,   ctx->Db,     ctx->Kb,   ctx->F,      ctx->f2_ptr, ctx->f2_jk, ctx->f2_v,
-                ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v, ctx->kt_ptr, ctx->kt_idx, ctx->kt_c};
+  return SysDev{ctx->Mb,     ctx->Db,     ctx->Kb,     ctx->F,      ctx->f2_ptr, ctx->f2_jk, ctx->f2_v,
+                ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v,   ctx->kt_ptr, ctx->kt_idx, ctx->kt_c,
+                ctx->has_vel ? ctx->ct_ptr : nullptr,   ctx->ct_idx, ctx->ct_c,   ctx->n};
 }
 
 TrajParams params(const fse_ctx *ctx, int B) {
@@ -768,14 +822,15 @@ fse_status launch_idft(fse_ctx *ctx, int B, const double *Z0) {
 
 fse_status launch_state(fse_ctx *ctx, int B) {
   const TrajParams P = params(ctx, B);
-  const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 8 * (size_t)ctx->n + 80;
+  const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 9 * (size_t)ctx->n + 80;
+  double *uh = ctx->has_vel ? ctx->uhist : nullptr;
   const size_t bytes = elems * sizeof(double);
   // reset the status word; the first failing step starts at "none"
   hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, ctx->stream, ctx->status_d, INT_MAX);
   const int threads = ctx->bw > 24 ? 256 : 64;
   if (bytes <= kLdsLimit) {
     hipLaunchKernelGGL(k_state<true>, dim3(P.W), dim3(threads), bytes, ctx->stream, P, sysdev(ctx),
-                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->zTw,
+                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, uh, ctx->u0, ctx->zTw,
                        ctx->Wmax, nullptr, ctx->status_d);
   } else {
     if (!ctx->state_scr) {
@@ -785,7 +840,7 @@ fse_status launch_state(fse_ctx *ctx, int B) {
       }
     }
     hipLaunchKernelGGL(k_state<false>, dim3(P.W), dim3(threads), 0, ctx->stream, P, sysdev(ctx),
-                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->zTw,
+                       ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, uh, ctx->u0, ctx->zTw,
                        ctx->Wmax, ctx->state_scr, ctx->status_d);
   }
   FSE_HIP(hipGetLastError());
@@ -804,12 +859,13 @@ fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU) {
   }
   const int C = ctx->sens_cols;
   const int nblk = (int)((n2 + C - 1) / C);
-  const size_t elems = 2 * n * (ctx->bw + 1) + n + 8;
+  const size_t elems = 3 * n * (ctx->bw + 1) + 2 * n + 8;
+  const double *uh = ctx->has_vel ? ctx->uhist : nullptr;
   const size_t bytes = elems * sizeof(double);
   dim3 grid(nblk, P.W);
   if (bytes <= kLdsLimit) {
     hipLaunchKernelGGL(k_sens<true>, grid, dim3(C), bytes, ctx->stream, P, sysdev(ctx), ctx->omega_d,
-                       ctx->qhist, ctx->Wmax, PhiQU, ctx->PhiA, ctx->sens_scr, nullptr, ctx->status_d);
+                       ctx->qhist, uh, ctx->Wmax, PhiQU, ctx->PhiA, ctx->sens_scr, nullptr, ctx->status_d);
   } else {
     const size_t need = elems * nblk * (size_t)ctx->Wmax;
     if (ctx->sens_gscr_elems < need) {
@@ -823,7 +879,7 @@ fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU) {
       ctx->sens_gscr_elems = need;
     }
     hipLaunchKernelGGL(k_sens<false>, grid, dim3(C), 0, ctx->stream, P, sysdev(ctx), ctx->omega_d,
-                       ctx->qhist, ctx->Wmax, PhiQU, ctx->PhiA, ctx->sens_scr, ctx->sens_gscr,
+                       ctx->qhist, uh, ctx->Wmax, PhiQU, ctx->PhiA, ctx->sens_scr, ctx->sens_gscr,
                        ctx->status_d);
   }
   ctx->last_sens_launches = 1;
@@ -953,6 +1009,10 @@ __global__ void k_set_pcol(double *__restrict__ A, size_t ldA, int N, int nu, co
 }
 
 fse_status launch_wsens(fse_ctx *ctx, int B, double *dzT) {
+  if (ctx->has_vel) {
+    ctx->err = "the omega_1 sensitivity is built for forces of q only";
+    return FSE_E_UNSUPPORTED;
+  }
   const fse_status fs = ctx->wsens_generic ? FSE_E_UNSUPPORTED : launch_wsens_fused(ctx, B, dzT);
   if (fs != FSE_E_UNSUPPORTED) return fs;
   const TrajParams P = params(ctx, B);

@@ -1,0 +1,94 @@
+"""GPU trajectories with velocity-dependent forces f_nl(q, qdot) (Eq. 1; factor index n + j
+names qdot_j) against the oracle's general Newmark branch.
+
+Bar: states, sensitivities, residual and Jacobian within 1e-10 normwise relative of the
+oracle; the forced van der Pol torus (omega_2 unknown) solved on the GPU to ||R|| < 1e-8,
+equal to the oracle's solve within 1e-8, Lyapunov exponents within 1e-6 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+from _velocity_systems import mixed_system, van_der_pol
+from fse_inputs import Torus
+from fse_inputs.systems import place_harmonics
+from oracle import lyapunov as oly
+from oracle import shooting as osh
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-10
+
+
+def fse():
+    import paper_2508_06302_amd as m
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("beta,gamma", [(0.25, 0.5), (0.3025, 0.6)])
+@pytest.mark.parametrize("n", [3, 9])
+def test_states_sensitivities_residual_and_jacobian(n, beta, gamma):
+    s = mixed_system(n=n)
+    om = np.array([0.9, 0.9 * 1.618])
+    tr = Torus(d=2, e=2, K=[np.arange(1, 4)], S=[8], S1=64, beta=beta, gamma=gamma)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(n).normal(size=(2 * n, tb.U))
+    log(f"velocity forces n={n} beta={beta} gamma={gamma}")
+    ref = osh.evaluate(s, tr, om, Z0, sens=True, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    zT, phi = fse().fse_integrate_batch(ctx, om[None], Z0[None], want_phi=True)
+    assert rel(zT[0].cpu().numpy(), ref["zbarT"]) < RTOL
+    assert rel(phi[0].cpu().numpy(), ref["Phi"]) < RTOL
+    R, rn, J = fse().fse_shooting_residual_jacobian(ctx, om[None], Z0[None], want_J=True)
+    assert rel(R[0].cpu().numpy(), ref["R"]) < RTOL
+    assert rel(J[0].cpu().numpy(), osh.jacobian(ref)) < RTOL
+
+
+def test_forced_van_der_pol_newton_and_lyapunov():
+    import torch
+    mu, w1 = 0.2, 2.3
+    s = van_der_pol(mu=mu)
+    tr = Torus(d=2, e=1, K=[np.arange(1, 8)], S=[16], S1=128)
+    tb = osh.TorusTables(tr)
+    A = 0.5 / (1 - w1 ** 2)
+    Z0 = place_harmonics(tb.table, [((0,), np.array([A, 0.0], complex)), ((1,), np.array([2.0, 2j / w1]))],
+                         1, tb.U)
+    om0 = np.array([w1, 1.0])
+    ctx = fse().fse_init_torus(s, tr)
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    omg = om0.copy()
+    it, rn = fse().fse_newton_solve(ctx, omg, Zg, tol=1e-10, maxit=25)
+    log(f"van der Pol: {it} Newton iterations, ||R|| {rn:.3e}, omega_2 {omg[1]:.12f}")
+    assert rn < 1e-8
+    Zo, omo, hist = osh.solve(s, tr, om0, Z0, tol_R=1e-10, max_newton=25, tables=tb)
+    assert abs(omg[1] - omo[1]) < 1e-9
+    assert rel(Zg.cpu().numpy(), Zo) < 1e-8
+    sg = fse().fse_lyapunov(ctx, omo, Zo, N_Ly=200)
+    res = osh.evaluate(s, tr, omo, Zo, sens=True, tables=tb)
+    so = oly.exponents(res["Phi"], omo, tb, N_Ly=200)[0]
+    log(f"Lyapunov GPU {sg} oracle {so}")
+    assert np.max(np.abs(sg - so)) < 1e-6
+
+
+def test_refusals():
+    s = mixed_system()
+    tr = Torus(d=2, e=2, K=[np.arange(1, 4)], S=[8], S1=64)
+    tb = osh.TorusTables(tr)
+    ctx = fse().fse_init_torus(s, tr)
+    om = np.array([0.9, 0.9 * 1.618])
+    Z0 = np.zeros((2 * s.n, tb.U))
+    with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
+        fse().fse_residual_dp(ctx, om[None], Z0[None])
+    bad = mixed_system()
+    bad.t3_idx = np.vstack([bad.t3_idx, [[0, 1, 1, bad.n + 2]]]).astype(np.int32)
+    bad.t3_val = np.concatenate([bad.t3_val, [0.5]])
+    with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
+        fse().fse_init_torus(bad, tr)
