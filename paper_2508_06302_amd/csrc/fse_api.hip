@@ -486,7 +486,8 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
   else
     FSE_TRY(launch_idft(ctx, B, Z0));
   FSE_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-  const bool fused = ctx->use_fused && fused_supported(ctx);
+  // the fused kernel evaluates forces of q only; velocity-dependent forces take the generic kernels
+  const bool fused = ctx->use_fused && !ctx->has_vel && fused_supported(ctx);
   if (!fused && Phi && ctx->prec == FSE_PREC_MIXED_FP32) {
     ctx->err = "FP32 sensitivities need the fused kernel (half bandwidth <= 16, LDS fit)";
     return FSE_E_UNSUPPORTED;

@@ -787,8 +787,7 @@ size_t lds_for(const fse_ctx *ctx) {
 int fused_band_bucket(const fse_ctx *ctx) { return bw_bucket(ctx->bw); }
 
 bool fused_supported(const fse_ctx *ctx) {
-  return !ctx->has_vel && ctx->bw <= 16 && ctx->n < 65536 && ctx->f2_pk && ctx->f3_pk &&
-         lds_for(ctx) + 64 <= 160 * 1024 &&
+  return ctx->bw <= 16 && ctx->n < 65536 && ctx->f2_pk && ctx->f3_pk && lds_for(ctx) + 64 <= 160 * 1024 &&
          ctx->fused_ncw >= 1 && ctx->fused_ncw <= 2;
 }
 
