@@ -38,6 +38,11 @@ class System:
     t3_idx: np.ndarray      # int32 [nnz3, 4]  (i, j, k, l), j <= k <= l
     t3_val: np.ndarray      # float64 [nnz3]
     F: np.ndarray           # float64 [e, n] load amplitude vectors
+    # unilateral contacts (penalty springs), one row each: dof, direction (+1 / -1), gap, stiffness
+    con_dof: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    con_dir: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    con_gap: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    con_k: np.ndarray = field(default_factory=lambda: np.zeros(0))
 
     @property
     def n(self) -> int:

@@ -17,7 +17,11 @@ Readings where the paper is silent:
   * f_nl may depend on qdot = omega_1 u (Eq. 1 allows it; the paper's examples do not):
     a tensor factor index in [n, 2n) names qdot.  Its tangent C_t = d f_nl / d qdot adds
     omega_1 gamma/(beta h) C_t to the step's iteration matrix and enters the
-    sensitivities as the state-dependent damping D + C_t (general rule only).
+    sensitivities as the state-dependent damping D + C_t (general rule only);
+  * nonsmooth forces (the paper recommends the extension without giving one) are read as
+    unilateral penalty contacts, piecewise linear in q: the step Newton uses the generalised
+    derivative (contact closed iff s q_i - g > 0), and the sensitivities are the derivative of
+    the discrete map wherever no step lands exactly on a gap (almost everywhere).
 
 Pins (tests/test_oracle_newmark.py): the closed-form average-acceleration
 response of an undamped oscillator (unit amplitude, phase 2 atan(Omega h/2) per
@@ -26,7 +30,11 @@ central finite differences of the sensitivities and of the omega-derivatives;
 with velocity-dependent forces (tests/test_oracle_velocity.py) finite differences
 of the sensitivities and of both tangents, and the forced van der Pol torus against
 the averaging result (limit-cycle frequency 1 - mu^2/16, amplitude 2) and its
-Lyapunov exponents (one zero, one near -mu).
+Lyapunov exponents (one zero, one near -mu); with unilateral contacts
+(tests/test_oracle_contact.py) the step equation solved by its case split, open contacts
+changing nothing, finite differences of the sensitivities, second-order convergence of the
+impact orbit to the exact piecewise flow, the orbit as the end of a long transient, and the
+half-wave symmetry of two symmetric stops.
 """
 from __future__ import annotations
 
@@ -47,6 +55,29 @@ def has_velocity(sysm) -> bool:
                 or (len(sysm.t3_val) and sysm.t3_idx[:, 1:].max() >= n))
 
 
+def has_contact(sysm) -> bool:
+    return len(getattr(sysm, "con_k", ())) > 0
+
+
+def contact_force(sysm, q: np.ndarray) -> np.ndarray:
+    """Unilateral penalty contacts, a nonsmooth f_nl (the paper's third recommendation): contact c
+    on DOF i with direction s = +-1, gap g and stiffness k pushes back with s k max(s q_i - g, 0)."""
+    f = np.zeros(len(q))
+    for i, sg, g, k in zip(sysm.con_dof, sysm.con_dir, sysm.con_gap, sysm.con_k):
+        f[i] += sg * k * max(sg * q[i] - g, 0.0)
+    return f
+
+
+def contact_tangent(sysm, q: np.ndarray) -> np.ndarray:
+    """Generalised derivative of contact_force: k on the diagonal of a closed contact
+    (s q_i - g > 0); an open contact or one exactly at its gap contributes nothing."""
+    Kt = np.zeros((len(q), len(q)))
+    for i, sg, g, k in zip(sysm.con_dof, sysm.con_dir, sysm.con_gap, sysm.con_k):
+        if sg * q[i] - g > 0.0:
+            Kt[i, i] += k
+    return Kt
+
+
 def _y(q, qd):
     return q if qd is None else np.concatenate([q, qd])
 
@@ -62,6 +93,8 @@ def internal_force(sysm, q: np.ndarray, qd: np.ndarray = None) -> np.ndarray:
     if len(sysm.t3_val):
         i, j, k, l = sysm.t3_idx.T
         f += np.bincount(i, weights=sysm.t3_val * y[j] * y[k] * y[l], minlength=n)
+    if has_contact(sysm):
+        f += contact_force(sysm, q)
     return f
 
 
@@ -81,7 +114,8 @@ def tangents(sysm, q: np.ndarray, qd: np.ndarray = None):
         np.add.at(G, (i, j), v * y[k] * y[l])
         np.add.at(G, (i, k), v * y[j] * y[l])
         np.add.at(G, (i, l), v * y[j] * y[k])
-    return G[:, :n], (G[:, n:] if qd is not None else np.zeros((n, n)))
+    Kt = G[:, :n] + (contact_tangent(sysm, q) if has_contact(sysm) else 0.0)
+    return Kt, (G[:, n:] if qd is not None else np.zeros((n, n)))
 
 
 def tangent(sysm, q: np.ndarray) -> np.ndarray:
@@ -99,6 +133,8 @@ def tangent(sysm, q: np.ndarray) -> np.ndarray:
         np.add.at(Kt, (i, j), v * q[k] * q[l])
         np.add.at(Kt, (i, k), v * q[j] * q[l])
         np.add.at(Kt, (i, l), v * q[j] * q[k])
+    if has_contact(sysm):
+        Kt += contact_tangent(sysm, q)
     return Kt
 
 

@@ -28,3 +28,19 @@ def mixed_system(n=3, seed=2, e=2, eps=0.4, mu=0.3):
     s.t3_idx = np.array(idx, np.int32)
     s.t3_val = np.array(val)
     return s
+
+
+def with_contacts(s, dof, direction, gap, k):
+    """Copy of s with unilateral penalty contacts (dof, direction +-1, gap, stiffness)."""
+    import dataclasses
+    return dataclasses.replace(s, con_dof=np.asarray(dof, np.int32), con_dir=np.asarray(direction, np.int32),
+                               con_gap=np.asarray(gap, float), con_k=np.asarray(k, float))
+
+
+def impact_oscillator(c=0.2, kc=4.0, gap=0.3, F=0.6, two_sided=False):
+    """q'' + c q' + q + contacts = F cos(omega_1 t) with a stop at q = gap (and at -gap)."""
+    s = System("impact", np.eye(1), np.array([[c]]), np.eye(1), np.zeros((0, 3), np.int32), np.zeros(0),
+               np.zeros((0, 4), np.int32), np.zeros(0), np.array([[F]]))
+    if two_sided:
+        return with_contacts(s, [0, 0], [1, -1], [gap, gap], [kc, kc])
+    return with_contacts(s, [0], [1], [gap], [kc])
