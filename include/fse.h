@@ -165,6 +165,20 @@ fse_status fse_newton_solve(fse_ctx *ctx, double *omega, double *Z0, double tol,
  * (states, sensitivities, d/d omega).  FSE_E_INVAL unless beta > 0 and gamma > 0, finite. */
 fse_status fse_set_newmark(fse_ctx *ctx, double beta, double gamma);
 
+/* Unilateral penalty contacts, a nonsmooth part of f_nl (the paper's conclusions recommend
+ * the extension to nonsmooth systems without giving a form): contact c on DOF dof[c] with
+ * direction dir[c] = +1 or -1, gap gap[c] and stiffness stiff[c] >= 0 adds
+ * dir k max(dir q_i - gap, 0) to f_nl(q)_i.  The step Newton and the sensitivities use its
+ * generalised derivative (k on the diagonal while dir q_i - gap > 0, nothing at or below
+ * the gap), so Phi, J and dR/dp are the derivatives of the discrete map wherever no step
+ * lands exactly on a gap.  Such systems run on the generic trajectory kernels, so the
+ * mixed-precision path returns FSE_E_UNSUPPORTED.  All arrays HOST [m], copied; m = 0
+ * removes the contacts.  Replaces the previous set; waits for the context's stream first.
+ * Applies to every later call.  FSE_E_INVAL for a DOF outside [0, n), a direction other
+ * than +-1, or a gap or stiffness that is not finite (or a negative stiffness). */
+fse_status fse_set_contacts(fse_ctx *ctx, int32_t m, const int32_t *dof, const int32_t *dir,
+                            const double *gap, const double *stiff);
+
 /* Forcing amplitudes: the load vectors of Eq. (25) become amp_i F_i, with the F given
  * to fse_init_torus as amplitude 1 (the paper's examples list the amplitudes f_i in
  * Sec. 4, Tables 1-4).  amp: HOST [e].  Applies to every later call. */

@@ -15,7 +15,7 @@ from . import _lib
 
 __all__ = ["FseError", "Context", "fse_init_torus", "fse_get_layout", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
-           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing", "fse_set_newmark",
+           "fse_newton_solve", "fse_lyapunov", "fse_last_timing", "fse_set_forcing", "fse_set_newmark", "fse_set_contacts",
            "fse_secant_predict", "fse_continuation", "fse_residual_domega", "Learned",
            "fse_learned_create", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
            "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step",
@@ -126,6 +126,8 @@ def fse_init_torus(system, torus, max_batch=1, precision=FSE_PREC_FP64, step_tol
     beta, gamma = getattr(torus, "beta", 0.25), getattr(torus, "gamma", 0.5)
     if (beta, gamma) != (0.25, 0.5):
         fse_set_newmark(ctx, beta, gamma)
+    if len(getattr(system, "con_k", ())):
+        fse_set_contacts(ctx, system.con_dof, system.con_dir, system.con_gap, system.con_k)
     return ctx
 
 
@@ -264,6 +266,19 @@ def fse_get_tuning(ctx: Context):
 
 def fse_set_newmark(ctx: Context, beta, gamma):
     ctx.check(ctx.lib.fse_set_newmark(ctx.h, float(beta), float(gamma)))
+
+
+def fse_set_contacts(ctx: Context, dof, direction, gap, stiffness):
+    """Unilateral penalty contacts (host arrays of equal length m; m = 0 removes them)."""
+    dof = np.ascontiguousarray(dof, dtype=np.int32).reshape(-1)
+    dr = np.ascontiguousarray(direction, dtype=np.int32).reshape(-1)
+    g = np.ascontiguousarray(gap, dtype=np.float64).reshape(-1)
+    k = np.ascontiguousarray(stiffness, dtype=np.float64).reshape(-1)
+    m = dof.size
+    if not (dr.size == g.size == k.size == m):
+        raise ValueError("contact arrays must have equal lengths")
+    ctx.check(ctx.lib.fse_set_contacts(ctx.h, m, _p(dof, C.c_int32), _p(dr, C.c_int32), _p(g, C.c_double),
+                                       _p(k, C.c_double)))
 
 
 def fse_set_forcing(ctx: Context, amp):

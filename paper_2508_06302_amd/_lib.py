@@ -12,7 +12,7 @@ FSE_STATUS = {0: "FSE_OK", 1: "FSE_E_INVAL", 2: "FSE_E_NOMEM", 3: "FSE_E_DEVICE"
 
 EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_batch",
            "fse_step_stats", "fse_shooting_residual_jacobian", "fse_newton_step",
-           "fse_newton_solve", "fse_lyapunov", "fse_set_forcing", "fse_set_newmark", "fse_secant_predict",
+           "fse_newton_solve", "fse_lyapunov", "fse_set_forcing", "fse_set_newmark", "fse_set_contacts", "fse_secant_predict",
            "fse_continuation", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
            "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_newton_krylov_step",
            "fse_hypertime_residual_jacobian", "fse_hypertime_newton_step", "fse_multiple_residual_jacobian",
@@ -70,6 +70,7 @@ def load(path: str = LIB_PATH):
     lib.fse_lyapunov.argtypes = [vp, f64p, vp, C.c_int32, vp, f64p]
     lib.fse_set_forcing.argtypes = [vp, f64p]
     lib.fse_set_newmark.argtypes = [vp, C.c_double, C.c_double]
+    lib.fse_set_contacts.argtypes = [vp, C.c_int32, i32p, i32p, f64p, f64p]
     lib.fse_secant_predict.argtypes = [vp, C.c_int32, f64p, f64p, f64p, vp, vp, vp]
     lib.fse_continuation.argtypes = [vp, C.c_int32, f64p, vp, C.c_double, C.c_int32, vp, i32p, f64p]
     lib.fse_residual_dp.argtypes = [vp, C.c_int32, f64p, vp, vp, vp]

@@ -415,7 +415,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
                   ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult,
-                  ctx->ct_ptr, ctx->ct_idx, ctx->ct_c, ctx->uhist};
+                  ctx->ct_ptr, ctx->ct_idx, ctx->ct_c, ctx->uhist, ctx->cn_ptr, ctx->cn_v};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
   if (ctx->f3_pk) (void)hipFree(ctx->f3_pk);
   for (void *p : ptrs)
@@ -486,8 +486,7 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
   else
     FSE_TRY(launch_idft(ctx, B, Z0));
   FSE_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-  // the fused kernel evaluates forces of q only; velocity-dependent forces take the generic kernels
-  const bool fused = ctx->use_fused && !ctx->has_vel && fused_supported(ctx);
+  const bool fused = fused_eligible(ctx);
   if (!fused && Phi && ctx->prec == FSE_PREC_MIXED_FP32) {
     ctx->err = "FP32 sensitivities need the fused kernel (half bandwidth <= 16, LDS fit)";
     return FSE_E_UNSUPPORTED;
@@ -803,6 +802,46 @@ fse_status fse_set_newmark(fse_ctx *ctx, double beta, double gamma) {
   }
   ctx->nm_beta = beta;
   ctx->nm_gamma = gamma;
+  return FSE_OK;
+}
+
+fse_status fse_set_contacts(fse_ctx *ctx, int32_t m, const int32_t *dof, const int32_t *dir,
+                            const double *gap, const double *stiff) {
+  if (!ctx) return FSE_E_INVAL;
+  if (m < 0 || (m > 0 && (!dof || !dir || !gap || !stiff))) {
+    ctx->err = "invalid contact arrays";
+    return FSE_E_INVAL;
+  }
+  const int n = ctx->n;
+  for (int c = 0; c < m; ++c)
+    if (dof[c] < 0 || dof[c] >= n || (dir[c] != 1 && dir[c] != -1) || !std::isfinite(gap[c]) ||
+        !std::isfinite(stiff[c]) || stiff[c] < 0.0) {
+      ctx->err = "contact " + std::to_string(c) + ": dof out of range, direction not +-1, or gap / stiffness "
+                 "not finite (stiffness must be >= 0)";
+      return FSE_E_INVAL;
+    }
+  std::vector<int32_t> ptr(n + 1, 0);
+  for (int c = 0; c < m; ++c) ptr[dof[c] + 1]++;
+  for (int i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  std::vector<double> v(3 * (size_t)m);
+  for (int c = 0; c < m; ++c) {
+    const int p = fill[dof[c]]++;
+    v[3 * p] = (double)dir[c];
+    v[3 * p + 1] = gap[c];
+    v[3 * p + 2] = stiff[c];
+  }
+  // earlier work on the stream may still read the old lists
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->cn_ptr) (void)hipFree(ctx->cn_ptr);
+  if (ctx->cn_v) (void)hipFree(ctx->cn_v);
+  ctx->cn_ptr = nullptr;
+  ctx->cn_v = nullptr;
+  ctx->ncon = 0;
+  if (m == 0) return FSE_OK;
+  FSE_TRY(upload(ctx, &ctx->cn_ptr, ptr));
+  FSE_TRY(upload(ctx, &ctx->cn_v, v));
+  ctx->ncon = m;
   return FSE_OK;
 }
 

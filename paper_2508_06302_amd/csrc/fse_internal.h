@@ -89,6 +89,10 @@ struct fse_ctx {
   // same layout as kt_*, and the velocity history [S1+1][n][Wmax] for the sensitivity pass
   bool has_vel = false;
   int32_t *ct_ptr = nullptr, *ct_idx = nullptr;  double *ct_c = nullptr;
+  // unilateral contacts, CSR by DOF: cn_v holds (direction, gap, stiffness) per contact
+  int32_t ncon = 0;
+  int32_t *cn_ptr = nullptr;
+  double *cn_v = nullptr;
   double *uhist = nullptr;
   // torus
   double *G_d = nullptr, *Gi_d = nullptr;
@@ -194,6 +198,10 @@ fse_status launch_dRdp_rot(fse_ctx *ctx, int B, const double *omega, const doubl
 fse_status launch_set_pcol(fse_ctx *ctx, double *A, size_t ldA, const double *col);
 // Fused state + sensitivity kernel (k_fused.hip), half bandwidth <= 16
 bool fused_supported(const fse_ctx *ctx);
+// The fused kernel evaluates polynomial forces of q only; other systems take the generic kernels.
+inline bool fused_eligible(const fse_ctx *ctx) {
+  return ctx->use_fused && !ctx->has_vel && ctx->ncon == 0 && fused_supported(ctx);
+}
 void newmark_coefficients(const fse_ctx *ctx, TrajParams &p);  // h, c0 .. d2
 fse_status launch_fused(fse_ctx *ctx, int B, double *Phi);
 // compile-time half bandwidth (4, 6, 8, 12 or 16) the fused kernels use for this system

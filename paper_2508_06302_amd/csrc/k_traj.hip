@@ -139,7 +139,9 @@ struct SysDev {
   const double *kt_c;
   const int32_t *ct_ptr, *ct_idx;  // C_t = d f / d qdot lists, or null (forces of q only)
   const double *ct_c;
-  int n;
+  const int32_t *cn_ptr;  // unilateral contacts by DOF, or null
+  const double *cn_v;     // (direction, gap, stiffness) per contact
+  int bw, n;
 };
 
 // y = [q; qdot]: factor index j < n is q_j, j >= n is qdot_{j-n} (qd is read only then)
@@ -154,6 +156,11 @@ __device__ inline double fnl_row(const SysDev &sy, const double *q, const double
   for (int p = sy.f3_ptr[i]; p < sy.f3_ptr[i + 1]; ++p)
     f += sy.f3_v[p] * yv(q, qd, n, sy.f3_jkl[3 * p]) * yv(q, qd, n, sy.f3_jkl[3 * p + 1]) *
          yv(q, qd, n, sy.f3_jkl[3 * p + 2]);
+  if (sy.cn_ptr)  // a closed contact pushes back with s k (s q_i - g)
+    for (int p = sy.cn_ptr[i]; p < sy.cn_ptr[i + 1]; ++p) {
+      const double sg = sy.cn_v[3 * p], pen = sg * q[i] - sy.cn_v[3 * p + 1];
+      if (pen > 0.0) f += sg * sy.cn_v[3 * p + 2] * pen;
+    }
   return f;
 }
 
@@ -169,8 +176,16 @@ __device__ inline double tangent_list(const int32_t *ptr, const int32_t *idx, co
 }
 
 // K_t(q, qdot) and C_t(q, qdot) (zero for forces of q only)
+// K_t includes the generalised derivative of the contacts: k on the diagonal of a closed one.
 __device__ inline double kt_entry(const SysDev &sy, const double *q, const double *qd, int pos) {
-  return tangent_list(sy.kt_ptr, sy.kt_idx, sy.kt_c, sy.n, q, qd, pos);
+  double v = tangent_list(sy.kt_ptr, sy.kt_idx, sy.kt_c, sy.n, q, qd, pos);
+  if (sy.cn_ptr) {
+    const int bp = sy.bw + 1, m = pos / bp;
+    if (pos == m * bp)
+      for (int p = sy.cn_ptr[m]; p < sy.cn_ptr[m + 1]; ++p)
+        if (sy.cn_v[3 * p] * q[m] - sy.cn_v[3 * p + 1] > 0.0) v += sy.cn_v[3 * p + 2];
+  }
+  return v;
 }
 __device__ inline double ct_entry(const SysDev &sy, const double *q, const double *qd, int pos) {
   return sy.ct_ptr ? tangent_list(sy.ct_ptr, sy.ct_idx, sy.ct_c, sy.n, q, qd, pos) : 0.0;
@@ -782,7 +797,8 @@ __global__ __launch_bounds__(256) void k_jac_gemm(const double *__restrict__ Phi
 SysDev sysdev(const fse_ctx *ctx) {
   return SysDev{ctx->Mb,     ctx->Db,     ctx->Kb,     ctx->F,      ctx->f2_ptr, ctx->f2_jk, ctx->f2_v,
                 ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v,   ctx->kt_ptr, ctx->kt_idx, ctx->kt_c,
-                ctx->has_vel ? ctx->ct_ptr : nullptr,   ctx->ct_idx, ctx->ct_c,   ctx->n};
+                ctx->has_vel ? ctx->ct_ptr : nullptr,   ctx->ct_idx, ctx->ct_c,
+                ctx->ncon ? ctx->cn_ptr : nullptr,      ctx->cn_v,   ctx->bw,     ctx->n};
 }
 
 TrajParams params(const fse_ctx *ctx, int B) {
