@@ -146,6 +146,21 @@ def run_precision(fse, torch, wl, prec, steps, warmup, solve):
            "value": St * tr.S1 / (el / steps), "kernel_ms": float(np.mean(kern_ms)),
            "fused": tm["sens_launches"] == 1 and tm["sens_ms"] < 0.05 * tm["state_ms"]}
     progress(f"precision {prec}: {res['ms_per_step']:.1f} ms per step")
+    if prec == fse.FSE_PREC_FP64:
+        # the trajectories alone (states, no sensitivities): same workload and step count
+        for _ in range(warmup):
+            fse.fse_integrate_batch(ctx, om, Zd)
+        torch.cuda.synchronize()
+        st_ms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fse.fse_integrate_batch(ctx, om, Zd)
+            st_ms.append(fse.fse_last_timing(ctx)["state_ms"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res["state_only"] = {"value": St * tr.S1 / (el / steps), "unit": "trajectory-steps/s",
+                             "ms_per_step": 1e3 * el / steps, "kernel_ms_per_launch": float(np.mean(st_ms))}
+        progress(f"precision {prec}: state only {res['state_only']['ms_per_step']:.1f} ms per step")
     if solve:
         # shooting solve: natural-parameter continuation in the forcing amplitude
         # f1 = f2 = 0.1 ... 0.5 N at the same omega, secant predictor, ||R||_2 < 1e-8 per point
@@ -261,6 +276,7 @@ def main():
                      "kernel_ms_per_launch": plain["kernel_ms"],
                      "algorithmic_bytes_per_launch": alg_bytes},
         "autotuner": plain["tuning"],
+        "state_only": plain["state_only"],
     }
     if mixed is not None:
         out["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
