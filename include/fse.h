@@ -69,8 +69,8 @@ typedef enum {
  * Velocity-dependent forces f_nl(q, qdot) (Eq. 1): a factor index j, k or l
  * in [n, 2n) names qdot_{index - n} (qdot = omega_1 dq/dphi_1); the output
  * index i stays in [0, n).  Then d f_nl / d qdot must be symmetric as well
- * (FSE_E_UNSUPPORTED otherwise), such systems run on the generic trajectory
- * kernels, and fse_residual_dp / fse_arclength return FSE_E_UNSUPPORTED.
+ * (FSE_E_UNSUPPORTED otherwise), and such systems run on the generic trajectory
+ * kernels (so the mixed-precision path returns FSE_E_UNSUPPORTED).
  * Indices outside these ranges return FSE_E_INVAL.
  * F: [e][n] load amplitude vectors, forcing i has frequency omega_i. */
 typedef struct {

@@ -104,6 +104,7 @@ struct fse_ctx {
   double *u0 = nullptr;             // [n][Wmax]
   double *zTw = nullptr;            // [2n][Wmax]
   double *state_scr = nullptr;      // per trajectory scratch for large systems
+  size_t state_scr_elems = 0;       // its size in doubles (grown, never shrunk)
   double *PhiA = nullptr;           // [Wmax][n][2n]
   double *PhiQU = nullptr;          // [Wmax][2n][2n] internal when caller passes none
   double *sens_scr = nullptr;       // per block factor + per column y

@@ -548,6 +548,11 @@ __global__ void k_sens(TrajParams P, SysDev sy, const double *__restrict__ omega
 // derivative of the consistent initial acceleration).  One block per trajectory; the state is
 // replayed from the displacement history of the integration, so the derivative is that of the
 // very trajectory whose end point enters R.  Output dzT [2n][ldw] = [Qw; Uw](2 pi).
+// entry (i, j) of a symmetric matrix from its lower band (pos = m (bw+1) + (i - m), m <= i)
+__device__ inline double ct_band(const double *Cb, int bp, int i, int j) {
+  return i >= j ? Cb[j * bp + (i - j)] : Cb[i * bp + (j - i)];
+}
+
 template <bool LDS>
 __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omega,
                         const int32_t *__restrict__ sidx, const int32_t *__restrict__ Sdim,
@@ -555,7 +560,8 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
                         double *__restrict__ dzT, double *__restrict__ gscr, DevStatus *st) {
   extern __shared__ double smem[];
   const int n = P.n, bw = P.bw, bp = bw + 1, w = blockIdx.x;
-  const size_t stride = (size_t)n * bp + 8 * (size_t)n + 80;
+  const bool vel = sy.ct_ptr != nullptr;
+  const size_t stride = (size_t)n * bp + 8 * (size_t)n + 80 + (vel ? (size_t)n * bp + n : 0);
   double *base = LDS ? smem : gscr + (size_t)w * stride;
   double *Lf = base;
   double *q = Lf + (size_t)n * bp;
@@ -568,6 +574,9 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
   double *x = Aw + n;
   double *cs = x + n;            // e cosines (<= 8)
   double *red = cs + 8;          // block reduction scratch (<= 64)
+  // velocity-dependent forces: C_t lower band and qdot = w1 u of the current state
+  double *Ct = red + 72;
+  double *qd = Ct + (size_t)n * bp;
   const int b = w / P.St, s = w - b * P.St;
   const double *om = omega + b * P.d;
   const double w1 = om[0];
@@ -578,6 +587,7 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
   for (int i = tid; i < n; i += nt) {
     q[i] = qhist[(size_t)i * ldw + w];
     u[i] = u0[(size_t)i * ldw + w];
+    if (vel) qd[i] = w1 * u[i];
   }
   if (tid < P.e) cs[tid] = forcing_cos(tid, 0.0, om, sidx, Sdim, P.St, s, P.phib * b);
   __syncthreads();
@@ -590,22 +600,24 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
       if (j < 0 || j >= n) continue;
       v -= w1 * sy.Db[(size_t)i * W2 + t] * u[j] + sy.Kb[(size_t)i * W2 + t] * q[j];
     }
-    a[i] = v - fnl_row(sy, q, q, i);  // forces of q only here: the qdot slot is never read
+    a[i] = v - fnl_row(sy, q, vel ? qd : q, i);  // without velocity forces the qdot slot is never read
   }
   for (int pos = tid; pos < n * bp; pos += nt) {
     const int m = pos / bp, t = pos - m * bp, i = m + t;
     Lf[pos] = i < n ? w1s * sy.Mb[(size_t)i * W2 + (bw - t)] : 0.0;
+    if (vel) Ct[pos] = i < n ? ct_entry(sy, q, qd, pos) : 0.0;
   }
   __syncthreads();
   band_ldlt(Lf, n, bw, st);
   band_solve(Lf, n, bw, a, red);
-  // (w1^2 M) Aw_0 = -D u0 - 2 w1 M a0
+  // (w1^2 M) Aw_0 = -(D + C_t) u0 - 2 w1 M a0
   for (int i = tid; i < n; i += nt) {
     double v = 0.0;
     for (int t = 0; t < W2; ++t) {
       const int j = i - bw + t;
       if (j < 0 || j >= n) continue;
-      v -= sy.Db[(size_t)i * W2 + t] * u[j] + 2.0 * w1 * sy.Mb[(size_t)i * W2 + t] * a[j];
+      const double Dij = sy.Db[(size_t)i * W2 + t] + (vel ? ct_band(Ct, bp, i, j) : 0.0);
+      v -= Dij * u[j] + 2.0 * w1 * sy.Mb[(size_t)i * W2 + t] * a[j];
     }
     x[i] = v;
   }
@@ -619,14 +631,27 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
   __syncthreads();
 
   for (int k = 0; k < P.S1; ++k) {
-    for (int i = tid; i < n; i += nt) qn[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
+    for (int i = tid; i < n; i += nt) {
+      qn[i] = qhist[((size_t)(k + 1) * n + i) * ldw + w];
+      // qdot of the step's end state, for C_t: u_{k+1} follows from q_{k+1} (Newmark relations)
+      if (vel) qd[i] = w1 * (P.c2 * (qn[i] - q[i]) - P.d1 * u[i] - P.d2 * a[i]);
+    }
     __syncthreads();
+    if (vel) {
+      for (int pos = tid; pos < n * bp; pos += nt) {
+        const int m = pos / bp, i = m + (pos - m * bp);
+        Ct[pos] = i < n ? ct_entry(sy, qn, qd, pos) : 0.0;
+      }
+      __syncthreads();
+    }
     for (int i = tid; i < n; i += nt) {
       double v = 0.0;
       for (int t = 0; t < W2; ++t) {
         const int j = i - bw + t;
         if (j < 0 || j >= n) continue;
-        const double Mij = sy.Mb[(size_t)i * W2 + t], Dij = sy.Db[(size_t)i * W2 + t];
+        // the velocity-dependent forces linearise into the damping D + C_t
+        const double Mij = sy.Mb[(size_t)i * W2 + t];
+        const double Dij = sy.Db[(size_t)i * W2 + t] + (vel ? ct_band(Ct, bp, i, j) : 0.0);
         v += w1s * Mij * (P.c0 * Qw[j] + P.c1 * Uw[j] + P.c3 * Aw[j]) + w1 * Dij * (P.c2 * Qw[j] + P.d1 * Uw[j] + P.d2 * Aw[j]);
         v += -(2.0 * w1 * P.c0 * Mij + P.c2 * Dij) * qn[j] +
              2.0 * w1 * Mij * (P.c0 * q[j] + P.c1 * u[j] + P.c3 * a[j]) + Dij * (P.c2 * q[j] + P.d1 * u[j] + P.d2 * a[j]);
@@ -638,7 +663,8 @@ __global__ void k_wsens(TrajParams P, SysDev sy, const double *__restrict__ omeg
       double v = 0.0;
       if (i < n) {
         const size_t e = (size_t)i * W2 + (bw - t);
-        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, qn, pos);
+        v = w1s * P.c0 * sy.Mb[e] + w1 * P.c2 * sy.Db[e] + sy.Kb[e] + kt_entry(sy, qn, vel ? qd : qn, pos);
+        if (vel) v += w1 * P.c2 * Ct[pos];
       }
       Lf[pos] = v;
     }
@@ -836,6 +862,25 @@ fse_status launch_idft(fse_ctx *ctx, int B, const double *Z0) {
   return FSE_OK;
 }
 
+// Global scratch of the state and omega_1-sensitivity kernels when their per-trajectory
+// working set exceeds LDS; the two kernels have different strides, so the buffer grows to the
+// larger request (the stream is drained before a reallocation).
+fse_status ensure_state_scr(fse_ctx *ctx, size_t elems) {
+  if (ctx->state_scr_elems >= elems) return FSE_OK;
+  if (ctx->state_scr) {
+    FSE_HIP(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->state_scr);
+  }
+  ctx->state_scr = nullptr;
+  ctx->state_scr_elems = 0;
+  if (hipMalloc((void **)&ctx->state_scr, sizeof(double) * elems) != hipSuccess) {
+    ctx->err = "hipMalloc failed for the state scratch";
+    return FSE_E_NOMEM;
+  }
+  ctx->state_scr_elems = elems;
+  return FSE_OK;
+}
+
 fse_status launch_state(fse_ctx *ctx, int B) {
   const TrajParams P = params(ctx, B);
   const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 9 * (size_t)ctx->n + 80;
@@ -849,12 +894,7 @@ fse_status launch_state(fse_ctx *ctx, int B) {
                        ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, uh, ctx->u0, ctx->zTw,
                        ctx->Wmax, nullptr, ctx->status_d);
   } else {
-    if (!ctx->state_scr) {
-      if (hipMalloc((void **)&ctx->state_scr, sizeof(double) * elems * ctx->Wmax) != hipSuccess) {
-        ctx->err = "hipMalloc failed for the state scratch";
-        return FSE_E_NOMEM;
-      }
-    }
+    FSE_TRY(ensure_state_scr(ctx, elems * ctx->Wmax));
     hipLaunchKernelGGL(k_state<false>, dim3(P.W), dim3(threads), 0, ctx->stream, P, sysdev(ctx),
                        ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, uh, ctx->u0, ctx->zTw,
                        ctx->Wmax, ctx->state_scr, ctx->status_d);
@@ -1025,14 +1065,11 @@ __global__ void k_set_pcol(double *__restrict__ A, size_t ldA, int N, int nu, co
 }
 
 fse_status launch_wsens(fse_ctx *ctx, int B, double *dzT) {
-  if (ctx->has_vel) {
-    ctx->err = "the omega_1 sensitivity is built for forces of q only";
-    return FSE_E_UNSUPPORTED;
-  }
   const fse_status fs = ctx->wsens_generic ? FSE_E_UNSUPPORTED : launch_wsens_fused(ctx, B, dzT);
   if (fs != FSE_E_UNSUPPORTED) return fs;
   const TrajParams P = params(ctx, B);
-  const size_t elems = (size_t)ctx->n * (ctx->bw + 1) + 8 * (size_t)ctx->n + 80;
+  const size_t nb = (size_t)ctx->n * (ctx->bw + 1);
+  const size_t elems = nb + 8 * (size_t)ctx->n + 80 + (ctx->has_vel ? nb + ctx->n : 0);
   const size_t bytes = elems * sizeof(double);
   const int threads = ctx->bw > 24 ? 256 : 64;
   if (bytes <= kLdsLimit) {
@@ -1040,12 +1077,7 @@ fse_status launch_wsens(fse_ctx *ctx, int B, double *dzT) {
                        ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->Wmax, dzT, nullptr,
                        ctx->status_d);
   } else {
-    if (!ctx->state_scr) {
-      if (hipMalloc((void **)&ctx->state_scr, sizeof(double) * elems * ctx->Wmax) != hipSuccess) {
-        ctx->err = "hipMalloc failed for the state scratch";
-        return FSE_E_NOMEM;
-      }
-    }
+    FSE_TRY(ensure_state_scr(ctx, elems * ctx->Wmax));
     hipLaunchKernelGGL(k_wsens<false>, dim3(P.W), dim3(threads), 0, ctx->stream, P, sysdev(ctx),
                        ctx->omega_d, ctx->sidx_d, ctx->Sdim_d, ctx->qhist, ctx->u0, ctx->Wmax, dzT,
                        ctx->state_scr, ctx->status_d);

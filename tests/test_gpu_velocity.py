@@ -11,6 +11,7 @@ import pytest
 from _velocity_systems import mixed_system, van_der_pol
 from fse_inputs import Torus
 from fse_inputs.systems import place_harmonics
+from oracle import continuation as ocont
 from oracle import lyapunov as oly
 from oracle import shooting as osh
 
@@ -78,15 +79,42 @@ def test_forced_van_der_pol_newton_and_lyapunov():
     assert np.max(np.abs(sg - so)) < 1e-6
 
 
-def test_refusals():
+@pytest.mark.parametrize("d,e", [(2, 2), (3, 2)])
+def test_residual_dp(d, e):
+    """dR/dp along the frequency conditions (the omega_1 sensitivity, where the velocity-dependent
+    forces add C_t to the damping and -(D + C_t) u to the forcing of the sensitivity)."""
+    s = mixed_system(e=e)
+    om = np.array([0.9, 0.9 * 1.618, 0.9 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=e, K=[np.arange(1, 4)] * (d - 1), S=[8] * (d - 1), S1=64)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(d).normal(size=(2 * s.n, tb.U))
+    ref = osh.evaluate(s, tr, om, Z0, omega_sens=True, tables=tb)
+    dref = ocont.residual_dp(ref, om, e)
+    ctx = fse().fse_init_torus(s, tr)
+    R, dRdp = fse().fse_residual_dp(ctx, om[None], Z0[None])
+    assert rel(R[0].cpu().numpy(), ref["R"]) < RTOL
+    err = rel(dRdp[0].cpu().numpy().ravel(), dref)
+    log(f"velocity forces dR/dp d={d} e={e}: rel err {err:.2e}")
+    assert err < RTOL
+
+
+def test_van_der_pol_residual_dp():
+    """d = 2, e = 1: dR/dp carries the rotation term of the unknown omega_2 as well."""
+    s = van_der_pol(mu=0.2)
+    tr = Torus(d=2, e=1, K=[np.arange(1, 8)], S=[16], S1=128)
+    tb = osh.TorusTables(tr)
+    om = np.array([2.3, 0.99])
+    Z0 = 0.3 * np.random.default_rng(5).normal(size=(2, tb.U))
+    ref = osh.evaluate(s, tr, om, Z0, omega_sens=True, tables=tb)
+    dref = ocont.residual_dp(ref, om, 1)
+    ctx = fse().fse_init_torus(s, tr)
+    R, dRdp = fse().fse_residual_dp(ctx, om[None], Z0[None])
+    assert rel(dRdp[0].cpu().numpy().ravel(), dref) < RTOL
+
+
+def test_non_symmetric_velocity_tangent_is_refused():
     s = mixed_system()
     tr = Torus(d=2, e=2, K=[np.arange(1, 4)], S=[8], S1=64)
-    tb = osh.TorusTables(tr)
-    ctx = fse().fse_init_torus(s, tr)
-    om = np.array([0.9, 0.9 * 1.618])
-    Z0 = np.zeros((2 * s.n, tb.U))
-    with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
-        fse().fse_residual_dp(ctx, om[None], Z0[None])
     bad = mixed_system()
     bad.t3_idx = np.vstack([bad.t3_idx, [[0, 1, 1, bad.n + 2]]]).astype(np.int32)
     bad.t3_val = np.concatenate([bad.t3_val, [0.5]])
