@@ -232,8 +232,7 @@ fse_status fse_residual_dp(fse_ctx *ctx, int32_t B, const double *omega, const d
  * [2n][U].  Outputs: Z_out device [P][2n][U]; HOST omega_out [P][d], steps [P] (step taken,
  * 0 for point 0), iters [P] (corrections), rnorm [P] (final ||R||_2).  On failure at point
  * j the status is returned with iters[j] = -1; earlier points are valid.  One dense
- * (2nU + d - e + 1)^2 FP64 workspace is held by the context.  d = e only (FSE_E_UNSUPPORTED
- * otherwise). */
+ * (2nU + d - e + 1)^2 FP64 workspace is held by the context. */
 fse_status fse_arclength(fse_ctx *ctx, int32_t P, const double *omega0, const double *Z_init, double ds,
                          double tol, int32_t maxit, double *Z_out, double *omega_out, double *steps,
                          int32_t *iters, double *rnorm);

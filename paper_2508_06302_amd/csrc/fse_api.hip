@@ -1069,12 +1069,6 @@ fse_status fse_arclength(fse_ctx *ctx, int32_t P, const double *omega0, const do
     ctx->err = "arclength step must be finite and non-zero, tol positive";
     return FSE_E_INVAL;
   }
-  if (ctx->d != ctx->e) {
-    // the bordered rows are assembled for d > e, but no quasi-periodic test system with an
-    // unknown frequency exists here to hold the path to the oracle
-    ctx->err = "arclength continuation is verified for d = e only";
-    return FSE_E_UNSUPPORTED;
-  }
   const int N = 2 * ctx->n * ctx->U, nu = ctx->d - ctx->e, d = ctx->d, e = ctx->e;
   const size_t Na = (size_t)N + nu + 1;
   FSE_TRY(ensure_matrix(ctx, Na));

@@ -191,13 +191,11 @@ def test_arclength_error_paths():
 
 
 def test_unsupported_and_invalid_calls():
-    """d > e is rejected by the arclength, Newton-Krylov and hyper-time calls (their bordered
-    rows are not held to the oracle); batch sizes beyond the context are rejected."""
+    """d > e is rejected by the Newton-Krylov and hyper-time calls (their bordered rows are not
+    held to the oracle); batch sizes beyond the context are rejected."""
     s, tr, tb, om, Z0 = _case(2, 1)
     ctx = fse().fse_init_torus(s, tr)
     m = fse()
-    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
-        m.fse_arclength(ctx, om, Z0, 0.1, 3)
     import torch
     Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
     with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):

@@ -161,3 +161,22 @@ def test_invalid_contacts_and_mixed_precision():
     cm = fse().fse_init_torus(s, tr, precision=fse().FSE_PREC_MIXED_FP32)
     with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
         fse().fse_integrate_batch(cm, om[None], Z0[None], want_phi=True)
+
+
+def test_impact_oscillator_arclength_matches_oracle():
+    """Pseudo-arclength continuation in omega_1 of the impact oscillator's orbit (d = 1): eight
+    points on the GPU equal the oracle's path."""
+    s = impact_oscillator()
+    tr = Torus(d=1, e=1, K=[], S=[], S1=256)
+    tb = osh.TorusTables(tr)
+    om0 = np.array([1.3])
+    Z0, _, _ = osh.solve(s, tr, om0, np.zeros((2, 1)), tol_R=1e-12, tables=tb)
+    path = ocont.arclength(s, tr, om0, Z0, 0.3, 8, tables=tb, tol_R=1e-11)
+    ctx = fse().fse_init_torus(s, tr)
+    Z, om, steps, it, rn = fse().fse_arclength(ctx, om0, Z0, 0.3, 8, tol=1e-11, maxit=8)
+    log(f"impact oscillator branch: omega {np.round(om[:, 0], 5).tolist()}, corrections {it.tolist()}")
+    assert np.all(rn < 1e-11)
+    for j, p in enumerate(path):
+        assert abs(om[j][0] - p["omega"][0]) < 1e-9 * p["omega"][0], (j, om[j], p["omega"])
+        assert rel(Z[j].cpu().numpy(), p["Z"]) < 1e-8
+        assert steps[j] == p["s"]

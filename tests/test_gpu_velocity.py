@@ -120,3 +120,26 @@ def test_non_symmetric_velocity_tangent_is_refused():
     bad.t3_val = np.concatenate([bad.t3_val, [0.5]])
     with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
         fse().fse_init_torus(bad, tr)
+
+
+def test_van_der_pol_arclength_matches_oracle():
+    """Pseudo-arclength continuation in omega_1 of the forced van der Pol torus (omega_2 unknown
+    along the branch): five points on the GPU equal the oracle's path (omega within 1e-9
+    relative, Z(0) within 1e-8, the same steps)."""
+    mu, w1 = 0.2, 2.3
+    s = van_der_pol(mu=mu)
+    tr = Torus(d=2, e=1, K=[np.arange(1, 8)], S=[16], S1=128)
+    tb = osh.TorusTables(tr)
+    A = 0.5 / (1 - w1 ** 2)
+    Zi = place_harmonics(tb.table, [((0,), np.array([A, 0.0], complex)), ((1,), np.array([2.0, 2j / w1]))],
+                         1, tb.U)
+    Z0, om0, _ = osh.solve(s, tr, np.array([w1, 1.0]), Zi, tol_R=1e-12, max_newton=25, tables=tb)
+    path = ocont.arclength(s, tr, om0, Z0, 0.05, 5, tables=tb, tol_R=1e-11)
+    ctx = fse().fse_init_torus(s, tr)
+    Z, om, steps, it, rn = fse().fse_arclength(ctx, om0, Z0, 0.05, 5, tol=1e-11, maxit=8)
+    log(f"van der Pol branch: omega {np.round(om, 6).tolist()}, corrections {it.tolist()}")
+    assert np.all(rn < 1e-11)
+    for j, p in enumerate(path):
+        assert np.allclose(om[j], p["omega"], rtol=1e-9), (j, om[j], p["omega"])
+        assert rel(Z[j].cpu().numpy(), p["Z"]) < 1e-8
+        assert steps[j] == p["s"]
