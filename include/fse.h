@@ -254,16 +254,19 @@ fse_status fse_shooting_residual_matfree(fse_ctx *ctx, const double *omega, cons
  * moved Z0 since). */
 fse_status fse_jacobian_apply(fse_ctx *ctx, const double *v, double *Jv);
 
-/* One Newton update Z0 <- Z0 + dZ (Z0 device [2n][U], omega HOST [d], d = e only:
- * FSE_E_UNSUPPORTED otherwise), with J dZ = -R solved by restarted GMRES(restart) to
- * ||J dZ + R|| <= rtol ||R|| or maxit iterations.  precond != 0 uses right preconditioning by
+/* One Newton update Z0 <- Z0 + dZ (Z0 device [2n][U], omega HOST [d]), with J dZ = -R solved
+ * by restarted GMRES(restart) to ||J dZ + R|| <= rtol ||R|| or maxit iterations.  For d > e
+ * the unknowns are [Z(0); omega_u] and the system is bordered as in fse_newton_step: the
+ * columns dR/domega_u and the phase rows of Eq. (18) join the matrix-free J, GMRES runs on
+ * 2nU + d - e unknowns, and omega[e..d-1] is updated in place (the preconditioner acts on the
+ * Z(0) block only).  precond != 0 uses right preconditioning by
  * the harmonic-block matrix P = Phi_bar (x) R(rho) - I (Phi_bar the mean of the trajectory
  * sensitivities; P = J for a linear system).  Each of its blocks (one 2n x 2n, one 4n x 4n per
  * harmonic pair) is factored once per step.  HOST outputs (any may be NULL): res_norm =
  * ||R||_2 before the update, gmres_iters, gmres_relres = ||J dZ + R|| / ||R|| reached.
- * Device workspace: (restart + 7) vectors of 2nU doubles and the preconditioner blocks
- * (2n)^2 (1 + 4 L) doubles, held by the context. */
-fse_status fse_newton_krylov_step(fse_ctx *ctx, const double *omega, double *Z0, double rtol, int32_t restart,
+ * Device workspace: (restart + 8) vectors of 2nU + d - e doubles, 2 (d - e) border vectors of
+ * 2nU doubles and the preconditioner blocks (2n)^2 (1 + 4 L) doubles, held by the context. */
+fse_status fse_newton_krylov_step(fse_ctx *ctx, double *omega, double *Z0, double rtol, int32_t restart,
                                   int32_t maxit, int32_t precond, double *res_norm, int32_t *gmres_iters,
                                   double *gmres_relres);
 

@@ -388,16 +388,19 @@ def fse_jacobian_apply(ctx: Context, v):
 
 def fse_newton_krylov_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxit=300, precond=True):
     """Z0 (torch cuda [2n][U], updated in place) <- Z0 + dZ with J dZ = -R by GMRES ->
-    (||R|| before, GMRES iterations, relative linear residual)."""
+    (||R|| before, GMRES iterations, relative linear residual).  For d > e the unknown
+    frequencies omega[e:] are updated in place (numpy float64 array), as in fse_newton_step."""
     _torch()
     ctx.bind_stream()
-    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    om = _omega_inout(omega, ctx.d)
     rn = C.c_double()
     its = C.c_int32()
     rel = C.c_double()
-    ctx.check(ctx.lib.fse_newton_krylov_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()), float(rtol),
-                                             int(restart), int(maxit), int(bool(precond)), C.byref(rn),
-                                             C.byref(its), C.byref(rel)))
+    st = ctx.lib.fse_newton_krylov_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()), float(rtol),
+                                        int(restart), int(maxit), int(bool(precond)), C.byref(rn),
+                                        C.byref(its), C.byref(rel))
+    ctx.check(st)
+    _omega_back(omega, om)
     return rn.value, its.value, rel.value
 
 

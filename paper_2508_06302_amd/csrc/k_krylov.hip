@@ -138,11 +138,50 @@ __global__ void k_scale(int N, double a, const double *__restrict__ x, double *_
   if (i < N) y[i] = a * x[i];
 }
 
+// out[r] += sum_u Bc[u][r] w[u] (r < N)
+__global__ void k_add_cols(const double *__restrict__ Bc, int N, int nu, const double *__restrict__ w,
+                           double *__restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  double acc = out[r];
+  for (int u = 0; u < nu; ++u) acc += Bc[(size_t)u * N + r] * w[u];
+  out[r] = acc;
+}
+
+// Border of the Newton matrix for the unknown base frequencies omega_{e+1..d} at (Z0, R):
+// Bc[u] = dR/domega_{e+u} (rotation term of Eqs. 23-24, d alpha_l / d omega = 2 pi k / omega_1,
+// applied to R + Z0 = R(rho) Z(2 pi)), Pr[u] = (I (x) nabla_{phi_{e+u}}) Z0 (the phase row of
+// Eq. 18 with Z* = dZ).
+__global__ void k_kr_border(double *__restrict__ Bc, double *__restrict__ Pr, int N, int nu,
+                            const double *__restrict__ R, const double *__restrict__ Z0,
+                            const int32_t *__restrict__ ktable, int dm1, int e, double two_pi_over_w1, int U) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nu) return;
+  const int u = idx / N, r = idx - u * N;
+  const int a = r % U, base = r - a;
+  double dr = 0.0, pr = 0.0;
+  if (a > 0) {
+    const double k = (double)ktable[(size_t)((a - 1) / 2) * dm1 + e + u - 1];
+    if (a & 1) {  // cos coefficient of the pair
+      dr = -two_pi_over_w1 * k * (R[base + a + 1] + Z0[base + a + 1]);
+      pr = k * Z0[base + a + 1];
+    } else {      // sin coefficient
+      dr = two_pi_over_w1 * k * (R[base + a - 1] + Z0[base + a - 1]);
+      pr = -k * Z0[base + a - 1];
+    }
+  }
+  Bc[(size_t)u * N + r] = dr;
+  Pr[(size_t)u * N + r] = pr;
+}
+
+// Unknowns [Z(0); omega_u] (Nb = N + nu entries; nu = d - e unknown base frequencies): the
+// Newton matrix is [[J, dR/domega_u], [phase rows, 0]] (Eqs. 17-18, 23-24).  Bc holds the
+// columns dR/domega_u and Pr the phase rows, [nu][N] each.
 struct Krylov {
   fse_ctx *ctx;
-  int N, n2, U, L;
+  int N, Nb, nu, n2, U, L;
   size_t ldv;
-  double *V, *w, *z, *u, *r, *x, *h, *bv, *xs, *ys, *Pbar, *blocks;
+  double *V, *w, *z, *u, *r, *x, *b, *h, *bv, *xs, *ys, *Pbar, *Bc, *Pr, *blocks;
   int32_t *piv;
 };
 
@@ -150,7 +189,9 @@ fse_status kr_alloc(fse_ctx *ctx, int restart) {
   const size_t N = (size_t)2 * ctx->n * ctx->U, n2 = 2 * (size_t)ctx->n;
   const size_t L = (size_t)ctx->L;
   const size_t blk = n2 * n2 + L * 4 * n2 * n2;
-  const size_t need = (size_t)(restart + 1) * N + 5 * N + (restart + 2) + N + 2 * n2 * ctx->Wmax + n2 * n2 + blk;
+  const size_t Nb = N + (size_t)(ctx->d - ctx->e);
+  const size_t need = (size_t)(restart + 1) * Nb + 6 * Nb + (restart + 2) + Nb + 2 * n2 * ctx->Wmax + n2 * n2 +
+                      2 * (Nb - N) * N + blk;
   if (ctx->kr_elems < need) {
     if (ctx->kr) (void)hipFree(ctx->kr);
     if (ctx->kr_piv) (void)hipFree(ctx->kr_piv);
@@ -171,39 +212,48 @@ Krylov kr_view(fse_ctx *ctx, int restart) {
   Krylov k;
   k.ctx = ctx;
   k.N = 2 * ctx->n * ctx->U;
+  k.nu = ctx->d - ctx->e;
+  k.Nb = k.N + k.nu;
   k.n2 = 2 * ctx->n;
   k.U = ctx->U;
   k.L = ctx->L;
-  k.ldv = (size_t)k.N;
+  k.ldv = (size_t)k.Nb;
   double *p = ctx->kr;
   k.V = p;
-  p += (size_t)(restart + 1) * k.N;
+  p += (size_t)(restart + 1) * k.Nb;
   k.w = p;
-  p += k.N;
+  p += k.Nb;
   k.z = p;
-  p += k.N;
+  p += k.Nb;
   k.u = p;
-  p += k.N;
+  p += k.Nb;
   k.r = p;
-  p += k.N;
+  p += k.Nb;
   k.x = p;
-  p += k.N;
+  p += k.Nb;
+  k.b = p;
+  p += k.Nb;
   k.h = p;
   p += restart + 2;
   k.bv = p;
-  p += k.N;
+  p += k.Nb;
   k.xs = p;
   p += (size_t)k.n2 * ctx->Wmax;
   k.ys = p;
   p += (size_t)k.n2 * ctx->Wmax;
   k.Pbar = p;
   p += (size_t)k.n2 * k.n2;
+  k.Bc = p;
+  p += (size_t)k.nu * k.N;
+  k.Pr = p;
+  p += (size_t)k.nu * k.N;
   k.blocks = p;
   k.piv = ctx->kr_piv;
   return k;
 }
 
-// out = J v with the sensitivities of the last evaluation (ctx->PhiQU, rotation in ctx->rot_d)
+// out = J v with the sensitivities of the last evaluation (ctx->PhiQU, rotation in ctx->rot_d);
+// with unknown frequencies, out = [J v_Z + dR/domega_u v_w; phase rows . v_Z]
 fse_status kr_matvec(const Krylov &k, const double *v, double *out) {
   fse_ctx *ctx = k.ctx;
   const int St = ctx->St, W = ctx->Wmax;
@@ -212,7 +262,14 @@ fse_status kr_matvec(const Krylov &k, const double *v, double *out) {
   hipLaunchKernelGGL(k_phi_apply, dim3(St, (k.n2 + kPhiRows - 1) / kPhiRows), dim3(256), sizeof(double) * k.n2,
                      ctx->stream, ctx->PhiQU, k.xs, k.n2, W, k.ys);
   FSE_HIP(hipGetLastError());
-  return launch_dft(ctx, 1, k.ys, v, out);
+  FSE_TRY(launch_dft(ctx, 1, k.ys, v, out));
+  if (k.nu > 0) {
+    hipLaunchKernelGGL(k_add_cols, dim3((k.N + 255) / 256), dim3(256), 0, ctx->stream, k.Bc, k.N, k.nu, v + k.N,
+                       out);
+    hipLaunchKernelGGL(k_dots, dim3(k.nu), dim3(256), 0, ctx->stream, k.Pr, (size_t)k.N, v, k.N, out + k.N);
+    FSE_HIP(hipGetLastError());
+  }
+  return FSE_OK;
 }
 
 size_t block_off(const Krylov &k, int l) {
@@ -248,16 +305,19 @@ fse_status kr_precond_apply(const Krylov &k, const double *v, double *out) {
   }
   hipLaunchKernelGGL(k_pc_gather, dim3(nbk), dim3(nth), 0, ctx->stream, out, k.n2, k.U, k.bv, 1);
   FSE_HIP(hipGetLastError());
+  // the frequency unknowns are not preconditioned
+  if (k.nu > 0 && out != v)
+    FSE_HIP(hipMemcpyAsync(out + k.N, v + k.N, sizeof(double) * k.nu, hipMemcpyDeviceToDevice, ctx->stream));
   return FSE_OK;
 }
 
-fse_status kr_norm(const Krylov &k, const double *v, double *out) { return launch_norm(k.ctx, v, (size_t)k.N, out); }
+fse_status kr_norm(const Krylov &k, const double *v, double *out) { return launch_norm(k.ctx, v, (size_t)k.Nb, out); }
 
 // Right-preconditioned restarted GMRES for J x = b (b device [N]); x returned in k.x.
 fse_status kr_gmres(const Krylov &k, const double *b, bool precond, double rtol, int restart, int maxit, int *its_out,
                     double *rel_out) {
   fse_ctx *ctx = k.ctx;
-  const int N = k.N, nth = 256, nbk = (N + nth - 1) / nth;
+  const int N = k.Nb, nth = 256, nbk = (N + nth - 1) / nth;  // every vector has the Nb unknowns
   double nb = 0.0;
   FSE_TRY(kr_norm(k, b, &nb));
   FSE_HIP(hipMemsetAsync(k.x, 0, sizeof(double) * N, ctx->stream));
@@ -372,30 +432,33 @@ fse_status fse_jacobian_apply(fse_ctx *ctx, const double *v, double *Jv) {
     return FSE_E_INVAL;
   }
   FSE_TRY(kr_alloc(ctx, 1));
-  const Krylov k = kr_view(ctx, 1);
+  Krylov k = kr_view(ctx, 1);
+  k.nu = 0;  // J alone: v and Jv hold 2nU entries, without the frequency border
   FSE_TRY(kr_matvec(k, v, Jv));
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
 
-fse_status fse_newton_krylov_step(fse_ctx *ctx, const double *omega, double *Z0, double rtol, int32_t restart,
+fse_status fse_newton_krylov_step(fse_ctx *ctx, double *omega, double *Z0, double rtol, int32_t restart,
                                   int32_t maxit, int32_t precond, double *res_norm, int32_t *gmres_iters,
                                   double *gmres_relres) {
   if (!ctx || !omega || !Z0 || restart < 1 || restart > 500 || maxit < 1 || !(rtol > 0.0)) return FSE_E_INVAL;
-  if (ctx->d != ctx->e) {
-    ctx->err = "the Newton-Krylov step needs every base frequency known (d = e)";
-    return FSE_E_UNSUPPORTED;
-  }
   FSE_TRY(kr_alloc(ctx, restart));
   const Krylov k = kr_view(ctx, restart);
   double rn = 0.0;
   FSE_TRY(kr_evaluate(ctx, omega, Z0, k.r, &rn));
   if (res_norm) *res_norm = rn;
-  // b = -R, held outside the GMRES work vectors
+  // b = [-R; 0], held outside the GMRES work vectors
   const int N = k.N, nbk = (N + 255) / 256;
-  double *b = ctx->Zwork;
+  double *b = k.b;
   hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, ctx->stream, N, -1.0, k.r, b);
   FSE_HIP(hipGetLastError());
+  if (k.nu > 0) {
+    FSE_HIP(hipMemsetAsync(b + N, 0, sizeof(double) * k.nu, ctx->stream));
+    hipLaunchKernelGGL(k_kr_border, dim3((N * k.nu + 255) / 256), dim3(256), 0, ctx->stream, k.Bc, k.Pr, N, k.nu,
+                       k.r, Z0, ctx->ktable_d, ctx->d - 1, ctx->e, 2.0 * M_PI / omega[0], ctx->U);
+    FSE_HIP(hipGetLastError());
+  }
   if (precond) FSE_TRY(kr_precond_build(k));
   int its = 0;
   double rel = 0.0;
@@ -403,6 +466,12 @@ fse_status fse_newton_krylov_step(fse_ctx *ctx, const double *omega, double *Z0,
   if (gmres_iters) *gmres_iters = its;
   if (gmres_relres) *gmres_relres = rel;
   FSE_TRY(launch_axpby(ctx, N, 1.0, Z0, 1.0, k.x, Z0));
+  if (k.nu > 0) {
+    std::vector<double> dw(k.nu);
+    FSE_HIP(hipMemcpyAsync(dw.data(), k.x + N, sizeof(double) * k.nu, hipMemcpyDeviceToHost, ctx->stream));
+    FSE_HIP(hipStreamSynchronize(ctx->stream));
+    for (int u = 0; u < k.nu; ++u) omega[ctx->e + u] += dw[u];
+  }
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   ctx->mf_ready = false;  // Z0 moved: the stored sensitivities belong to the old point
   return FSE_OK;

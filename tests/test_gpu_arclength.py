@@ -191,15 +191,11 @@ def test_arclength_error_paths():
 
 
 def test_unsupported_and_invalid_calls():
-    """d > e is rejected by the Newton-Krylov and hyper-time calls (their bordered rows are not
-    held to the oracle); batch sizes beyond the context are rejected."""
+    """d > e is rejected by the hyper-time calls (the paper gives that form no phase rows);
+    batch sizes beyond the context are rejected."""
     s, tr, tb, om, Z0 = _case(2, 1)
     ctx = fse().fse_init_torus(s, tr)
     m = fse()
-    import torch
-    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
-    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
-        m.fse_newton_krylov_step(ctx, om, Zg)
     zb = np.zeros((2 * s.n, tb.Stilde))
     with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
         m.fse_hypertime_residual_jacobian(ctx, om[None], zb[None])

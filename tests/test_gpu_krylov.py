@@ -159,3 +159,54 @@ def test_c4_newton_krylov_converges_sampled_by_the_oracle():
     ref = osh.evaluate(sj, wl.torus, wl.omega, Zh, tables=tb, samples=samples)
     for s_ in samples:
         assert rel(zT[0][:, s_].cpu().numpy(), ref["zbarT"][:, s_]) < RTOL, s_
+
+
+@pytest.mark.parametrize("d,e", [(2, 1), (3, 2)])
+def test_bordered_krylov_step_equals_the_dense_bordered_step(d, e):
+    """Unknown base frequencies (d > e): the GMRES step on [Z(0); omega_u] with the columns
+    dR/domega_u and the phase rows of Eq. (18) equals the oracle's dense bordered Newton step."""
+    import torch
+    s = tiny_system(n=3, seed=8, cubic=1.0, quad=0.3, e=e)
+    om = np.array([1.05, 1.05 * GOLDEN, 1.05 * 2 ** 0.5][:d])
+    tr = Torus(d=d, e=e, K=[np.arange(1, 4)] * (d - 1), S=[8] * (d - 1), S1=48)
+    tb = osh.TorusTables(tr)
+    Z0 = 0.2 * np.random.default_rng(2).normal(size=(6, tb.U))
+    Z1, om1, r0 = osh.newton_step(s, tr, om, Z0, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    Zg = torch.tensor(Z0, dtype=torch.float64, device="cuda")
+    omg = om.copy()
+    rn, its, relres = fse().fse_newton_krylov_step(ctx, omg, Zg, rtol=1e-13, restart=80, maxit=400)
+    log(f"bordered Newton-Krylov d={d} e={e}: {its} GMRES iterations, relative residual {relres:.1e}")
+    assert abs(rn - r0) < 1e-12 * r0
+    assert relres < 1e-12
+    assert rel(Zg.cpu().numpy(), Z1) < 1e-9
+    assert np.allclose(omg, om1, rtol=0, atol=1e-10)
+
+
+def test_van_der_pol_newton_krylov_reaches_the_oracle_torus():
+    """Forced van der Pol oscillator (omega_2 unknown): Newton-Krylov steps from the averaging
+    start reach the oracle's torus and its free frequency."""
+    import torch
+    from _velocity_systems import van_der_pol
+    from fse_inputs.systems import place_harmonics
+    s = van_der_pol(mu=0.2)
+    w1 = 2.3
+    tr = Torus(d=2, e=1, K=[np.arange(1, 8)], S=[16], S1=128)
+    tb = osh.TorusTables(tr)
+    A = 0.5 / (1 - w1 ** 2)
+    Zi = place_harmonics(tb.table, [((0,), np.array([A, 0.0], complex)), ((1,), np.array([2.0, 2j / w1]))],
+                         1, tb.U)
+    Zo, omo, _ = osh.solve(s, tr, np.array([w1, 1.0]), Zi, tol_R=1e-11, max_newton=25, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    Zg = torch.tensor(Zi, dtype=torch.float64, device="cuda")
+    omg = np.array([w1, 1.0])
+    hist = []
+    for _ in range(12):
+        rn, its, _ = fse().fse_newton_krylov_step(ctx, omg, Zg, rtol=1e-12, restart=60, maxit=300)
+        hist.append(rn)
+        if rn < 1e-11:
+            break
+    log(f"van der Pol Newton-Krylov: ||R|| {['%.1e' % h for h in hist]}, omega_2 {omg[1]:.12f}")
+    assert hist[-1] < 1e-9
+    assert abs(omg[1] - omo[1]) < 1e-9
+    assert rel(Zg.cpu().numpy(), Zo) < 1e-8
