@@ -17,7 +17,9 @@ Pins (tests/test_oracle_multiple.py): M = 1 equals the single-shooting residual 
 Jacobian; on a linear system one Newton step lands on the closed-form discrete torus, whose
 section m is the section-0 torus with the harmonic of frequency 1 turned by 2 pi m / M;
 central finite differences of R; on a nonlinear system the converged section 0 agrees with
-the single-shooting torus to the Fourier truncation.
+the single-shooting torus to the Fourier truncation.  With unknown frequencies (d > e):
+M = 1 gives the single-shooting bordered step, dR/d omega_u matches central differences, and
+the forced van der Pol torus from two segments has the single-shooting free frequency.
 """
 from __future__ import annotations
 
@@ -75,22 +77,67 @@ def jacobian(res):
     return J
 
 
+def residual_domega_u(res, omega, e, Zs):
+    """dR/d omega_u for the unknown base frequencies u = e+1..d, as [M 2n U~][d-e].
+
+    The trajectories do not depend on an unknown frequency (only forcing frequencies enter
+    Eq. E1); it acts through the rotation R(rho / M) alone: d R_m / d omega_u =
+    (I (x) dR(rho/M)/d omega_u) Gamma^-1 zbar^(m)(2 pi / M), where R_m + Z^(m+1) is
+    R(rho/M) Gamma^-1 zbar^(m)(2 pi / M).  With omega' = (omega_1, omega_2 / M, ...),
+    R(rho/M) = R(rho') and dR(rho/M)/d omega_u = (1/M) dR(rho')/d omega'_u (Eq. 24)."""
+    tb, M = res["tables"], res["M"]
+    omega = np.asarray(omega, dtype=float)
+    d = len(omega)
+    om_s = np.concatenate([omega[:1], omega[1:] / M])
+    Zs = np.asarray(Zs, dtype=float).reshape(res["R"].shape)
+    Zend = np.stack([np.linalg.solve(res["Rrot"], (res["R"][m] + Zs[(m + 1) % M]).T).T for m in range(M)])
+    cols = []
+    for i in range(e + 1, d + 1):
+        dR = tor.rotation_domega(tb.table, om_s, i) / M
+        cols.append(np.concatenate([(Zend[m] @ dR.T).ravel() for m in range(M)]))
+    return np.array(cols).T
+
+
 def newton_step(sysm, torus, omega, Zs, M, tables=None):
-    """Zs -> Zs - J^-1 R; returns (Zs_new, ||R||_2 before)."""
+    """Zs -> Zs - J^-1 R; returns (Zs_new, ||R||_2 before).  For d > e the unknowns are
+    [Z^(0..M-1); omega_u], bordered as in single shooting (Eqs. 17-18) by the columns
+    dR/d omega_u and the phase rows of Eq. (18) on section 0; returns (Zs_new, omega_new,
+    ||R||_2 before) then."""
     res = evaluate(sysm, torus, omega, Zs, M, sens=True, tables=tables)
-    dz = np.linalg.solve(jacobian(res), -res["R"].ravel())
-    return np.asarray(Zs, dtype=float) + dz.reshape(res["R"].shape), float(np.linalg.norm(res["R"]))
+    d, e = torus.d, torus.e
+    if d == e:
+        dz = np.linalg.solve(jacobian(res), -res["R"].ravel())
+        return np.asarray(Zs, dtype=float) + dz.reshape(res["R"].shape), float(np.linalg.norm(res["R"]))
+    J = jacobian(res)
+    nu = d - e
+    B = residual_domega_u(res, omega, e, Zs)
+    P = np.zeros((nu, J.shape[0]))
+    P[:, :res["R"][0].size] = shooting.phase_rows(res["tables"], np.asarray(Zs, dtype=float)[0], e, d)
+    big = np.block([[J, B], [P, np.zeros((nu, nu))]])
+    x = np.linalg.solve(big, np.concatenate([-res["R"].ravel(), np.zeros(nu)]))
+    om = np.array(omega, dtype=float)
+    om[e:] += x[-nu:]
+    return (np.asarray(Zs, dtype=float) + x[:-nu].reshape(res["R"].shape), om,
+            float(np.linalg.norm(res["R"])))
 
 
 def solve(sysm, torus, omega, Zs, M, tol_R=1e-8, max_newton=20, tables=None):
-    """Newton iterations until ||R||_2 < tol_R; returns (Zs, history of ||R||_2)."""
+    """Newton iterations until ||R||_2 < tol_R; returns (Zs, history of ||R||_2), or
+    (Zs, omega, history) when d > e."""
     Z = np.array(Zs, dtype=float)
+    om = np.array(omega, dtype=float)
+    bordered = torus.d > torus.e
     hist = []
     for _ in range(max_newton):
-        Zn, r = newton_step(sysm, torus, omega, Z, M, tables=tables)
+        if bordered:
+            Zn, omn, r = newton_step(sysm, torus, om, Z, M, tables=tables)
+        else:
+            Zn, r = newton_step(sysm, torus, om, Z, M, tables=tables)
         hist.append(r)
         if r < tol_R:
-            return Z, hist
+            return (Z, om, hist) if bordered else (Z, hist)
         Z = Zn
-    hist.append(float(np.linalg.norm(evaluate(sysm, torus, omega, Z, M, tables=tables)["R"])))
-    return Z, hist
+        if bordered:
+            om = omn
+    hist.append(float(np.linalg.norm(evaluate(sysm, torus, om, Z, M, tables=tables)["R"])))
+    return (Z, om, hist) if bordered else (Z, hist)
