@@ -295,8 +295,8 @@ fse_status fse_hypertime_newton_step(fse_ctx *ctx, const double *omega, double *
  * Eq. 13 over the phases of the other frequencies at that moment).  Segment m starts on
  * section m with the forcing of frequency 1 at phase 2 pi m / M; with Eq. (16) per segment
  *     R_m = (I (x) R(rho / M)) Gamma^-1 zbar^(m)(2 pi / M) - Z^((m + 1) mod M).
- * M = 1 is FSE-Shooting.  d = e only (FSE_E_UNSUPPORTED otherwise); 1 <= M <= max_batch and
- * S1 a multiple of M (FSE_E_INVAL otherwise).  The segments run as one batch of M points. */
+ * M = 1 is FSE-Shooting.  1 <= M <= max_batch and S1 a multiple of M (FSE_E_INVAL
+ * otherwise).  The segments run as one batch of M points. */
 
 /* omega HOST [d], Zs device [M][2n][U~]; outputs R device [M][2n][U~], rnorm HOST (||R||_2
  * over all segments, may be NULL), J device [M 2nU~][M 2nU~] row-major or NULL: diagonal
@@ -307,8 +307,11 @@ fse_status fse_multiple_residual_jacobian(fse_ctx *ctx, int32_t M, const double 
 
 /* One Newton update of all sections (Zs device [M][2n][U~], in place) with a dense LU of the
  * block-cyclic Jacobian held by the context; res_norm HOST = ||R||_2 before the update (may
- * be NULL).  FSE_E_SINGULAR on a zero pivot. */
-fse_status fse_multiple_newton_step(fse_ctx *ctx, int32_t M, const double *omega, double *Zs, double *res_norm);
+ * be NULL).  For d > e the unknown frequencies join the unknowns as in fse_newton_step: the
+ * matrix is bordered by dR_m/domega_u (through R(rho / M), d alpha / d omega_u =
+ * 2 pi k_u / (M omega_1)) and by the phase rows of Eq. (18) on section 0, and omega[e..d-1]
+ * (HOST, in/out) is updated.  FSE_E_SINGULAR on a zero pivot. */
+fse_status fse_multiple_newton_step(fse_ctx *ctx, int32_t M, double *omega, double *Zs, double *res_norm);
 
 /* ---------------------------------------------------------------- learned predictor
  * Initial iterates for new continuation parameters from the converged tori of earlier

@@ -440,13 +440,15 @@ def fse_multiple_residual_jacobian(ctx: Context, M, omega, Zs, want_J=False):
 
 
 def fse_multiple_newton_step(ctx: Context, M, omega, Zs):
-    """Zs (torch cuda [M][2n][U], updated in place) <- one dense Newton step -> ||R|| before."""
+    """Zs (torch cuda [M][2n][U], updated in place) <- one dense Newton step -> ||R|| before.
+    For d > e the unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     _torch()
     ctx.bind_stream()
-    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    om = _omega_inout(omega, ctx.d)
     rn = C.c_double()
     ctx.check(ctx.lib.fse_multiple_newton_step(ctx.h, int(M), _p(om, C.c_double), C.c_void_p(Zs.data_ptr()),
                                                C.byref(rn)))
+    _omega_back(omega, om)
     return rn.value
 
 

@@ -18,17 +18,46 @@ namespace {
 
 // J (row-major, MN x MN, diagonal blocks from the single-segment Jacobian, which carries -I):
 // +I on the diagonal blocks, -I on the blocks (m, m + 1 mod M); one thread per row.
-__global__ void k_mult_blocks(double *__restrict__ J, int N, int M) {
+__global__ void k_mult_blocks(double *__restrict__ J, int N, int M, size_t ld) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M * N) return;
   const int m = idx / N, i = idx - (idx / N) * N;
-  const size_t ld = (size_t)M * N, row = (size_t)m * N + i;
+  const size_t row = (size_t)m * N + i;
   J[row * ld + row] += 1.0;
   J[row * ld + (size_t)((m + 1) % M) * N + i] -= 1.0;
 }
 
+// Border of the multiple-shooting Newton matrix for the unknown base frequencies (d > e):
+// column M N + u holds dR_m/domega_{e+u} = (I (x) dR(rho/M)/domega) Gamma^-1 zbar^(m), with
+// R(rho/M) Gamma^-1 zbar^(m) = R_m + Z^(m+1) and d alpha_l / d omega_{e+u} = 2 pi k / (M omega_1);
+// row M N + u is the phase row of Eq. (18) on section 0 (zero over the other sections, which
+// the caller has cleared).
+__global__ void k_mult_border(double *__restrict__ J, size_t ld, int M, int N, int nu, const double *__restrict__ R,
+                              const double *__restrict__ Zs, const int32_t *__restrict__ ktable, int dm1, int e,
+                              double c_w, int U) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int MN = M * N;
+  if (idx >= MN * nu) return;
+  const int u = idx / MN, rr = idx - u * MN, m = rr / N, r = rr - m * N;
+  const int a = r % U, base = r - a;
+  const double *Rm = R + (size_t)m * N, *Zn = Zs + (size_t)((m + 1) % M) * N;
+  double dr = 0.0, pr = 0.0;
+  if (a > 0) {
+    const double k = (double)ktable[(size_t)((a - 1) / 2) * dm1 + e + u - 1];
+    if (a & 1) {  // cos coefficient of the pair
+      dr = -c_w * k * (Rm[base + a + 1] + Zn[base + a + 1]);
+      pr = k * Zs[base + a + 1];
+    } else {      // sin coefficient
+      dr = c_w * k * (Rm[base + a - 1] + Zn[base + a - 1]);
+      pr = -k * Zs[base + a - 1];
+    }
+  }
+  J[(size_t)rr * ld + MN + u] = dr;
+  if (m == 0) J[(size_t)(MN + u) * ld + r] = pr;
+}
+
 fse_status mult_buffers(fse_ctx *ctx, int M) {
-  const size_t N = 2 * (size_t)ctx->n * ctx->U, need = 2 * (size_t)M * N;
+  const size_t N = 2 * (size_t)ctx->n * ctx->U, need = 2 * (size_t)M * N + (ctx->d - ctx->e);
   if (ctx->mult_elems < need) {
     if (ctx->mult) (void)hipFree(ctx->mult);
     ctx->mult = nullptr;
@@ -43,10 +72,6 @@ fse_status mult_buffers(fse_ctx *ctx, int M) {
 }
 
 fse_status mult_check(fse_ctx *ctx, int M) {
-  if (ctx->d != ctx->e) {
-    ctx->err = "multiple shooting is built for d = e";
-    return FSE_E_UNSUPPORTED;
-  }
   if (M < 1 || M > ctx->Bmax) {
     ctx->err = "the number of segments must be in [1, max_batch]";
     return FSE_E_INVAL;
@@ -58,19 +83,11 @@ fse_status mult_check(fse_ctx *ctx, int M) {
   return FSE_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-fse_status fse_multiple_residual_jacobian(fse_ctx *ctx, int32_t M, const double *omega, const double *Zs,
-                                          double *R, double *rnorm, double *J) {
-  if (!ctx || !omega || !Zs || !R) return FSE_E_INVAL;
-  FSE_TRY(mult_check(ctx, M));
+// Residual (and the block-cyclic Jacobian into J with leading dimension ld >= M N) of the
+// M segments at (omega, Zs).
+fse_status mult_system(fse_ctx *ctx, int M, const double *omega, const double *Zs, double *R, double *rnorm,
+                       double *J, size_t ld) {
   const size_t N = 2 * (size_t)ctx->n * ctx->U;
-  if ((size_t)M * N > (size_t)INT32_MAX / 2) {
-    ctx->err = "too many unknowns";
-    return FSE_E_UNSUPPORTED;
-  }
   FSE_TRY(mult_buffers(ctx, M));
   double *Phi = nullptr;
   if (J) {
@@ -104,35 +121,65 @@ fse_status fse_multiple_residual_jacobian(fse_ctx *ctx, int32_t M, const double 
   FSE_TRY(launch_dft(ctx, M, ctx->zTw, Znext, R));
   if (rnorm) FSE_TRY(launch_norm(ctx, R, (size_t)M * N, rnorm));
   if (J) {
-    const size_t ld = (size_t)M * N;
     FSE_HIP(hipMemsetAsync(J, 0, sizeof(double) * ld * ld, ctx->stream));
     const size_t phi_seg = (size_t)ctx->St * 4 * ctx->n * ctx->n;
     for (int m = 0; m < M; ++m)
       FSE_TRY(launch_jacobian(ctx, 1, Phi + (size_t)m * phi_seg, J + (size_t)m * N * ld + (size_t)m * N, ld));
     hipLaunchKernelGGL(k_mult_blocks, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, ctx->stream, J, (int)N,
-                       M);
+                       M, ld);
     FSE_HIP(hipGetLastError());
   }
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
 
-fse_status fse_multiple_newton_step(fse_ctx *ctx, int32_t M, const double *omega, double *Zs, double *res_norm) {
+}  // namespace
+
+extern "C" {
+
+fse_status fse_multiple_residual_jacobian(fse_ctx *ctx, int32_t M, const double *omega, const double *Zs,
+                                          double *R, double *rnorm, double *J) {
+  if (!ctx || !omega || !Zs || !R) return FSE_E_INVAL;
+  FSE_TRY(mult_check(ctx, M));
+  const size_t N = 2 * (size_t)ctx->n * ctx->U;
+  if ((size_t)M * N > (size_t)INT32_MAX / 2) {
+    ctx->err = "too many unknowns";
+    return FSE_E_UNSUPPORTED;
+  }
+  return mult_system(ctx, M, omega, Zs, R, rnorm, J, (size_t)M * N);
+}
+
+fse_status fse_multiple_newton_step(fse_ctx *ctx, int32_t M, double *omega, double *Zs, double *res_norm) {
   if (!ctx || !omega || !Zs) return FSE_E_INVAL;
   FSE_TRY(mult_check(ctx, M));
   const size_t N = 2 * (size_t)ctx->n * ctx->U, NM = (size_t)M * N;
-  if (NM > (size_t)INT32_MAX / 2) {
+  const int nu = ctx->d - ctx->e;
+  const size_t Nb = NM + nu;
+  if (Nb > (size_t)INT32_MAX / 2) {
     ctx->err = "too many unknowns for the dense Newton step";
     return FSE_E_UNSUPPORTED;
   }
   FSE_TRY(mult_buffers(ctx, M));
-  FSE_TRY(ensure_dense_matrix(ctx, NM));
-  double *R = ctx->mult + NM;
+  FSE_TRY(ensure_dense_matrix(ctx, Nb));
+  double *R = ctx->mult + NM;  // [M N + nu]: residuals, then the phase-row zeros
   double rn = 0.0;
-  FSE_TRY(fse_multiple_residual_jacobian(ctx, M, omega, Zs, R, &rn, ctx->Jw));
+  FSE_TRY(mult_system(ctx, M, omega, Zs, R, &rn, ctx->Jw, Nb));
   if (res_norm) *res_norm = rn;
-  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, (int)NM, R));
+  if (nu > 0) {
+    hipLaunchKernelGGL(k_mult_border, dim3((unsigned)((NM * nu + 255) / 256)), dim3(256), 0, ctx->stream, ctx->Jw,
+                       Nb, M, (int)N, nu, R, Zs, ctx->ktable_d, ctx->d - 1, ctx->e, 2.0 * M_PI / (M * omega[0]),
+                       ctx->U);
+    FSE_HIP(hipGetLastError());
+    FSE_HIP(hipMemsetAsync(R + NM, 0, sizeof(double) * nu, ctx->stream));
+  }
+  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, (int)Nb, R));
   FSE_TRY(launch_axpy(ctx, (int)NM, -1.0, R, Zs));
+  if (nu > 0) {
+    std::vector<double> dw(nu);
+    FSE_HIP(hipMemcpyAsync(dw.data(), R + NM, sizeof(double) * nu, hipMemcpyDeviceToHost, ctx->stream));
+    FSE_HIP(hipStreamSynchronize(ctx->stream));
+    for (int u = 0; u < nu; ++u) omega[ctx->e + u] -= dw[u];
+  }
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }

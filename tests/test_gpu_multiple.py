@@ -133,7 +133,25 @@ def test_invalid_calls():
     ctx5 = fse().fse_init_torus(s, Torus(d=2, e=2, K=[np.arange(1, 3)], S=[8], S1=50), max_batch=4)
     with pytest.raises(fse().FseError, match="FSE_E_INVAL"):
         fse().fse_multiple_newton_step(ctx5, 4, om, Z[:2].repeat(2, 1, 1))   # 50 steps, 4 segments
-    su = tiny_system(n=2, seed=2, cubic=1.0, quad=0.3, e=1)
-    ctxu = fse().fse_init_torus(su, Torus(d=2, e=1, K=[np.arange(1, 3)], S=[8], S1=48), max_batch=2)
-    with pytest.raises(fse().FseError, match="FSE_E_UNSUPPORTED"):
-        fse().fse_multiple_residual_jacobian(ctxu, 2, om, Z[:2])
+
+
+@pytest.mark.parametrize("M", [1, 2, 3])
+def test_unknown_frequency_bordered_step(M):
+    """d = 2, e = 1: the bordered multiple-shooting step (dR_m/domega_2 columns, phase rows on
+    section 0) equals the oracle's, sections and omega_2 within 1e-10 relative."""
+    import torch
+    s = tiny_system(n=2, seed=8, cubic=1.0, quad=0.3, e=1)
+    tr = Torus(d=2, e=1, K=[np.arange(1, 3)], S=[5], S1=24)
+    tb = osh.TorusTables(tr)
+    om = np.array([1.05, 1.05 * GOLDEN])
+    Zs = 0.2 * np.random.default_rng(M).normal(size=(M, 4, tb.U))
+    Z1, om1, r0 = omult.newton_step(s, tr, om, Zs, M, tables=tb)
+    ctx = fse().fse_init_torus(s, tr, max_batch=M)
+    Zg = torch.tensor(Zs, dtype=torch.float64, device="cuda")
+    omg = om.copy()
+    rn = fse().fse_multiple_newton_step(ctx, M, omg, Zg)
+    log(f"bordered multiple shooting M={M}: ||R|| {rn:.3e}, omega_2 {omg[1]:.14f} (oracle {om1[1]:.14f})")
+    assert abs(rn - r0) < 1e-12 * r0
+    assert rel(Zg.cpu().numpy(), Z1) < 1e-10
+    assert abs(omg[1] - om1[1]) < 1e-10 * abs(om1[1])
+    assert omg[0] == om[0]
