@@ -241,7 +241,8 @@ fse_status fse_arclength(fse_ctx *ctx, int32_t P, const double *omega0, const do
  * For unknown counts whose dense Jacobian is too large to factor, the Jacobian of Eq. (22) is
  * applied to vectors instead:
  *     J v = (I (x) R(rho) Gamma^-1) blkdiag_s(Phi_s) (I (x) Gamma) v - v,
- * using the trajectory sensitivities kept by the context (one point, d = e). */
+ * using the trajectory sensitivities kept by the context (one point).  fse_jacobian_apply
+ * applies J alone; fse_newton_krylov_step borders it for unknown frequencies (d > e). */
 
 /* Residual R (device [2n][U], and ||R||_2 on the host if rnorm is non-null) at one point
  * (omega HOST [d], Z0 device [2n][U]); keeps the sensitivities of every trajectory in the
