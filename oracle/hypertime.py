@@ -15,7 +15,9 @@ Pins (tests/test_oracle_hypertime.py): for zbar(0) = Gamma Z(0), the hyper-time 
 Gamma applied to the multi-frequency residual (Gamma^-1 Gamma = I); the Jacobian against
 central differences; a linear system's closed-form torus, sampled, solves it, and one Newton
 step reaches it; on a nonlinear system the hyper-time Newton solution is the sampled
-multi-frequency torus.
+multi-frequency torus.  With unknown frequencies (border of `border`, a reading: the paper
+gives this form no phase condition): with S~ = U~ the bordered step is Gamma times the
+multi-frequency bordered step, and the border column matches central differences.
 """
 from __future__ import annotations
 
@@ -64,12 +66,40 @@ def jacobian(res):
     return J - np.eye(n2 * St)
 
 
+def border(res, omega, e, zbar0):
+    """Border of the Newton matrix for the unknown frequencies u = e+1..d (the paper gives the
+    hyper-time form no phase condition; this carries Eqs. 18 and 23-24 over through
+    Z = Gamma^-1 zbar): columns dR/d omega_u = (I (x) Gamma dR(rho)/d omega_u Gamma^-1) zbar(2 pi)
+    and phase rows [(I (x) nabla_{phi_u}) Gamma^-1 zbar(0)]^T (I (x) Gamma^-1), as
+    ([2n S~][d-e], [d-e][2n S~])."""
+    tb = res["tables"]
+    omega = np.asarray(omega, dtype=float)
+    d = len(omega)
+    z0 = np.asarray(zbar0, dtype=float)
+    cols, rows = [], []
+    for i in range(e + 1, d + 1):
+        dA = tb.G @ tor.rotation_domega(tb.table, omega, i) @ tb.Gi
+        cols.append((res["zbarT"] @ dA.T).ravel())
+        pz = (z0 @ tb.Gi.T) @ tor.nabla(tb.table, i).T          # (I (x) nabla) Z(0), [2n][U~]
+        rows.append((pz @ tb.Gi).ravel())                        # times (I (x) Gamma^-1)
+    return np.array(cols).T, np.array(rows)
+
+
 def newton_step(sysm, torus, omega, zbar0, tables=None, tol=1e-12):
-    """zbar0 -> zbar0 - J^-1 R; returns (zbar_new, ||R||_2 before)."""
+    """zbar0 -> zbar0 - J^-1 R; returns (zbar_new, ||R||_2 before).  For d > e the unknowns are
+    [zbar(0); omega_u] with the border of `border`; returns (zbar_new, omega_new, ||R||_2)."""
     res = evaluate(sysm, torus, omega, zbar0, sens=True, tables=tables, tol=tol)
     J = jacobian(res)
-    dz = np.linalg.solve(J, -res["R"].ravel())
-    return zbar0 + dz.reshape(np.shape(zbar0)), float(np.linalg.norm(res["R"]))
+    if torus.d == torus.e:
+        dz = np.linalg.solve(J, -res["R"].ravel())
+        return zbar0 + dz.reshape(np.shape(zbar0)), float(np.linalg.norm(res["R"]))
+    nu = torus.d - torus.e
+    B, P = border(res, omega, torus.e, zbar0)
+    big = np.block([[J, B], [P, np.zeros((nu, nu))]])
+    x = np.linalg.solve(big, np.concatenate([-res["R"].ravel(), np.zeros(nu)]))
+    om = np.array(omega, dtype=float)
+    om[torus.e:] += x[-nu:]
+    return np.asarray(zbar0, float) + x[:-nu].reshape(np.shape(zbar0)), om, float(np.linalg.norm(res["R"]))
 
 
 def solve(sysm, torus, omega, zbar0, tol_R=1e-8, max_newton=20, tables=None):

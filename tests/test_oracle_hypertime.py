@@ -64,3 +64,27 @@ def test_nonlinear_solution_is_the_sampled_multifrequency_torus():
     zh, hh = ht.solve(s, tr, om, np.zeros((4, tb.Stilde)), tol_R=1e-13, tables=tb)
     assert hm[-1] < 1e-13 and hh[-1] < 1e-13
     assert np.abs(zh - Zm @ tb.G.T).max() < 1e-10 * np.abs(zh).max()
+
+
+def test_unknown_frequency_border_matches_the_multi_frequency_step():
+    """d > e with S~ = U~ (Gamma invertible): the bordered hyper-time step from zbar = Gamma Z is
+    Gamma times the multi-frequency bordered step, with the same omega_u update; the border
+    column matches central differences in omega_2."""
+    from oracle import hypertime as oht
+    s = tiny_system(n=2, seed=8, cubic=1.0, quad=0.3, e=1)
+    tr = Torus(d=2, e=1, K=[np.arange(1, 3)], S=[5], S1=20)
+    tb = shooting.TorusTables(tr)
+    assert tb.Stilde == tb.U
+    om = np.array([1.05, 1.05 * (1 + 5 ** 0.5) / 2])
+    Z0 = 0.2 * np.random.default_rng(2).normal(size=(4, tb.U))
+    Z1, om1, r1 = shooting.newton_step(s, tr, om, Z0, tables=tb)
+    zb1, omh, rh = oht.newton_step(s, tr, om, Z0 @ tb.G.T, tables=tb)
+    assert np.allclose(zb1, Z1 @ tb.G.T, rtol=1e-9, atol=1e-11)
+    assert np.allclose(omh, om1, rtol=1e-11)
+    res = oht.evaluate(s, tr, om, Z0 @ tb.G.T, tables=tb)
+    B, P = oht.border(res, om, 1, Z0 @ tb.G.T)
+    h = 1e-6
+    e2 = np.array([0.0, h])
+    fd = (oht.evaluate(s, tr, om + e2, Z0 @ tb.G.T, tables=tb)["R"]
+          - oht.evaluate(s, tr, om - e2, Z0 @ tb.G.T, tables=tb)["R"]).ravel() / (2 * h)
+    assert np.allclose(B[:, 0], fd, rtol=1e-7, atol=1e-9)
