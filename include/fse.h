@@ -275,7 +275,8 @@ fse_status fse_newton_krylov_step(fse_ctx *ctx, double *omega, double *Z0, doubl
  * FSE-Shooting with the sampled initial states as unknowns (Sec. 3.4, Eq. FSES_T):
  *     R(zbar(0), omega) = (I (x) Gamma R(rho) Gamma^-1) zbar(2 pi) - zbar(0),
  * zbar(0), zbar(2 pi) and R laid out [2n][S~] per point; unknowns (i, s) -> i S~ + s.
- * d = e only (FSE_E_UNSUPPORTED otherwise). */
+ * The paper gives this form no phase condition; with unknown frequencies (d > e) the Newton
+ * step carries Eqs. (18) and (23)-(24) over through Z = Gamma^-1 zbar. */
 
 /* omega HOST [B][d], zbar0 device [B][2n][S~]; outputs R device [B][2n][S~], rnorm HOST [B]
  * (may be NULL), J device [B][2nS~][2nS~] row-major or NULL (then no sensitivities are
@@ -286,8 +287,11 @@ fse_status fse_hypertime_residual_jacobian(fse_ctx *ctx, int32_t B, const double
 
 /* One Newton update of the hyper-time unknowns (zbar0 device [2n][S~], in place) with a dense
  * LU of the (2nS~)^2 Jacobian held by the context; res_norm HOST = ||R||_2 before the update
- * (may be NULL).  FSE_E_SINGULAR on a zero pivot. */
-fse_status fse_hypertime_newton_step(fse_ctx *ctx, const double *omega, double *zbar0, double *res_norm);
+ * (may be NULL).  For d > e the matrix is bordered by the columns
+ * (I (x) Gamma dR(rho)/domega_u Gamma^-1) zbar(2 pi) and the phase rows
+ * [(I (x) nabla_{phi_u}) Gamma^-1 zbar(0)]^T (I (x) Gamma^-1), and omega[e..d-1] (HOST, in/out)
+ * is updated.  FSE_E_SINGULAR on a zero pivot. */
+fse_status fse_hypertime_newton_step(fse_ctx *ctx, double *omega, double *zbar0, double *res_norm);
 
 /* ---------------------------------------------------------------- multiple FSE-Shooting
  * The paper's first recommendation for future work (Sec. 5), in the classical multiple-

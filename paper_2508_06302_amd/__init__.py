@@ -453,13 +453,15 @@ def fse_multiple_newton_step(ctx: Context, M, omega, Zs):
 
 
 def fse_hypertime_newton_step(ctx: Context, omega, zbar0):
-    """zbar0 (torch cuda [2n][S~], updated in place) <- one dense Newton step -> ||R|| before."""
+    """zbar0 (torch cuda [2n][S~], updated in place) <- one dense Newton step -> ||R|| before.
+    For d > e the unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     _torch()
     ctx.bind_stream()
-    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    om = _omega_inout(omega, ctx.d)
     rn = C.c_double()
     ctx.check(ctx.lib.fse_hypertime_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(zbar0.data_ptr()),
                                                 C.byref(rn)))
+    _omega_back(omega, om)
     return rn.value
 
 

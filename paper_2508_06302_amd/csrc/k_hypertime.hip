@@ -5,7 +5,7 @@
 // with zbar(2 pi) from the same trajectory kernels as the multi-frequency form, and its
 // Jacobian J[(i, s), (j, t)] = A[s, t] Phi_t[i, j] - delta (unknowns state-major,
 // (i, s) -> i S~ + s).  A is built on the device per point from Gamma, Gamma^-1 and the
-// rotation angles of Eq. (14).  d = e only.
+// rotation angles of Eq. (14).  With unknown frequencies the Newton step is bordered (k_ht_border).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -79,7 +79,7 @@ __global__ void k_ht_residual(const double *__restrict__ zT, int ldw, const doub
 
 // J[(i, s), (j, t)] = A[s][t] Phi_{b S~ + t}[i][j] - delta for one point b (grid-stride)
 __global__ void k_ht_jac(const double *__restrict__ A, const double *__restrict__ Phi, int n2, int St, int b,
-                         double *__restrict__ J) {
+                         double *__restrict__ J, size_t ld) {
   const size_t Nh = (size_t)n2 * St;
   const size_t total = Nh * Nh;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -87,13 +87,48 @@ __global__ void k_ht_jac(const double *__restrict__ A, const double *__restrict_
     const size_t row = idx / Nh, col = idx - (idx / Nh) * Nh;
     const int i = (int)(row / St), s = (int)(row % St), j = (int)(col / St), t = (int)(col % St);
     const double v = A[((size_t)b * St + s) * St + t] * Phi[(((size_t)b * St + t) * n2 + i) * n2 + j];
-    J[idx] = v - (row == col ? 1.0 : 0.0);
+    J[row * ld + col] = v - (row == col ? 1.0 : 0.0);
   }
+}
+
+// Border of the hyper-time Newton matrix for the unknown frequencies (d > e), through
+// Z = Gamma^-1 zbar (the paper gives this form no phase condition): column Nh + u holds
+// dR/domega_{e+u} = (I (x) Gamma dR(rho)/domega Gamma^-1) zbar(2 pi), with R(rho) Gamma^-1 zbar(2 pi)
+// = RGi zbar(2 pi) and d alpha_l / d omega = 2 pi k / omega_1; row Nh + u is the phase row of
+// Eq. (18), [(I (x) nabla_{phi_{e+u}}) Gamma^-1 zbar(0)]^T (I (x) Gamma^-1).  One point (b = 0).
+__global__ void k_ht_border(double *__restrict__ J, size_t ld, int Nh, int nu, int n2, int St, int U, int L,
+                            const double *__restrict__ zT, int ldw, const double *__restrict__ zb0,
+                            const double *__restrict__ RGi, const double *__restrict__ G,
+                            const double *__restrict__ Gi, const int32_t *__restrict__ ktable, int dm1, int e,
+                            double c_w) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Nh * nu) return;
+  const int u = idx / Nh, rr = idx - u * Nh, i = rr / St, s = rr - i * St;
+  double col = 0.0, row = 0.0;
+  for (int l = 0; l < L; ++l) {
+    const double k = (double)ktable[(size_t)l * dm1 + e + u - 1];
+    if (k == 0.0) continue;
+    const double *rc = RGi + (size_t)(2 * l + 1) * St, *rs = rc + St;
+    const double *gc = Gi + (size_t)(2 * l + 1) * St, *gs = gc + St;
+    double wc = 0.0, ws = 0.0, vc = 0.0, vs = 0.0;
+    for (int t = 0; t < St; ++t) {
+      const double zt = zT[(size_t)i * ldw + t], z0 = zb0[(size_t)i * St + t];
+      wc += rc[t] * zt;
+      ws += rs[t] * zt;
+      vc += gc[t] * z0;
+      vs += gs[t] * z0;
+    }
+    col += c_w * k * (G[(size_t)s * U + 2 * l + 1] * (-ws) + G[(size_t)s * U + 2 * l + 2] * wc);
+    row += k * (vs * gc[s] - vc * gs[s]);
+  }
+  J[(size_t)rr * ld + Nh + u] = col;
+  J[(size_t)(Nh + u) * ld + rr] = row;
+  if (rr < nu) J[(size_t)(Nh + u) * ld + Nh + rr] = 0.0;
 }
 
 fse_status ht_buffers(fse_ctx *ctx) {
   const size_t St = ctx->St, U = ctx->U, B = ctx->Bmax, Nh = 2 * (size_t)ctx->n * St;
-  const size_t need = B * U * St + B * St * St + B * Nh;
+  const size_t need = B * U * St + B * St * St + B * Nh + (ctx->d - ctx->e);
   if (ctx->ht_elems < need) {
     if (ctx->ht) (void)hipFree(ctx->ht);
     ctx->ht = nullptr;
@@ -118,15 +153,9 @@ fse_status launch_samples_in(fse_ctx *ctx, int B, const double *zbar0) {
   return FSE_OK;
 }
 
-extern "C" {
-
-fse_status fse_hypertime_residual_jacobian(fse_ctx *ctx, int32_t B, const double *omega, const double *zbar0,
-                                           double *R, double *rnorm, double *J) {
-  if (!ctx || !omega || !zbar0 || !R) return FSE_E_INVAL;
-  if (ctx->d != ctx->e) {
-    ctx->err = "hyper-time shooting is built for d = e";
-    return FSE_E_UNSUPPORTED;
-  }
+// Residual and (J != null) Jacobian of B points, each J with leading dimension ld >= 2n S~.
+static fse_status ht_system(fse_ctx *ctx, int32_t B, const double *omega, const double *zbar0, double *R,
+                            double *rnorm, double *J, size_t ld) {
   if (B < 1 || B > ctx->Bmax) {
     ctx->err = "B out of range [1, max_batch]";
     return FSE_E_INVAL;
@@ -158,28 +187,53 @@ fse_status fse_hypertime_residual_jacobian(fse_ctx *ctx, int32_t B, const double
     const size_t total = Nh * Nh;
     const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 1u << 20);
     for (int b = 0; b < B; ++b)
-      hipLaunchKernelGGL(k_ht_jac, dim3(blocks), dim3(256), 0, ctx->stream, A, Phi, n2, St, b, J + (size_t)b * total);
+      hipLaunchKernelGGL(k_ht_jac, dim3(blocks), dim3(256), 0, ctx->stream, A, Phi, n2, St, b, J + (size_t)b * ld * ld,
+                         ld);
     FSE_HIP(hipGetLastError());
   }
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
 
-fse_status fse_hypertime_newton_step(fse_ctx *ctx, const double *omega, double *zbar0, double *res_norm) {
+extern "C" {
+
+fse_status fse_hypertime_residual_jacobian(fse_ctx *ctx, int32_t B, const double *omega, const double *zbar0,
+                                           double *R, double *rnorm, double *J) {
+  if (!ctx || !omega || !zbar0 || !R) return FSE_E_INVAL;
+  return ht_system(ctx, B, omega, zbar0, R, rnorm, J, 2 * (size_t)ctx->n * ctx->St);
+}
+
+fse_status fse_hypertime_newton_step(fse_ctx *ctx, double *omega, double *zbar0, double *res_norm) {
   if (!ctx || !omega || !zbar0) return FSE_E_INVAL;
   const size_t Nh = 2 * (size_t)ctx->n * ctx->St;
-  if (Nh > (size_t)INT32_MAX / 2) {
+  const int nu = ctx->d - ctx->e;
+  const size_t Nb = Nh + nu;
+  if (Nb > (size_t)INT32_MAX / 2) {
     ctx->err = "too many hyper-time unknowns for the dense Newton step";
     return FSE_E_UNSUPPORTED;
   }
   FSE_TRY(ht_buffers(ctx));
-  FSE_TRY(ensure_dense_matrix(ctx, Nh));
+  FSE_TRY(ensure_dense_matrix(ctx, Nb));
+  const double *RGi = ctx->ht;
   double *R = ctx->ht + (size_t)ctx->Bmax * ctx->U * ctx->St + (size_t)ctx->Bmax * ctx->St * ctx->St;
   double rn = 0.0;
-  FSE_TRY(fse_hypertime_residual_jacobian(ctx, 1, omega, zbar0, R, &rn, ctx->Jw));
+  FSE_TRY(ht_system(ctx, 1, omega, zbar0, R, &rn, ctx->Jw, Nb));
   if (res_norm) *res_norm = rn;
-  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, (int)Nh, R));
+  if (nu > 0) {
+    hipLaunchKernelGGL(k_ht_border, dim3((unsigned)((Nh * nu + 255) / 256)), dim3(256), 0, ctx->stream, ctx->Jw, Nb,
+                       (int)Nh, nu, 2 * ctx->n, ctx->St, ctx->U, ctx->L, ctx->zTw, ctx->Wmax, zbar0, RGi, ctx->G_d,
+                       ctx->Gi_d, ctx->ktable_d, ctx->d - 1, ctx->e, 2.0 * M_PI / omega[0]);
+    FSE_HIP(hipGetLastError());
+    FSE_HIP(hipMemsetAsync(R + Nh, 0, sizeof(double) * nu, ctx->stream));
+  }
+  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, (int)Nb, R));
   FSE_TRY(launch_axpy(ctx, (int)Nh, -1.0, R, zbar0));
+  if (nu > 0) {
+    std::vector<double> dw(nu);
+    FSE_HIP(hipMemcpyAsync(dw.data(), R + Nh, sizeof(double) * nu, hipMemcpyDeviceToHost, ctx->stream));
+    FSE_HIP(hipStreamSynchronize(ctx->stream));
+    for (int u = 0; u < nu; ++u) omega[ctx->e + u] -= dw[u];
+  }
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }

@@ -86,3 +86,26 @@ def test_newton_reaches_the_sampled_multifrequency_torus():
     Zm = torch.zeros((4, tb.U), dtype=torch.float64, device="cuda")
     fse().fse_newton_solve(ctx, om, Zm, tol=1e-13, maxit=20)
     assert rel(zg, Zm.cpu().numpy() @ tb.G.T) < 1e-9
+
+
+@pytest.mark.parametrize("S", [5, 7])
+def test_unknown_frequency_bordered_step(S):
+    """d = 2, e = 1 (S~ = U~ and S~ > U~): the bordered hyper-time step equals the oracle's,
+    samples and omega_2 within 1e-10 relative."""
+    import torch
+    from oracle import hypertime as oht
+    s = tiny_system(n=2, seed=8, cubic=1.0, quad=0.3, e=1)
+    tr = Torus(d=2, e=1, K=[np.arange(1, 3)], S=[S], S1=20)
+    tb = osh.TorusTables(tr)
+    om = np.array([1.05, 1.05 * (1 + 5 ** 0.5) / 2])
+    Z0 = 0.2 * np.random.default_rng(2).normal(size=(4, tb.U))
+    zb0 = Z0 @ tb.G.T
+    zb1, om1, r0 = oht.newton_step(s, tr, om, zb0, tables=tb)
+    ctx = fse().fse_init_torus(s, tr)
+    zg = torch.tensor(zb0, dtype=torch.float64, device="cuda")
+    omg = om.copy()
+    rn = fse().fse_hypertime_newton_step(ctx, omg, zg)
+    print(f"bordered hyper-time S={S}: omega_2 {omg[1]:.14f} (oracle {om1[1]:.14f})", flush=True)
+    assert abs(rn - r0) < 1e-12 * r0
+    assert np.linalg.norm(zg.cpu().numpy() - zb1) < 1e-10 * np.linalg.norm(zb1)
+    assert abs(omg[1] - om1[1]) < 1e-10 * abs(om1[1])
