@@ -8,8 +8,9 @@ The S~ x S~ operator A = Gamma R(rho) Gamma^-1 shifts the sampled torus by -2 pi
 its Fourier interpolant.  Its Jacobian is
     J[(i, s), (j, t)] = A[s, t] Phi_t[i, j] - delta,
 with Phi_t the sensitivity matrix of trajectory t (Eqs. E8-E9).  Unknowns are ordered
-state-major, (i, s) -> i S~ + s.  Only d = e is built: the unknown-frequency rows of the
-multi-frequency form have no counterpart here yet.
+state-major, (i, s) -> i S~ + s.  With unknown frequencies (d > e) the Newton step is bordered
+by the columns dR/domega_u and the phase rows of Eq. (18) carried over through Z = Gamma^-1 zbar
+(`border`), and the step also updates omega_u.
 
 Pins (tests/test_oracle_hypertime.py): for zbar(0) = Gamma Z(0), the hyper-time residual is
 Gamma applied to the multi-frequency residual (Gamma^-1 Gamma = I); the Jacobian against
@@ -103,15 +104,22 @@ def newton_step(sysm, torus, omega, zbar0, tables=None, tol=1e-12):
 
 
 def solve(sysm, torus, omega, zbar0, tol_R=1e-8, max_newton=20, tables=None):
-    """Newton iterations until ||R||_2 < tol_R; returns (zbar0, history of ||R||_2)."""
+    """Newton iterations until ||R||_2 < tol_R; returns (zbar0, history of ||R||_2), and for
+    d > e (unknown frequencies, bordered step) (zbar0, omega, history)."""
     z = np.array(zbar0, dtype=float)
+    om = np.array(omega, dtype=float)
+    bordered = torus.d > torus.e
     hist = []
     for _ in range(max_newton):
-        z_new, r = newton_step(sysm, torus, omega, z, tables=tables)
+        if bordered:
+            z_new, om_new, r = newton_step(sysm, torus, om, z, tables=tables)
+        else:
+            z_new, r = newton_step(sysm, torus, om, z, tables=tables)
+            om_new = om
         hist.append(r)
         if r < tol_R:
-            return z, hist
-        z = z_new
-    res = evaluate(sysm, torus, omega, z, tables=tables)
+            return (z, om, hist) if bordered else (z, hist)
+        z, om = z_new, om_new
+    res = evaluate(sysm, torus, om, z, tables=tables)
     hist.append(float(np.linalg.norm(res["R"])))
-    return z, hist
+    return (z, om, hist) if bordered else (z, hist)

@@ -12,6 +12,11 @@ values:
   bf16_round      round-to-nearest-even to bfloat16 (8 significand bits), pinned by
                   hand-worked values; mlp_forward_bf16 is mlp_forward with every layer's
                   weights and inputs rounded to bfloat16 (the reduced-precision inference)
+  adamw_step      the published AdamW rule (Adam with bias-corrected moments, weight decay
+                  decoupled from the gradient and scaled by the learning rate), pinned by
+                  torch.optim.AdamW in FP64 and by three closed forms: constant-gradient
+                  steps of exactly lr g/(|g| + eps), geometric decay under zero gradient,
+                  scale invariance of the first step
 """
 from __future__ import annotations
 

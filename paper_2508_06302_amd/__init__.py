@@ -185,13 +185,21 @@ def fse_shooting_residual_jacobian(ctx: Context, omega, Z0, want_J=False):
     return R, rn, J
 
 
-def _omega_inout(omega, d):
-    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(d)).copy()
-    return om
+def _omega_inout(omega, d, e):
+    """Host copy of omega [d] for a call that updates the unknown frequencies omega[e:] in place.
+    With d > e the caller's omega must be a writable contiguous float64 ndarray of d entries
+    (the updated frequencies are written back into it); anything else raises TypeError, so
+    Z(0) and omega can never drift apart."""
+    if d > e and not (isinstance(omega, np.ndarray) and omega.dtype == np.float64
+                      and omega.size == d and omega.flags.writeable and omega.flags.c_contiguous):
+        raise TypeError("with unknown frequencies (d > e) omega must be a writable contiguous "
+                        "float64 numpy array of d entries; it is updated in place")
+    return np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(d)).copy()
 
 
 def _omega_back(omega, om):
-    if isinstance(omega, np.ndarray) and omega.dtype == np.float64 and omega.size == om.size:
+    if isinstance(omega, np.ndarray) and omega.dtype == np.float64 and omega.size == om.size \
+            and omega.flags.writeable and omega.flags.c_contiguous:
         omega.reshape(-1)[:] = om
 
 
@@ -199,7 +207,7 @@ def fse_newton_step(ctx: Context, omega, Z0):
     """Z0 (torch cuda tensor [2n][U], updated in place) -> ||R||_2 before the update.
     For d > e the unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     ctx.bind_stream()
-    om = _omega_inout(omega, ctx.d)
+    om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
     ctx.check(ctx.lib.fse_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
                                       C.byref(rn)))
@@ -211,7 +219,7 @@ def fse_newton_solve(ctx: Context, omega, Z0, tol=1e-8, maxit=20):
     """Z0 (torch cuda tensor, in place) -> (iterations, final ||R||_2).  For d > e the
     unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     ctx.bind_stream()
-    om = _omega_inout(omega, ctx.d)
+    om = _omega_inout(omega, ctx.d, ctx.e)
     it, rn = C.c_int32(), C.c_double()
     st = ctx.lib.fse_newton_solve(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
                                   tol, maxit, C.byref(it), C.byref(rn))
@@ -392,7 +400,7 @@ def fse_newton_krylov_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxi
     frequencies omega[e:] are updated in place (numpy float64 array), as in fse_newton_step."""
     _torch()
     ctx.bind_stream()
-    om = _omega_inout(omega, ctx.d)
+    om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
     its = C.c_int32()
     rel = C.c_double()
@@ -444,7 +452,7 @@ def fse_multiple_newton_step(ctx: Context, M, omega, Zs):
     For d > e the unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     _torch()
     ctx.bind_stream()
-    om = _omega_inout(omega, ctx.d)
+    om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
     ctx.check(ctx.lib.fse_multiple_newton_step(ctx.h, int(M), _p(om, C.c_double), C.c_void_p(Zs.data_ptr()),
                                                C.byref(rn)))
@@ -457,7 +465,7 @@ def fse_hypertime_newton_step(ctx: Context, omega, zbar0):
     For d > e the unknown frequencies omega[e:] are updated in place (numpy float64 array)."""
     _torch()
     ctx.bind_stream()
-    om = _omega_inout(omega, ctx.d)
+    om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
     ctx.check(ctx.lib.fse_hypertime_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(zbar0.data_ptr()),
                                                 C.byref(rn)))

@@ -88,3 +88,32 @@ def test_unknown_frequency_border_matches_the_multi_frequency_step():
     fd = (oht.evaluate(s, tr, om + e2, Z0 @ tb.G.T, tables=tb)["R"]
           - oht.evaluate(s, tr, om - e2, Z0 @ tb.G.T, tables=tb)["R"]).ravel() / (2 * h)
     assert np.allclose(B[:, 0], fd, rtol=1e-7, atol=1e-9)
+
+
+def test_bordered_solve_returns_the_unknown_frequency_and_reaches_the_van_der_pol_torus():
+    """d > e: solve() carries omega_u through every bordered step.  On the forced van der Pol
+    oscillator (omega_2 the free limit-cycle frequency) the hyper-time solution, started from
+    the sampled averaging iterate, has the free frequency of the multi-frequency solution and
+    its samples are that torus up to the phase along omega_2 (compared through amplitudes)."""
+    import math
+    from _velocity_systems import van_der_pol
+    from fse_inputs.systems import place_harmonics
+    s = van_der_pol(mu=0.2)
+    w1 = 2.3
+    tr = Torus(d=2, e=1, K=[np.arange(1, 6)], S=[11], S1=96)
+    tb = shooting.TorusTables(tr)
+    A = 0.5 / (1 - w1 ** 2)
+    Z0 = place_harmonics(tb.table, [((0,), np.array([A, 0.0], complex)), ((1,), np.array([2.0, 2j / w1]))],
+                         1, tb.U)
+    om = np.array([w1, 1.0])
+    Zm, omm, hm = shooting.solve(s, tr, om, Z0, tol_R=1e-11, max_newton=25, tables=tb)
+    out = ht.solve(s, tr, om, Z0 @ tb.G.T, tol_R=1e-11, max_newton=25, tables=tb)
+    assert len(out) == 3
+    zh, omh, hist = out
+    assert hm[-1] < 1e-11 and hist[-1] < 1e-11
+    assert omh[0] == om[0]
+    assert abs(omh[1] - omm[1]) < 1e-9
+    Zh = zh @ tb.Gi.T
+    amp = lambda Z, l: math.hypot(Z[0, 2 * l + 1], Z[0, 2 * l + 2])
+    for l in range(tb.U // 2):
+        assert abs(amp(Zh, l) - amp(Zm, l)) < 1e-8

@@ -70,3 +70,54 @@ def test_bf16_rounding_hand_worked_values():
     rv = bf16_round(v)
     assert np.all(np.abs(rv - v) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-7))
     assert np.array_equal(bf16_round(rv), rv)
+
+
+def _adamw_run(params, grads_seq, **kw):
+    state = {}
+    for g in grads_seq:
+        params = learned.adamw_step(params, g, state, **kw)
+    return params
+
+
+def test_adamw_matches_torch_adamw():
+    """The published AdamW rule (Adam moments with bias correction, weight decay decoupled from
+    the gradient and scaled by the learning rate) as implemented by torch.optim.AdamW, in FP64."""
+    import torch
+    rng = np.random.default_rng(11)
+    shapes = [(4, 3), (4,), (2, 4), (2,)]
+    p0 = [rng.normal(size=sh) for sh in shapes]
+    grads = [[rng.normal(size=sh) * (1 + 5 * k % 3) for sh in shapes] for k in range(25)]
+    lr, wd = 3e-2, 5e-2
+    params = [[p0[0].copy(), p0[1].copy()], [p0[2].copy(), p0[3].copy()]]
+    out = _adamw_run(params, [[[g[0], g[1]], [g[2], g[3]]] for g in grads], lr=lr, wd=wd)
+    tp = [torch.tensor(p, dtype=torch.float64, requires_grad=True) for p in p0]
+    opt = torch.optim.AdamW(tp, lr=lr, betas=(0.9, 0.999), eps=1e-8, weight_decay=wd)
+    for g in grads:
+        for t, gg in zip(tp, g):
+            t.grad = torch.tensor(gg, dtype=torch.float64)
+        opt.step()
+    mine = [out[0][0], out[0][1], out[1][0], out[1][1]]
+    for a, t in zip(mine, tp):
+        assert np.allclose(a, t.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_adamw_closed_forms():
+    """Three consequences of the rule that a dropped bias correction, a wrong moment power or a
+    decay coupled into the gradient would each break:
+    (i) a constant gradient g moves every entry by lr g / (|g| + eps) per step, whatever |g|
+        (m_t / (1 - b1^t) = g and v_t / (1 - b2^t) = g^2 exactly);
+    (ii) with zero gradient the decoupled decay is geometric: p_T = (1 - lr wd)^T p_0;
+    (iii) the first step is invariant under scaling the gradient (up to eps)."""
+    lr = 1e-2
+    p0 = np.array([0.7, -1.3, 2.0, 0.0])
+    g = np.array([3.0, -0.02, 1e-3, -40.0])
+    T = 17
+    out = _adamw_run([[p0.copy()]], [[[g]]] * T, lr=lr, wd=0.0)[0][0]
+    assert np.allclose(out, p0 - T * lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14)
+    wd = 0.3
+    out = _adamw_run([[p0.copy()]], [[[np.zeros(4)]]] * T, lr=lr, wd=wd)[0][0]
+    assert np.allclose(out, (1 - lr * wd) ** T * p0, rtol=1e-14, atol=0)
+    a = _adamw_run([[p0.copy()]], [[[g]]], lr=lr, wd=0.0, eps=0.0)[0][0]
+    b = _adamw_run([[p0.copy()]], [[[1e4 * g]]], lr=lr, wd=0.0, eps=0.0)[0][0]
+    assert np.allclose(a, b, rtol=0, atol=1e-15)
+    assert np.allclose(a, p0 - lr * np.sign(g), rtol=0, atol=1e-15)
