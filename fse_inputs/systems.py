@@ -464,6 +464,65 @@ def synthetic_shell(NH=12, NL=24, Lx=2.0, Hy=1.0, thick=0.01, rho=2700.0,
                   t3_idx, t3_val, F)
 
 
+# --------------------------------------------------------------------------- banded test systems
+def banded_lumped_system(n=37, bw=20, seed=3, e=2, quad=0.3, cubic=1.0, zeta=0.02, windows=None) -> System:
+    """Seeded banded system with a lumped (diagonal) mass, for the wide-band kernels' tests.
+
+    K = diagonal + sum of random SPD blocks on windows of bw + 1 consecutive DOFs (half band
+    exactly bw); M = positive diagonal; D Rayleigh (ratio zeta at modes 1-2).  The polynomial
+    forces are gradients of potentials h/3 (g.q)^3 + c/4 (g.q)^4 with g supported on a window,
+    so the tangent is symmetric and inside the band.  Loads on DOFs 0 and n - 1.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = np.diag(np.linspace(2.0, 6.0, n))
+    starts = list(range(0, max(n - bw, 1), max(bw // 2, 1)))
+    for a in starts:
+        m = min(bw + 1, n - a)
+        G = rng.normal(size=(m, m))
+        K[a:a + m, a:a + m] += 0.3 * (G @ G.T) / m
+    K = 0.5 * (K + K.T)
+    M = np.diag(rng.uniform(0.5, 1.5, size=n))
+    alpha, beta = rayleigh_from_modes(M, K, zeta)
+    D = alpha * M + beta * K
+    d2, d3 = {}, {}
+    for a in (starts if windows is None else windows):
+        m = min(bw + 1, n - a)
+        g = np.zeros(n)
+        g[a:a + m] = rng.normal(size=m) / np.sqrt(m)
+        hm = quad * rng.uniform(0.5, 1.0)
+        cm = cubic * rng.uniform(0.5, 1.0)
+        idx = np.arange(a, a + m)
+        for i in idx:
+            for j in idx:
+                for k in idx:
+                    if k < j:
+                        continue
+                    mult = 1.0 if j == k else 2.0
+                    key = (int(i), int(j), int(k))
+                    d2[key] = d2.get(key, 0.0) + mult * hm * g[i] * g[j] * g[k]
+    for a in (starts if windows is None else windows)[:3]:
+        m = min(bw + 1, n - a)
+        g = np.zeros(n)
+        g[a:a + m] = rng.normal(size=m) / np.sqrt(m)
+        cm = cubic * rng.uniform(0.5, 1.0)
+        idx = np.arange(a, a + min(m, 8))
+        for i in idx:
+            for j in idx:
+                for k in idx:
+                    for l in idx:
+                        if not (j <= k <= l):
+                            continue
+                        cnt = len({(j, k, l), (j, l, k), (k, j, l), (k, l, j), (l, j, k), (l, k, j)})
+                        key = (int(i), int(j), int(k), int(l))
+                        d3[key] = d3.get(key, 0.0) + cnt * cm * g[i] * g[j] * g[k] * g[l]
+    t2_idx, t2_val, t3_idx, t3_val = _coo_from_dicts(d2, d3)
+    F = np.zeros((e, n))
+    F[0, 0] = 1.0
+    if e > 1:
+        F[1, n - 1] = 0.5
+    return System(f"banded_{n}_{bw}", M, D, K, t2_idx, t2_val, t3_idx, t3_val, F)
+
+
 # --------------------------------------------------------------------------- tiny systems
 def linear_oscillator(Omega=1.0, zeta=0.0, f=0.0, e=1) -> System:
     """Single DOF q'' + 2 zeta Omega q' + Omega^2 q = f cos(...)."""

@@ -173,7 +173,7 @@ def _solve(A, B):
 def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
               omega_sens: bool = False, tol: float = 1e-12, maxit: int = 30,
               q_scale: float = 0.0, history: bool = False, beta: float = 0.25, gamma: float = 0.5,
-              general: bool = False, steps: int = None, phi0: float = 0.0):
+              general: bool = False, steps: int = None, phi0: float = 0.0, sens_cols=None):
     """Integrate one trajectory from phi_1 = 0 to 2 pi in S1 Newmark steps.
 
     Returns dict with zT = [q; u](2 pi), Phi (2n x 2n) if sens, dz_domega
@@ -181,8 +181,13 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
     (beta, gamma) other than the average-acceleration (1/4, 1/2) of App. E, or general=True,
     take the general Newmark rule (integrate_general).  steps < S1 integrates that many
     steps of h = 2 pi / S1 from the section phi_1 = phi0 (a segment of multiple shooting).
+    sens_cols (average-acceleration rule): propagate only those columns of the sensitivities,
+    Phi[:, sens_cols] (2n x len), by the same recursion started from the same columns of
+    Q_0, U_0, A_0 (the recursion is linear and acts on every column on its own).
     """
     if general or beta != 0.25 or gamma != 0.5 or has_velocity(sysm):
+        if sens_cols is not None:
+            raise ValueError("sens_cols needs the average-acceleration rule")
         return integrate_general(sysm, omega, S1, phases, z0, sens=sens, omega_sens=omega_sens, tol=tol,
                                  maxit=maxit, q_scale=q_scale, history=history, beta=beta, gamma=gamma,
                                  steps=steps, phi0=phi0)
@@ -203,6 +208,9 @@ def integrate(sysm, omega, S1: int, phases, z0, sens: bool = False,
         Q = np.hstack([np.eye(n), np.zeros((n, n))])
         U = np.hstack([np.zeros((n, n)), np.eye(n)])
         A = -_solve(Mw, np.hstack([K + tangent(sysm, q), w1 * D]))
+        if sens_cols is not None:
+            cols = np.asarray(sens_cols, dtype=np.int64)
+            Q, U, A = Q[:, cols], U[:, cols], A[:, cols]
     ne = sysm.e
     if omega_sens:
         # d q0/d omega = d u0/d omega = 0; d a0/d omega_i from the consistency equation

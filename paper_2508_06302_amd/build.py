@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
-SOURCES = ["fse_api.hip", "k_traj.hip", "k_fused.hip", "k_wsens.hip", "k_krylov.hip", "k_hypertime.hip", "k_multiple.hip", "k_linalg.hip", "k_learned.hip"]
+SOURCES = ["fse_api.hip", "k_traj.hip", "k_fused.hip", "k_wide.hip", "k_wsens.hip", "k_krylov.hip", "k_hypertime.hip", "k_multiple.hip", "k_linalg.hip", "k_learned.hip"]
 LIB = os.path.join(HERE, "libfse.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

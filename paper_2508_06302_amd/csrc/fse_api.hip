@@ -136,7 +136,13 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   ctx->tol = desc->step_tol > 0 ? desc->step_tol : 1e-12;
   ctx->maxit = desc->step_maxit > 0 ? desc->step_maxit : 30;
   // FSE_KERNELS=fused|generic selects the trajectory kernels (tests cover both paths)
-  if (const char *kv = std::getenv("FSE_KERNELS")) ctx->use_fused = std::strcmp(kv, "generic") != 0;
+  // (fused where it applies, then the wide-band path, then generic; "wide" puts the wide-band
+  // path first wherever it applies, "generic" turns both off)
+  if (const char *kv = std::getenv("FSE_KERNELS")) {
+    ctx->use_fused = std::strcmp(kv, "generic") != 0;
+    ctx->use_wide = std::strcmp(kv, "generic") != 0;
+    ctx->wide_forced = std::strcmp(kv, "wide") == 0;
+  }
   // FSE_WSENS=generic keeps the omega_1 sensitivity on the generic replay kernel
   if (const char *kv = std::getenv("FSE_WSENS")) ctx->wsens_generic = std::strcmp(kv, "generic") == 0;
   if (const char *nc = std::getenv("FSE_FUSED_NCW")) {
@@ -352,6 +358,8 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
     }
   }
 
+  FSE_TRY(wide_prepare(ctx, Mb, Db, Kb, p2, jk, p3, jkl, ktp, kti));
+
   // ---- uploads
   FSE_TRY(upload(ctx, &ctx->Mb, Mb));
   FSE_TRY(upload(ctx, &ctx->Db, Db));
@@ -408,6 +416,7 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
 }
 
 void free_all(fse_ctx *ctx) {
+  wide_free(ctx);
   void *ptrs[] = {ctx->Mb, ctx->Db, ctx->Kb, ctx->F, ctx->f2_ptr, ctx->f2_jk, ctx->f2_v,
                   ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v, ctx->kt_ptr, ctx->kt_idx, ctx->kt_c,
                   ctx->G_d, ctx->Gi_d, ctx->sidx_d, ctx->Sdim_d, ctx->ktable_d, ctx->omega_d,
@@ -486,14 +495,20 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
   else
     FSE_TRY(launch_idft(ctx, B, Z0));
   FSE_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
-  const bool fused = fused_eligible(ctx);
-  if (!fused && Phi && ctx->prec == FSE_PREC_MIXED_FP32) {
-    ctx->err = "FP32 sensitivities need the fused kernel (half bandwidth <= 16, LDS fit)";
+  const bool wide = wide_eligible(ctx);
+  const bool fused = !wide && fused_eligible(ctx);
+  if (!fused && !wide && Phi && ctx->prec == FSE_PREC_MIXED_FP32) {
+    ctx->err = "FP32 sensitivities need the fused kernel (half bandwidth <= 16, LDS fit) or the wide-band "
+               "path (lumped mass, half bandwidth <= 96, average acceleration, no contacts)";
     return FSE_E_UNSUPPORTED;
   }
   if (fused) {
     FSE_TRY(launch_fused(ctx, B, Phi));
     FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
+  } else if (wide) {
+    FSE_TRY(launch_wide_state(ctx, B));
+    FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
+    if (Phi) FSE_TRY(launch_wide_sens(ctx, B, Phi));
   } else {
     FSE_TRY(launch_state(ctx, B));
     FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));

@@ -154,6 +154,11 @@ struct fse_ctx {
   size_t fused_band_elems = 0;
   bool use_fused = true;
 
+  // wide-band trajectory path (k_wide.hip): half bandwidths above the fused kernel's, lumped mass
+  struct WideState *wide = nullptr;
+  bool wide_forced = false;         // FSE_KERNELS=wide: take the wide path wherever it applies
+  bool use_wide = true;             // FSE_KERNELS=generic turns it off
+
   // tuning
   int sens_cols = 64;               // columns per sensitivity work-group (generic kernel)
   int fused_ncw = 2;                // column waves per fused work-group
@@ -210,6 +215,21 @@ int fused_band_bucket(const fse_ctx *ctx);
 // omega_1 sensitivity with the fused kernel's per-point bands (after a fused integration,
 // k_wsens.hip); FSE_E_UNSUPPORTED when the generic replay must be used
 fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT);
+// Wide-band trajectory path (k_wide.hip): batched shared-S chord iteration for the states,
+// per-trajectory banded LDL^T and MFMA block sweeps for the sensitivities.  wide_prepare is
+// called by fse_init_torus with the full-row bands [n][2bw+1] of M, D, K, the f_nl rows (CSR by
+// output index) and the tangent contribution lists (host); it keeps nothing when the system
+// does not qualify (mass not diagonal, half bandwidth above 96, velocity-dependent forces, or
+// staged rows beyond LDS).
+fse_status wide_prepare(fse_ctx *ctx, const std::vector<double> &Mb, const std::vector<double> &Db,
+                        const std::vector<double> &Kb, const std::vector<int32_t> &p2,
+                        const std::vector<int32_t> &jk, const std::vector<int32_t> &p3,
+                        const std::vector<int32_t> &jkl, const std::vector<int32_t> &ktp,
+                        const std::vector<int32_t> &kti);
+bool wide_eligible(const fse_ctx *ctx);
+fse_status launch_wide_state(fse_ctx *ctx, int B);
+fse_status launch_wide_sens(fse_ctx *ctx, int B, double *Phi);
+void wide_free(fse_ctx *ctx);
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // the two halves of dense_lu_solve: factor A (row-major N x N, in place, pivots piv[N]), then

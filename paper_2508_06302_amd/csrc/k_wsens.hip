@@ -220,7 +220,8 @@ fse_status launch_wsens_bw(fse_ctx *ctx, const TrajParams &P, double *dzT) {
 }  // namespace
 
 fse_status launch_wsens_fused(fse_ctx *ctx, int B, double *dzT) {
-  if (!fused_eligible(ctx)) return FSE_E_UNSUPPORTED;
+  // the per-point bands it reads are those of the fused integration
+  if (!fused_eligible(ctx) || wide_eligible(ctx)) return FSE_E_UNSUPPORTED;
   const int BWb = fused_band_bucket(ctx);
   const size_t fb = (size_t)(ctx->n + BWb) * (BWb + 1);
   // the per-step factors of every trajectory are held at once: stay within 8 GiB, and the

@@ -418,12 +418,16 @@ def test_autotuner_times_both_configs_and_they_agree(monkeypatch):
     assert np.array_equal(phi.cpu().numpy(), outs[0][1].cpu().numpy())
 
 
-def test_wide_band_shell_generic_kernels():
+@pytest.mark.parametrize("kernels", ["generic", "default"])
+def test_wide_band_shell(kernels, monkeypatch):
     """A 360-DOF shell-like system (half bandwidth 47, 39k quadratic and 93k cubic force
-    terms) goes through the generic kernels with their global-memory factor scratch:
-    sampled trajectories against the oracle; the FP32-sensitivity path, which needs the
-    fused kernel, reports FSE_E_UNSUPPORTED."""
+    terms): by default it takes the wide-band path (lumped mass), with FSE_KERNELS=generic the
+    generic kernels with their global-memory factor scratch; sampled trajectories against the
+    oracle either way.  The FP32-sensitivity mode runs on the wide-band path (Phi within 1e-4)
+    and is refused by the generic kernels (FSE_E_UNSUPPORTED)."""
     from fse_inputs.systems import synthetic_shell
+    if kernels == "generic":
+        monkeypatch.setenv("FSE_KERNELS", "generic")
     m = fse()
     s = synthetic_shell(NH=5, NL=10)
     w1 = 0.98 * 628.31853072
@@ -434,7 +438,7 @@ def test_wide_band_shell_generic_kernels():
     ctx = m.fse_init_torus(s, tr)
     U, St, bw, kt = m.fse_get_layout(ctx)
     assert bw == 47
-    log("wide-band shell: gpu integrate with sensitivities")
+    log(f"wide-band shell ({kernels}): gpu integrate with sensitivities")
     zT, phi = m.fse_integrate_batch(ctx, om[None], Z0[None], want_phi=True)
     samples = [0, 5]
     log("wide-band shell: oracle samples")
@@ -443,5 +447,10 @@ def test_wide_band_shell_generic_kernels():
         assert rel(zT[0][:, s_].cpu().numpy(), ref["zbarT"][:, s_]) < RTOL, s_
         assert rel(phi[0, s_].cpu().numpy(), ref["Phi"][s_]) < 1e-9, s_
     cm = m.fse_init_torus(s, tr, precision=m.FSE_PREC_MIXED_FP32)
-    with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
-        m.fse_integrate_batch(cm, om[None], Z0[None], want_phi=True)
+    if kernels == "generic":
+        with pytest.raises(m.FseError, match="FSE_E_UNSUPPORTED"):
+            m.fse_integrate_batch(cm, om[None], Z0[None], want_phi=True)
+    else:
+        _, phm = m.fse_integrate_batch(cm, om[None], Z0[None], want_phi=True)
+        for s_ in samples:
+            assert rel(phm[0, s_].cpu().numpy(), ref["Phi"][s_]) < 1e-4, s_

@@ -205,3 +205,17 @@ def test_general_rule_sensitivities_match_finite_differences(beta, gamma):
         zp = newmark.integrate(s, omega + e, 48, phases, z0, beta=beta, gamma=gamma)["zT"]
         zm = newmark.integrate(s, omega - e, 48, phases, z0, beta=beta, gamma=gamma)["zT"]
         assert np.allclose(out["dz_domega"][:, i], (zp - zm) / (2 * hh), rtol=1e-6, atol=1e-7)
+
+
+def test_sensitivity_column_subset_equals_the_full_columns():
+    """sens_cols propagates chosen columns of Phi by the same recursion: they equal those
+    columns of the full Phi (which central differences pin), in any order and with repeats."""
+    from fse_inputs import tiny_system
+    s = tiny_system(n=4, seed=5, cubic=1.0, quad=0.3, e=2)
+    om = np.array([0.9, 0.9 * 1.618])
+    z0 = 0.3 * np.random.default_rng(9).normal(size=8)
+    full = newmark.integrate(s, om, 40, np.array([0.7]), z0, sens=True)["Phi"]
+    cols = [7, 0, 3, 3, 5]
+    sub = newmark.integrate(s, om, 40, np.array([0.7]), z0, sens=True, sens_cols=cols)["Phi"]
+    assert sub.shape == (8, len(cols))
+    assert np.allclose(sub, full[:, cols], rtol=1e-13, atol=1e-14)
