@@ -1,18 +1,21 @@
 """Benchmark of the FSE-Shooting hot path on one MI355X.
 
-One step = one pass of the hot path over the von Karman beam workload
-(147 DOF, d = 2, 64 trajectories, H = 15, S1 = 512, full sensitivities):
-inverse DFT, consistent a_0 / Phi_0, Newmark integration with per-step Newton,
-sensitivity propagation, DFT + rotation + residual, and the Jacobian of Eq. (22).
-value = trajectory-steps/s = S~ * S1 / (time per step).
+Headline workload: the 1872-DOF synthetic shell (12 x 24 triangle mesh, 6 DOF per node, half band
+89, lumped mass), d = 2, 128 trajectories on the 1-torus, H = 20 (U = 41), S1 = 1024 Newmark steps,
+full sensitivities (3744 columns per trajectory), plain FP64.  One step = one pass of the hot path
+for one continuation point: inverse DFT, consistent a_0 and the sensitivity seeds, the batched
+Newmark integration with the per-step chord iteration, the sensitivity propagation, DFT +
+rotation + residual, and one matrix-free Jacobian product J v from the stored sensitivities.
+value = trajectory-steps/s = S~ * S1 / (time per step), inputs resident in HBM.
 
-Prints ONE JSON line.  Extra fields: the roofline of the dominant kernel (the
-fused trajectory kernel: state integration + sensitivity propagation), the FP64
-oracle timed on the host cores on a bounded sample, and the shooting solve time to
-||R|| < 1e-8 (measured outside the timed region).
+Prints ONE JSON line.  Besides the headline: the roofline of the dominant kernel (the wide-band
+sensitivity sweep), the mixed-precision throughput of the same workload, the 147-DOF beam
+(throughput, roofline of the fused kernel, shooting solve and arclength continuation times in
+both precisions), the three-frequency beam with 8 continuation points in one launch and its
+Newton-Krylov solve, and the FP64 oracle timed on the host cores on a bounded sample.
 
 `--calibrate-copy` instead times a plain device-to-device copy of known size; its
-FETCH_SIZE / WRITE_SIZE counters scale the counters of the fused kernel to bytes.
+FETCH_SIZE / WRITE_SIZE counters scale the counters of the profiled kernels to bytes.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -29,34 +33,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3
 ARC_POINTS = 10
 ARC_DS = 0.5
+CSRC = os.path.join(ROOT, "paper_2508_06302_amd", "csrc")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-krylov", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_fused_c2_traffic.json"))
+    ap.add_argument("--no-beam", action="store_true", help="skip the 147-DOF beam fields")
+    ap.add_argument("--no-c4", action="store_true", help="skip the three-frequency beam fields")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--shell-solve", action="store_true",
+                    help="also time the shell's Newton-Krylov solve in both precisions (minutes)")
     ap.add_argument("--calibrate-copy", action="store_true")
     return ap.parse_args()
 
 
-FUSED_SRC = [os.path.join(ROOT, "paper_2508_06302_amd", "csrc", f) for f in ("k_fused.hip", "band_ldlt.h")]
-
-
-def fused_source_hash():
-    """Hash of the sources the fused kernel is compiled from (counters taken on other
-    sources are not used)."""
+def source_hash(files):
     h = hashlib.sha256()
-    for f in FUSED_SRC:
-        h.update(open(f, "rb").read())
+    for f in files:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def read_traffic(name, files):
+    """HBM bytes per launch of a profiled kernel from its counter summary, or None when absent or
+    taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("source_sha256_16") != source_hash(files):
+        return None
+    return t.get("bytes_per_launch")
 
 
 def calibrate_copy():
@@ -75,95 +94,173 @@ def calibrate_copy():
                       "GBps_read_plus_write": 2 * nbytes / el / 1e9}), flush=True)
 
 
-def read_traffic(path):
-    """HBM bytes per launch of the fused kernel from counter runs, or None when absent or
-    taken on a different kernel source."""
-    if not os.path.exists(path):
-        return None
-    try:
-        t = json.load(open(path))
-    except Exception:
-        return None
-    if t.get("k_fused_source_sha256_16") != fused_source_hash():
-        return None
-    return t.get("bytes_per_launch")
-
-
-def cpu_baseline(wl, Z0, tables, budget_s=20.0):
-    """The oracle as it stands on a bounded sample: whole trajectories with sensitivities."""
-    from oracle import shooting as osh
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    done = 0
-    t0 = time.perf_counter()
-    s = 0
-    while time.perf_counter() - t0 < budget_s and s < tables.Stilde:
-        osh.evaluate(wl.system, wl.torus, wl.omega, Z0, sens=True, tables=tables, samples=[s])
-        done += 1
-        s += 1
-    el = time.perf_counter() - t0
-    return {"value": done * wl.torus.S1 / el, "unit": "trajectory-steps/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{done} of {tables.Stilde} trajectories of the same workload, each the "
-                      f"full {wl.torus.S1}-step integration with sensitivities, {el:.1f} s"}
-
-
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(fse, torch, wl, prec, steps, warmup, solve):
-    """Throughput of the residual + Jacobian step and the continuation solve in one
-    precision mode; returns a dict (kernel times from HIP events on the library stream)."""
-    progress(f"precision {prec}: {warmup} warmup + {steps} timed steps")
+# ----------------------------------------------------------------------------- host baseline
+_ORACLE_INPUT = None
+
+
+def _oracle_init(payload):
+    """Pool initializer: the shell's inputs, built once by the parent."""
+    global _ORACLE_INPUT
+    _ORACLE_INPUT = payload
+
+
+def _oracle_steps(args):
+    """One worker of the host baseline: the oracle integrates `steps` Newmark steps of trajectory
+    s with all sensitivity columns, on one BLAS thread; returns (steps done, seconds)."""
+    s, steps = args
+    from threadpoolctl import threadpool_limits
+    from oracle import newmark
+    sysm, omega, S1, phases, zbar0 = _ORACLE_INPUT
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        newmark.integrate(sysm, omega, S1, phases[:, s], zbar0[:, s], sens=True, steps=steps)
+        return steps, time.perf_counter() - t0
+
+
+def cpu_baseline(steps_per_worker=1):
+    """The oracle as it stands, on the host cores: trajectories of the same shell workload with all
+    sensitivity columns, the first `steps_per_worker` Newmark steps each (a whole trajectory takes
+    minutes), one process per trajectory with one BLAS thread each, at 1 worker and at as many
+    workers as the host share has cores (at most 16).  value = trajectory-steps/s at that count."""
+    from multiprocessing import get_context
+    from fse_inputs import workload
+    from oracle import shooting
+    cpus = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(16, cpus))
+    try:
+        model = [l.split(":", 1)[1].strip() for l in subprocess.run(["lscpu"], capture_output=True, text=True)
+                 .stdout.splitlines() if l.startswith("Model name")][0]
+    except Exception:
+        model = "unknown"
+    wl = workload("C3")
+    tb = shooting.TorusTables(wl.torus)
+    n = wl.system.n
+    zbar0 = wl.initial_iterate(tb.table).reshape(2 * n, tb.U) @ tb.G.T
+    payload = (wl.system, wl.omega, wl.torus.S1, tb.phases, zbar0)
+    out = {}
+    ctx = get_context("spawn")
+    for nw in sorted({1, workers}):
+        progress(f"oracle: starting {nw} worker(s)")
+        with ctx.Pool(nw, initializer=_oracle_init, initargs=(payload,)) as pool:
+            pool.map(_oracle_steps, [(0, 1)] * nw)          # imports and first touch outside the clock
+            t0 = time.perf_counter()
+            res = pool.map(_oracle_steps, [(s * 7 % 128, steps_per_worker) for s in range(nw)])
+            el = time.perf_counter() - t0
+        out[nw] = (sum(r[0] for r in res) / el, el)
+        progress(f"oracle: {nw} worker(s), {out[nw][0]:.3f} trajectory-steps/s")
+    v, el = out[workers]
+    return {"value": v, "unit": "trajectory-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{workers} trajectories of the shell workload, the first {steps_per_worker} Newmark step(s) "
+                      f"each with all 3744 sensitivity columns, one process per trajectory on one BLAS thread "
+                      f"({el:.1f} s wall)",
+            "one_core": {"value": out[1][0], "wall_s": out[1][1]},
+            "host": {"cpu_model": model, "cpus_available": cpus}}
+
+
+# ----------------------------------------------------------------------------- shell (headline)
+def sweep_flops_per_traj_step(sysm, bw):
+    """Algorithmic FP64 work of one sensitivity step of one trajectory on the wide-band path: the
+    right-hand side w1^2 M P2 + w1 D P1 (lumped M, sparse D), forward and backward substitution with
+    the banded unit lower factor, the pivot scaling and the updates of P1, P2 (5 flops per entry)."""
+    n = sysm.n
+    nnzD = int(np.count_nonzero(sysm.D))
+    nnzL = n * bw - bw * (bw + 1) // 2
+    return 2 * n * (2 * n + 2 * nnzD + 4 * nnzL + n + 5 * n)
+
+
+def run_shell(fse, torch, prec, steps, warmup):
+    from fse_inputs import workload
+    wl = workload("C3")
+    progress(f"shell: init (precision {prec})")
+    ctx = fse.fse_init_torus(wl.system, wl.torus, precision=prec)
+    U, St, bw, kt = fse.fse_get_layout(ctx)
+    Z0 = torch.tensor(wl.initial_iterate(kt), dtype=torch.float64, device="cuda")
+    v = torch.randn_like(Z0)
+
+    def step():
+        R, rn = fse.fse_shooting_residual_matfree(ctx, wl.omega, Z0)
+        Jv = fse.fse_jacobian_apply(ctx, v)
+        return rn, Jv
+
+    for i in range(warmup):
+        step()
+        progress(f"shell: warmup {i + 1}/{warmup}")
+    torch.cuda.synchronize()
+    kms, kl, st = [], [], []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        rn, _ = step()
+        path, ms, nl = fse.fse_last_kernel_timing(ctx)
+        kms.append(ms)
+        kl.append(nl)
+        st.append(fse.fse_last_timing(ctx)["state_ms"])
+        progress(f"shell: step {i + 1}/{steps} |R| {rn:.3e}")
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    mx, tot = fse.fse_step_stats(ctx)
+    return {"ctx": ctx, "wl": wl, "Z0": Z0, "U": U, "St": St, "bw": bw, "path": path,
+            "s_per_step": el, "value": St * wl.torus.S1 / el, "rnorm": rn,
+            "sweep_ms_per_launch": float(np.mean(kms)) / float(np.mean(kl)) if np.mean(kl) > 0 else None,
+            "sweep_launches": int(np.mean(kl)), "state_ms": float(np.mean(st)),
+            "chord_iterations": {"max_per_step": mx, "mean_per_step": tot / (St * wl.torus.S1)}}
+
+
+def shell_solve(fse, torch, wl, prec):
+    """Newton-Krylov solve of the shell from its linear harmonic start to ||R||_2 < 1e-8."""
+    ctx = fse.fse_init_torus(wl.system, wl.torus, precision=prec)
+    U, St, bw, kt = fse.fse_get_layout(ctx)
+    Z = torch.tensor(wl.initial_iterate(kt), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, gits = [], []
+    for _ in range(8):
+        rn, its, _ = fse.fse_newton_krylov_step(ctx, wl.omega, Z, rtol=1e-6, restart=30, maxit=300)
+        hist.append(rn)
+        gits.append(its)
+        progress(f"shell solve (precision {prec}): |R| {rn:.3e}")
+        if rn < 1e-8:
+            break
+    torch.cuda.synchronize()
+    R, rn = fse.fse_shooting_residual_matfree(ctx, wl.omega, Z)
+    return {"time_s": time.perf_counter() - t0, "newton_residuals": [float(h) for h in hist] + [float(rn)],
+            "gmres_iterations": [int(g) for g in gits], "converged": bool(rn < 1e-8)}, Z
+
+
+# ----------------------------------------------------------------------------- 147-DOF beam
+def run_beam(fse, torch, prec, steps, warmup, solve):
+    """Throughput of the residual + dense Jacobian step on the 147-DOF beam and its solves."""
+    from fse_inputs import workload
+    wl = workload("C2")
     tr = wl.torus
     ctx = fse.fse_init_torus(wl.system, tr, precision=prec)
     U, St, bw, kt = fse.fse_get_layout(ctx)
     Z0 = wl.initial_iterate(kt)
     om = wl.omega[None]
     Zd = torch.tensor(Z0[None], dtype=torch.float64, device="cuda")
-
-    def step():
-        return fse.fse_shooting_residual_jacobian(ctx, om, Zd, want_J=True)
-
+    step = lambda: fse.fse_shooting_residual_jacobian(ctx, om, Zd, want_J=True)
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    kern_ms = []
+    kern = []
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
-        tm = fse.fse_last_timing(ctx)          # HIP events around the launch, on its stream
-        kern_ms.append(tm["state_ms"] + tm["sens_ms"])
+        kern.append(fse.fse_last_kernel_timing(ctx)[1])
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ncw, tune_ms = fse.fse_get_tuning(ctx)
-    res = {"ctx": ctx, "U": U, "St": St, "bw": bw, "Z0": Z0, "ms_per_step": 1e3 * el / steps,
-           "tuning": {"column_waves_per_workgroup": ncw, "tuned_launch_ms": [float(x) for x in tune_ms]},
-           "value": St * tr.S1 / (el / steps), "kernel_ms": float(np.mean(kern_ms)),
-           "fused": tm["sens_launches"] == 1 and tm["sens_ms"] < 0.05 * tm["state_ms"]}
-    progress(f"precision {prec}: {res['ms_per_step']:.1f} ms per step")
-    if prec == fse.FSE_PREC_FP64:
-        # the trajectories alone (states, no sensitivities): same workload and step count
-        for _ in range(warmup):
-            fse.fse_integrate_batch(ctx, om, Zd)
-        torch.cuda.synchronize()
-        st_ms = []
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            fse.fse_integrate_batch(ctx, om, Zd)
-            st_ms.append(fse.fse_last_timing(ctx)["state_ms"])
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        res["state_only"] = {"value": St * tr.S1 / (el / steps), "unit": "trajectory-steps/s",
-                             "ms_per_step": 1e3 * el / steps, "kernel_ms_per_launch": float(np.mean(st_ms))}
-        progress(f"precision {prec}: state only {res['state_only']['ms_per_step']:.1f} ms per step")
+    el = (time.perf_counter() - t0) / steps
+    n = wl.system.n
+    alg = 6 * n * (2 * n) * 8 * St * tr.S1
+    kms = float(np.mean(kern))
+    res = {"value": St * tr.S1 / el, "ms_per_step": 1e3 * el, "kernel_ms_per_launch": kms,
+           "roofline": {"bound": "hbm", "achieved": alg / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "kernel": "k_fused", "algorithmic_bytes_per_launch": alg}}
+    progress(f"beam (precision {prec}): {res['ms_per_step']:.1f} ms per step")
     if solve:
-        # shooting solve: natural-parameter continuation in the forcing amplitude
-        # f1 = f2 = 0.1 ... 0.5 N at the same omega, secant predictor, ||R||_2 < 1e-8 per point
         amps = [0.1, 0.2, 0.3, 0.4, 0.5]
         params = np.array([[*wl.omega, a, a] for a in amps])
         torch.cuda.synchronize()
@@ -174,33 +271,66 @@ def run_precision(fse, torch, wl, prec, steps, warmup, solve):
         except fse.FseError as ex:
             Zs, its, rns, ok = ex.Z, ex.iters, ex.rnorm, str(ex)
         torch.cuda.synchronize()
-        res["solve"] = {"time_s": time.perf_counter() - t1,
-                        "newton_iterations": [int(i) for i in its],
+        res["solve"] = {"time_s": time.perf_counter() - t1, "newton_iterations": [int(i) for i in its],
                         "final_residuals": [float(r) for r in rns], "converged": ok is True}
         res["Z_solution"] = Zs[-1].clone() if ok is True else None
-        progress(f"precision {prec}: amplitude continuation {res['solve']['time_s']:.1f} s")
         if ok is True:
-            # pseudo-arclength continuation in omega_1 (tangent predictor, orthogonal
-            # corrector) from the 0.3 N torus: ARC_POINTS points, step ARC_DS in the 2-norm of
-            # [Z(0); omega_1], ||R||_2 < 1e-8 per point
             fse.fse_set_forcing(ctx, [amps[2]] * wl.system.e)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             try:
-                _, oms, steps, cits, crn = fse.fse_arclength(ctx, wl.omega, Zs[2], ARC_DS, ARC_POINTS,
-                                                             tol=1e-8, maxit=8)
+                _, oms, _, cits, crn = fse.fse_arclength(ctx, wl.omega, Zs[2], ARC_DS, ARC_POINTS, tol=1e-8, maxit=8)
                 aok = True
             except fse.FseError as ex:
-                oms, steps, cits, crn, aok = ex.omega, ex.steps, ex.iters, ex.rnorm, str(ex)
+                oms, cits, crn, aok = ex.omega, ex.iters, ex.rnorm, str(ex)
             torch.cuda.synchronize()
             el2 = time.perf_counter() - t2
-            progress(f"precision {prec}: arclength {el2:.1f} s")
-            res["arclength"] = {"time_s": el2, "points": ARC_POINTS, "s_per_point": el2 / ARC_POINTS,
-                                "corrections": [int(i) for i in cits],
-                                "omega1": [float(o[0]) for o in oms], "final_residuals": [float(r) for r in crn],
-                                "converged": aok is True}
-        fse.fse_set_forcing(ctx, [1.0] * wl.system.e)
+            res["arclength"] = {"time_s": el2, "points": ARC_POINTS, "corrections": [int(i) for i in cits],
+                                "omega1": [float(o[0]) for o in oms], "converged": aok is True}
+        progress(f"beam (precision {prec}): solves done")
     return res
+
+
+# ----------------------------------------------------------------------------- 3-frequency beam
+def run_c4(fse, torch, steps, warmup, solve):
+    """Eight continuation points (omega_1 from 36.5 to 40.0 rad/s, below the first resonance at
+    44.55 rad/s where the 1 N linear start stays within the step Newton's reach) of the
+    three-frequency beam in one launch: 8 x 1024 trajectories of 512 steps with full sensitivities."""
+    from fse_inputs import workload
+    w1s = np.linspace(36.5, 40.0, 8)
+    wls = [workload("C4", omega1=float(w)) for w in w1s]
+    tr = wls[0].torus
+    ctx = fse.fse_init_torus(wls[0].system, tr, max_batch=8)
+    U, St, bw, kt = fse.fse_get_layout(ctx)
+    om = np.stack([w.omega for w in wls])
+    Zs = np.stack([w.initial_iterate(kt) for w in wls])
+    for _ in range(warmup):
+        fse.fse_integrate_batch(ctx, om, Zs, want_phi=True)
+    torch.cuda.synchronize()
+    kern = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fse.fse_integrate_batch(ctx, om, Zs, want_phi=True)
+        kern.append(fse.fse_last_kernel_timing(ctx)[1])
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    n = wls[0].system.n
+    W = 8 * St
+    alg = 6 * n * (2 * n) * 8 * W * tr.S1
+    kms = float(np.mean(kern))
+    out = {"workload": "von Karman beam, 147 DOF, d=3 (omega_1 (1, sqrt2, sqrt3)), 32x32 trajectories, H=8x8 "
+                       f"(U={U}), S1=512, 8 continuation points omega_1 = 36.5..40.0 rad/s in one launch, "
+                       "full sensitivities, FP64",
+           "value": W * tr.S1 / el, "unit": "trajectory-steps/s", "s_per_launch": el, "kernel_ms_per_launch": kms,
+           "roofline": {"bound": "hbm", "achieved": alg / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, "kernel": "k_fused",
+                        "algorithmic_bytes_per_launch": alg}}
+    progress(f"three-frequency beam, 8 points: {el:.2f} s per launch")
+    del ctx
+    torch.cuda.empty_cache()
+    if solve:
+        out["krylov_solve"] = krylov_solve(fse, torch)
+    return out
 
 
 def krylov_solve(fse, torch, amp=0.1):
@@ -212,7 +342,6 @@ def krylov_solve(fse, torch, amp=0.1):
     U, St, bw, kt = fse.fse_get_layout(ctx)
     fse.fse_set_forcing(ctx, [amp] * wl.system.e)
     Z = torch.tensor(wl.initial_iterate(kt) * amp, dtype=torch.float64, device="cuda")
-    progress("three-frequency beam: Newton-Krylov")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist, gits = [], []
@@ -224,12 +353,10 @@ def krylov_solve(fse, torch, amp=0.1):
             break
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    progress(f"three-frequency beam: {len(hist)} Newton steps, {el:.1f} s")
-    return {"workload": "von Karman beam, 147 DOF, d=3 (omega_1 (1, sqrt2, sqrt3)), 32x32 trajectories, "
-                        f"H=8x8 (U={U}), S1=512, forcing {amp} N, from the linear response",
-            "unknowns": int(2 * wl.system.n * U), "time_s": el,
-            "newton_residuals": [float(h) for h in hist], "gmres_iterations": [int(g) for g in gits],
-            "converged": bool(hist[-1] < 1e-8), "gmres": "restart 30, rtol 1e-8, harmonic-block preconditioner"}
+    progress(f"three-frequency beam Newton-Krylov: {len(hist)} steps, {el:.1f} s")
+    return {"point": "omega_1 = 40 rad/s, forcing 0.1 N, from the linear response", "unknowns": int(2 * wl.system.n * U),
+            "time_s": el, "newton_residuals": [float(h) for h in hist], "gmres_iterations": [int(g) for g in gits],
+            "converged": bool(hist[-1] < 1e-8)}
 
 
 def main():
@@ -239,71 +366,90 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard trajectories or sensitivity columns across GPUs)",
-              file=sys.stderr)
+              "(the path would shard trajectories or sensitivity columns across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
 
     import paper_2508_06302_amd as fse
-    from fse_inputs import workload
     torch.cuda.set_device(0)
-    wl = workload("C2")
-    tr = wl.torus
-    solve = not args.no_solve
-    plain = run_precision(fse, torch, wl, fse.FSE_PREC_FP64, args.steps, args.warmup, solve)
-    mixed = None if args.no_mixed else run_precision(fse, torch, wl, fse.FSE_PREC_MIXED_FP32, args.steps,
-                                                     args.warmup, solve)
-    U, St, bw, Z0 = plain["U"], plain["St"], plain["bw"], plain["Z0"]
-    n = wl.system.n
-    traj_steps = St * tr.S1
-    bytes_per_traj_step = 6 * n * (2 * n) * 8          # read + write Q, U, A (FP64)
-    alg_bytes = bytes_per_traj_step * traj_steps
-    achieved = alg_bytes / (plain["kernel_ms"] * 1e-3) / 1e9
-    traffic = read_traffic(args.traffic)
+    sh = run_shell(fse, torch, fse.FSE_PREC_FP64, args.steps, args.warmup)
+    wl, St, bw = sh["wl"], sh["St"], sh["bw"]
+    n, S1 = wl.system.n, wl.torus.S1
+    fl_ts = sweep_flops_per_traj_step(wl.system, bw)
+    flops_launch = fl_ts * St
+    achieved = flops_launch / (sh["sweep_ms_per_launch"] * 1e-3) / 1e12
+    traffic = read_traffic("k_wide_sweep_shell_traffic.json", ["k_wide.hip"])
     out = {
         "metric": "trajectory-steps/s and shooting solve time @||R||<1e-8, mixed vs plain FP64",
-        "value": plain["value"], "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": plain["ms_per_step"], "higher_is_better": True,
+        "value": sh["value"], "unit": "trajectory-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * sh["s_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "von Karman clamped-clamped beam, 50 elements (147 DOF), d=2, "
-                               "64 trajectories, H=15 (U=31), S1=512, full sensitivities, "
-                               "plain FP64, one continuation point; one step = residual and "
-                               "Jacobian of the shooting problem",
-                   "n": n, "Stilde": St, "U": U, "S1": tr.S1, "half_band": bw},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused (state + sensitivities)" if plain["fused"] else "k_state + k_sens",
-                     "kernel_ms_per_launch": plain["kernel_ms"],
-                     "algorithmic_bytes_per_launch": alg_bytes},
-        "autotuner": plain["tuning"],
-        "state_only": plain["state_only"],
+        "config": {"workload": "synthetic shell, 12 x 24 triangle mesh, 6 DOF per node (1872 DOF, half band 89, "
+                               "lumped mass), d=2, 128 trajectories, H=20 (U=41), S1=1024, full sensitivities "
+                               "(3744 columns per trajectory), plain FP64, one continuation point; one step = "
+                               "residual with sensitivities and one matrix-free Jacobian product",
+                   "n": n, "Stilde": St, "U": sh["U"], "S1": S1, "half_band": bw},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFS, "traffic": traffic,
+                     "kernel": "k_wide_sweep (FP64 matrix cores; one launch per Newmark step)",
+                     "kernel_ms_per_launch": sh["sweep_ms_per_launch"], "launches_per_step": sh["sweep_launches"],
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "algorithmic_bytes_per_launch": 4 * n * (2 * n) * 8 * St},
+        "state_chain_ms": sh["state_ms"], "chord_iterations": sh["chord_iterations"],
+        "residual_norm_at_start": sh["rnorm"],
     }
-    if mixed is not None:
-        out["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
-                        "kernel_ms_per_launch": mixed["kernel_ms"],
-                        "dtype": "f64 arithmetic, f32 sensitivity storage"}
-    if solve:
-        path = "forcing amplitude 0.1 -> 0.5 N in 5 points from the linear response at 0.1 N, secant predictor"
-        out["shooting_solve"] = {"path": path, "fp64": plain["solve"]}
-        if "arclength" in plain:
-            out["arclength_continuation"] = {
-                "path": f"omega_1 from {wl.omega[0]:g} rad/s at 0.3 N, {ARC_POINTS} points, step {ARC_DS} "
-                        "(2-norm of [Z(0); omega_1]), tangent predictor and orthogonal corrector",
-                "fp64": plain["arclength"]}
-            if mixed is not None and "arclength" in mixed:
-                out["arclength_continuation"]["mixed"] = mixed["arclength"]
-        if mixed is not None:
-            out["shooting_solve"]["mixed"] = mixed["solve"]
-            zp, zm = plain.get("Z_solution"), mixed.get("Z_solution")
+    del sh["ctx"]
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        mx = run_shell(fse, torch, fse.FSE_PREC_MIXED_FP32, max(1, args.steps // 2), args.warmup)
+        out["mixed"] = {"value": mx["value"], "ms_per_step": 1e3 * mx["s_per_step"],
+                        "speedup_vs_fp64": mx["value"] / sh["value"],
+                        "sweep_ms_per_launch": mx["sweep_ms_per_launch"],
+                        "sweep_frac_of_fp32_peak": fl_ts * St / (mx["sweep_ms_per_launch"] * 1e-3) / 1e12 / FP32_PEAK_TFS,
+                        "dtype": "FP32 factor, FP32 matrix-core sweeps and FP32 sensitivity storage; FP64 states "
+                                 "and residuals"}
+        del mx["ctx"]
+        torch.cuda.empty_cache()
+    if args.shell_solve:
+        s64, Z64 = shell_solve(fse, torch, wl, fse.FSE_PREC_FP64)
+        s32, Z32 = shell_solve(fse, torch, wl, fse.FSE_PREC_MIXED_FP32)
+        out["shell_solve"] = {"fp64": s64, "mixed": s32,
+                              "mixed_vs_fp64_torus_rel_diff": float((Z32 - Z64).norm() / Z64.norm())}
+    def guarded(name, fn):
+        """Secondary fields: a failure is recorded in the line instead of losing it."""
+        try:
+            fn()
+        except Exception as ex:  # noqa: BLE001
+            out[name] = {"error": f"{type(ex).__name__}: {ex}"}
+            progress(f"{name} failed: {ex}")
+
+    def beam_fields():
+        b64 = run_beam(fse, torch, fse.FSE_PREC_FP64, 5, 1, not args.no_solve)
+        beam = {"workload": "von Karman clamped-clamped beam, 50 elements (147 DOF), d=2, 64 trajectories, H=15 "
+                            "(U=31), S1=512, full sensitivities; step = residual and dense Jacobian",
+                "fp64": {k: v for k, v in b64.items() if k not in ("Z_solution",)}}
+        if not args.no_mixed:
+            b32 = run_beam(fse, torch, fse.FSE_PREC_MIXED_FP32, 5, 1, not args.no_solve)
+            beam["mixed"] = {k: v for k, v in b32.items() if k not in ("Z_solution",)}
+            zp, zm = b64.get("Z_solution"), b32.get("Z_solution")
             if zp is not None and zm is not None:
-                out["shooting_solve"]["mixed_vs_fp64_torus_rel_diff"] = float((zm - zp).norm() / zp.norm())
-    if solve and not args.no_krylov:
-        out["krylov_solve"] = krylov_solve(fse, torch)
-    if not args.no_cpu_baseline:
-        from oracle import shooting as osh
-        tb = osh.TorusTables(tr)
+                beam["mixed_vs_fp64_torus_rel_diff"] = float((zm - zp).norm() / zp.norm())
+        out["beam"] = beam
+        torch.cuda.empty_cache()
+
+    def c4_fields():
+        out["three_frequency_beam"] = run_c4(fse, torch, 1, 1, not args.no_solve)
+
+    def cpu_fields():
         progress("oracle on the host cores (bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(wl, Z0, tb)
+        out["cpu_baseline"] = cpu_baseline()
+
+    if not args.no_beam:
+        guarded("beam", beam_fields)
+    if not args.no_c4:
+        guarded("three_frequency_beam", c4_fields)
+    if not args.no_cpu_baseline:
+        guarded("cpu_baseline", cpu_fields)
     print(json.dumps(out), flush=True)
 
 

@@ -416,6 +416,13 @@ fse_status fse_last_timing(const fse_ctx *ctx, double *ms4, int32_t *launches_ou
  * fastest.  ncw (HOST): the count in use; ms2 (HOST [2], may be NULL): the timed launches
  * (0 until tuned).  Setting FSE_FUSED_NCW in the environment before fse_init_torus fixes
  * the count and skips the tuning. */
+/* Timing of the dominant trajectory kernel of the last integration, from HIP events recorded on
+ * the context stream around its launches (host outputs): path 1 = the fused state + sensitivity
+ * kernel (one launch), 2 = the wide-band sensitivity sweep k_wide_sweep (one launch per Newmark
+ * step; the summed durations and the count), 0 = the generic kernels (ms_total 0).  Used to
+ * relate algorithmic work to kernel time (App. E, Eqs. E8-E9).  FSE_E_INVAL on a null pointer. */
+fse_status fse_last_kernel_timing(fse_ctx *ctx, int32_t *path, double *ms_total, int32_t *launches);
+
 fse_status fse_get_tuning(const fse_ctx *ctx, int32_t *ncw, float *ms2);
 
 const char *fse_last_error(const fse_ctx *ctx);

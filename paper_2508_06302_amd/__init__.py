@@ -264,6 +264,14 @@ def fse_last_timing(ctx: Context):
             "sens_launches": nl.value}
 
 
+def fse_last_kernel_timing(ctx: Context):
+    """-> (path of the last integration: 0 generic, 1 fused, 2 wide-band; summed duration [ms]
+    of its dominant kernel's launches from HIP events on the context stream; launch count)."""
+    path, ms, nl = C.c_int32(), C.c_double(), C.c_int32()
+    ctx.check(ctx.lib.fse_last_kernel_timing(ctx.h, C.byref(path), C.byref(ms), C.byref(nl)))
+    return path.value, ms.value, nl.value
+
+
 def fse_get_tuning(ctx: Context):
     """-> (column waves per fused work-group in use, timed launches [ms] for 1 and 2 waves)."""
     ncw = C.c_int32()

@@ -21,7 +21,7 @@ EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_
            "fse_learned_get_params", "fse_learned_fit_pod", "fse_learned_get_pod",
            "fse_learned_loss_grad", "fse_learned_fit", "fse_learned_train", "fse_learned_predict",
            "fse_learned_forward", "fse_learned_predict_batch",
-           "fse_learned_destroy", "fse_get_tuning", "fse_last_timing", "fse_last_error", "fse_destroy"]
+           "fse_learned_destroy", "fse_last_kernel_timing", "fse_get_tuning", "fse_last_timing", "fse_last_error", "fse_destroy"]
 
 i32p = C.POINTER(C.c_int32)
 f64p = C.POINTER(C.c_double)
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.fse_learned_predict_batch.argtypes = [vp, C.c_int32, f64p, C.c_int32, vp]
     lib.fse_learned_destroy.argtypes = [vp]
     lib.fse_learned_destroy.restype = None
+    lib.fse_last_kernel_timing.argtypes = [vp, i32p, f64p, i32p]
     lib.fse_get_tuning.argtypes = [vp, i32p, f32p]
     lib.fse_last_timing.argtypes = [vp, f64p, i32p]
     lib.fse_last_error.argtypes = [vp]

@@ -502,6 +502,7 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
                "path (lumped mass, half bandwidth <= 96, average acceleration, no contacts)";
     return FSE_E_UNSUPPORTED;
   }
+  ctx->last_path = fused ? 1 : wide ? 2 : 0;
   if (fused) {
     FSE_TRY(launch_fused(ctx, B, Phi));
     FSE_HIP(hipEventRecord(ctx->ev[2], ctx->stream));
@@ -1226,6 +1227,23 @@ fse_status fse_last_timing(const fse_ctx *ctx, double *ms4, int32_t *launches_ou
   if (ms4)
     for (int i = 0; i < 4; ++i) ms4[i] = ctx->last_ms[i];
   if (launches_out) *launches_out = ctx->last_sens_launches;
+  return FSE_OK;
+}
+
+fse_status fse_last_kernel_timing(fse_ctx *ctx, int32_t *path, double *ms_total, int32_t *launches) {
+  if (!ctx || !path || !ms_total || !launches) return FSE_E_INVAL;
+  *path = ctx->last_path;
+  *ms_total = 0.0;
+  *launches = 0;
+  if (ctx->last_path == 1) {
+    // the fused kernel is one launch between the idft and end-of-integration events
+    *ms_total = ctx->last_ms[1] + ctx->last_ms[2];
+    *launches = 1;
+  } else if (ctx->last_path == 2) {
+    int l = 0;
+    FSE_TRY(wide_sweep_timing(ctx, ms_total, &l));
+    *launches = l;
+  }
   return FSE_OK;
 }
 

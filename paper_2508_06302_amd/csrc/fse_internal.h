@@ -169,6 +169,7 @@ struct fse_ctx {
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   double last_ms[4] = {0, 0, 0, 0};
   int last_sens_launches = 0;
+  int last_path = 0;                // trajectory kernels of the last integration: 0 generic, 1 fused, 2 wide
   int last_max_iters = 0;
   unsigned long long last_total_iters = 0;
 };
@@ -230,6 +231,9 @@ bool wide_eligible(const fse_ctx *ctx);
 fse_status launch_wide_state(fse_ctx *ctx, int B);
 fse_status launch_wide_sens(fse_ctx *ctx, int B, double *Phi);
 void wide_free(fse_ctx *ctx);
+// summed durations (HIP events on the context stream) and count of the sweep launches of the
+// last wide-band integration with sensitivities (zero when there was none)
+fse_status wide_sweep_timing(fse_ctx *ctx, double *ms_total, int *launches);
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // the two halves of dense_lu_solve: factor A (row-major N x N, in place, pivots piv[N]), then

@@ -75,6 +75,8 @@ struct WideState {
   void *dinv = nullptr;                          // [2][Wmax][nrb * 16]
   hipStream_t side = nullptr;
   hipEvent_t ev_fac[2] = {nullptr, nullptr}, ev_sw[2] = {nullptr, nullptr}, ev_go = nullptr;
+  std::vector<hipEvent_t> ev_k;                  // start / end of every sweep of the last call
+  int ev_used = 0;
   void *Ysc = nullptr;                           // [Wmax][n][2n]
   float *P32 = nullptr;                          // [Wmax][2n][2n] (mixed mode)
   size_t frag_bytes = 0, ysc_bytes = 0;
@@ -1139,6 +1141,12 @@ fse_status launch_wide_sens(fse_ctx *ctx, int B, double *Phi) {
     FSE_HIP(hipEventCreateWithFlags(&ws->ev_go, hipEventDisableTiming));
   }
   const TrajParams P = wparams(ctx, B);
+  while ((int)ws->ev_k.size() < 2 * P.S1) {
+    hipEvent_t e;
+    FSE_HIP(hipEventCreate(&e));
+    ws->ev_k.push_back(e);
+  }
+  ws->ev_used = 0;
   const dim3 gt(nrb, (W + kLanes - 1) / kLanes);
   const size_t tl = sizeof(double) * ((size_t)ws->span_t * kLanes + 64 * 65);
   const size_t fl = factor_lds(bw, NB);
@@ -1179,6 +1187,7 @@ fse_status launch_wide_sens(fse_ctx *ctx, int B, double *Phi) {
     // context stream: the sweep of step k
     FSE_HIP(hipStreamWaitEvent(ctx->stream, ws->ev_fac[bf], 0));
     const int last = k == P.S1 - 1;
+    FSE_HIP(hipEventRecord(ws->ev_k[2 * k], ctx->stream));
     if (f32) {
 #define WIDE_SWEEP32(NBV)                                                                                      \
   if (exact)                                                                                                   \
@@ -1218,12 +1227,28 @@ fse_status launch_wide_sens(fse_ctx *ctx, int B, double *Phi) {
       }
 #undef WIDE_SWEEP64
     }
+    FSE_HIP(hipEventRecord(ws->ev_k[2 * k + 1], ctx->stream));
     FSE_HIP(hipEventRecord(ws->ev_sw[bf], ctx->stream));
   }
+  ws->ev_used = P.S1;
   if (f32)
     hipLaunchKernelGGL(k_widen, dim3(4096), dim3(256), 0, ctx->stream, ws->P32, Phi, (size_t)W * n2 * n2);
   ctx->last_sens_launches = 3 * P.S1 + 2;
   FSE_HIP(hipGetLastError());
+  return FSE_OK;
+}
+
+fse_status wide_sweep_timing(fse_ctx *ctx, double *ms_total, int *launches) {
+  WideState *ws = ctx->wide;
+  *ms_total = 0.0;
+  *launches = 0;
+  if (!ws || ws->ev_used == 0) return FSE_OK;
+  for (int k = 0; k < ws->ev_used; ++k) {
+    float ms = 0.0f;
+    FSE_HIP(hipEventElapsedTime(&ms, ws->ev_k[2 * k], ws->ev_k[2 * k + 1]));
+    *ms_total += ms;
+  }
+  *launches = ws->ev_used;
   return FSE_OK;
 }
 
@@ -1243,6 +1268,7 @@ void wide_free(fse_ctx *ctx) {
     }
     (void)hipEventDestroy(ws->ev_go);
   }
+  for (hipEvent_t e : ws->ev_k) (void)hipEventDestroy(e);
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   delete ws;
