@@ -255,6 +255,19 @@ fse_status fse_shooting_residual_matfree(fse_ctx *ctx, const double *omega, cons
  * moved Z0 since). */
 fse_status fse_jacobian_apply(fse_ctx *ctx, const double *v, double *Jv);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same product J v as fse_jacobian_apply, with the
+ * same arguments (v, Jv: [2n][U] device arrays owned by the caller; the sensitivities are those
+ * of the last fse_shooting_residual_matfree on this context), computed without any allocation.
+ * Its intermediates (I (x) Gamma) v and Phi_s x_s use a fixed scratch of 2^21 doubles (16 MiB)
+ * that the library holds on each GPU for the life of the process (its address is taken by
+ * fse_init_torus); it serves 2 x 2n x (max_batch S~) <= 2^21, e.g. the 1872-DOF shell with 128
+ * trajectories or the three-frequency beam with 1024.  Larger problems: FSE_E_UNSUPPORTED.  All
+ * calls on one GPU share that scratch: calls that overlap on one GPU (two host threads, two
+ * streams) race and must be serialised by the caller.  Enqueued on the context stream; returns
+ * after the stream has completed it.  FSE_E_INVAL without sensitivities or on a null pointer. */
+fse_status fse_jacobian_apply_noalloc(fse_ctx *ctx, const double *v, double *Jv);
+
 /* One Newton update Z0 <- Z0 + dZ (Z0 device [2n][U], omega HOST [d]), with J dZ = -R solved
  * by restarted GMRES(restart) to ||J dZ + R|| <= rtol ||R|| or maxit iterations.  For d > e
  * the unknowns are [Z(0); omega_u] and the system is bordered as in fse_newton_step: the

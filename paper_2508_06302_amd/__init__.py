@@ -402,6 +402,15 @@ def fse_jacobian_apply(ctx: Context, v):
     return out
 
 
+def fse_jacobian_apply_noalloc(ctx: Context, v, out):
+    """J v into the caller's out (torch cuda [2n][U]) without any device allocation (the library's
+    fixed per-GPU scratch); the sensitivities of the last fse_shooting_residual_matfree."""
+    ctx.bind_stream()
+    x = _dev(v, (2 * ctx.n, ctx.U))
+    ctx.check(ctx.lib.fse_jacobian_apply_noalloc(ctx.h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr())))
+    return out
+
+
 def fse_newton_krylov_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxit=300, precond=True):
     """Z0 (torch cuda [2n][U], updated in place) <- Z0 + dZ with J dZ = -R by GMRES ->
     (||R|| before, GMRES iterations, relative linear residual).  For d > e the unknown

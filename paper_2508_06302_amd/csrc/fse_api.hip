@@ -574,6 +574,7 @@ fse_status fse_init_torus(const fse_system *sys, const fse_torus_desc *desc, fse
   fse_ctx *ctx = new (std::nothrow) fse_ctx();
   if (!ctx) return FSE_E_NOMEM;
   fse_status s = init_impl(sys, desc, ctx);
+  if (s == FSE_OK) s = noalloc_setup(ctx);
   if (s != FSE_OK) {
     // keep the context alive so that fse_last_error can report; caller destroys it
     *out = ctx;

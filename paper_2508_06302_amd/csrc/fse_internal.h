@@ -234,6 +234,11 @@ void wide_free(fse_ctx *ctx);
 // summed durations (HIP events on the context stream) and count of the sweep launches of the
 // last wide-band integration with sensitivities (zero when there was none)
 fse_status wide_sweep_timing(fse_ctx *ctx, double *ms_total, int *launches);
+// Fixed scratch of the no-allocation J v (k_krylov.hip): 2^21 doubles (16 MiB) per GPU
+constexpr size_t kNoAllocScratch = size_t(1) << 21;
+constexpr int kMaxDevices = 64;
+fse_status noalloc_setup(fse_ctx *ctx);   // once per device, from fse_init_torus
+double *noalloc_scratch(int device);      // the device address taken by noalloc_setup, or null
 // Dense linear algebra (k_linalg.hip)
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // the two halves of dense_lu_solve: factor A (row-major N x N, in place, pivots piv[N]), then

@@ -18,7 +18,35 @@
 #include <cmath>
 #include <vector>
 
+#include <mutex>
+
 #include "fse_internal.h"
+
+// Fixed device scratch of fse_jacobian_apply_noalloc (callers that cannot allocate): one copy per
+// GPU for the life of the process.  Host code never uses the symbol's name as a device address;
+// fse_init_torus takes the address on each device once (noalloc_setup) and kernels receive it.
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+static double *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+fse_status noalloc_setup(fse_ctx *ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices) {
+    ctx->err = "device index beyond the no-allocation scratch table";
+    return FSE_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[ctx->device]) return FSE_OK;
+  void *p = nullptr;
+  FSE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[ctx->device] = static_cast<double *>(p);
+  return FSE_OK;
+}
+
+double *noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 namespace {
 
@@ -435,6 +463,36 @@ fse_status fse_jacobian_apply(fse_ctx *ctx, const double *v, double *Jv) {
   Krylov k = kr_view(ctx, 1);
   k.nu = 0;  // J alone: v and Jv hold 2nU entries, without the frequency border
   FSE_TRY(kr_matvec(k, v, Jv));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  return FSE_OK;
+}
+
+fse_status fse_jacobian_apply_noalloc(fse_ctx *ctx, const double *v, double *Jv) {
+  if (!ctx || !v || !Jv) return FSE_E_INVAL;
+  if (!ctx->mf_ready) {
+    ctx->err = "no sensitivities: call fse_shooting_residual_matfree first";
+    return FSE_E_INVAL;
+  }
+  const size_t n2 = 2 * (size_t)ctx->n, W = ctx->Wmax;
+  if (2 * n2 * W > kNoAllocScratch) {
+    ctx->err = "fse_jacobian_apply_noalloc: 2 x 2n x (trajectories) = " + std::to_string(2 * n2 * W) +
+               " doubles exceed the fixed scratch of " + std::to_string(kNoAllocScratch) + " doubles";
+    return FSE_E_UNSUPPORTED;
+  }
+  double *base = noalloc_scratch(ctx->device);
+  if (!base) {
+    ctx->err = "fse_jacobian_apply_noalloc: the scratch address of this device was not set up by fse_init_torus";
+    return FSE_E_DEVICE;
+  }
+  // (I (x) Gamma) v -> xs, Phi_s x_s -> ys (both [2n][Wmax] in the scratch), DFT + rotation - v
+  double *xs = base, *ys = base + n2 * W;
+  const int St = ctx->St;
+  hipLaunchKernelGGL(k_gamma_expand, dim3((St + 63) / 64, (unsigned)n2), dim3(64), 0, ctx->stream, v, ctx->G_d,
+                     (int)n2, ctx->U, St, (int)W, xs);
+  hipLaunchKernelGGL(k_phi_apply, dim3(St, (unsigned)((n2 + kPhiRows - 1) / kPhiRows)), dim3(256),
+                     sizeof(double) * n2, ctx->stream, ctx->PhiQU, xs, (int)n2, (int)W, ys);
+  FSE_HIP(hipGetLastError());
+  FSE_TRY(launch_dft(ctx, 1, ys, v, Jv));
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
