@@ -644,7 +644,7 @@ __global__ void k_wide_sens0(int n, int bw, int W, int St, int d, TrajParams P, 
 // blocks stay in registers (D layout).  Blocks map to XCDs by trajectory, so the column groups of
 // a trajectory share its factor in one L2.
 template <int NB, typename FT, bool EXACT>
-__global__ __launch_bounds__(256) void k_wide_sweep(int n, int W, int St, int d, int nrb, int ncg, int per_xcd,
+__global__ __launch_bounds__(256, 2) void k_wide_sweep(int n, int W, int St, int d, int nrb, int ncg, int per_xcd,
                                                     const double *__restrict__ omega, TrajParams P,
                                                     const double *__restrict__ mdiag,
                                                     const FT *__restrict__ Dfrag, const uint32_t *__restrict__ Dmask,
@@ -654,6 +654,7 @@ __global__ __launch_bounds__(256) void k_wide_sweep(int n, int W, int St, int d,
   constexpr int NBL = 2 * NB + 1;               // D blocks per row block
   constexpr int NSTG = NB + 1 + NBL;            // staged blocks per forward row block
   __shared__ FT stg[NSTG * 256];
+  __shared__ FT stgr[32];                       // per-row scalars of the block: mass, 1 / d
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int pidx = xcd * per_xcd + slot;
   if (pidx >= W * ncg) return;
@@ -725,34 +726,30 @@ __global__ __launch_bounds__(256) void k_wide_sweep(int n, int W, int St, int d,
   for (int s = 0; s <= NB; ++s) pre[s] = fr[s * 256 + tid];
 #pragma unroll
   for (int s = 0; s < NBL; ++s) pre[NB + 1 + s] = Dfrag[s * 256 + tid];
-  // per-row scalars of a block (lumped mass, 1/d of the factor), loaded one block ahead
-  auto ldrow = [&](const auto *base, int I, int lim) -> V4 {
-    V4 r = zero4;
-    if (I < nrb) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = I * 16 + trow<FT>(v, rsub);
-        r[v] = row < lim ? (FT)base[row] : (FT)0;
-      }
+  // per-row scalars of a block (lumped mass, 1/d of the factor), staged with the blocks by the
+  // first 32 threads
+  auto ldrow = [&](int I) -> FT {
+    if (tid < 16) {
+      const int row = I * 16 + tid;
+      return row < n ? (FT)mdiag[row] : (FT)0;
     }
-    return r;
+    return tid < 32 ? dv[I * 16 + tid - 16] : (FT)0;
   };
-  V4 p2n = ld4(P2, 0), mn = ldrow(mdiag, 0, n), dn = ldrow(dv, 0, nrb * 16);
+  FT prer = ldrow(0);
   for (int I = 0; I < nrb; ++I) {
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < NSTG; ++s) stg[s * 256 + tid] = pre[s];
+    if (tid < 32) stgr[tid] = prer;
     __syncthreads();
     if (I + 1 < nrb) {
 #pragma unroll
       for (int s = 0; s <= NB; ++s) pre[s] = fr[(size_t)(I + 1) * fst + s * 256 + tid];
 #pragma unroll
       for (int s = 0; s < NBL; ++s) pre[NB + 1 + s] = Dfrag[((size_t)(I + 1) * NBL + s) * 256 + tid];
+      prer = ldrow(I + 1);
     }
-    const V4 p2 = p2n, mI = mn, dI = dn;
-    p2n = ld4(P2, I + 1);
-    mn = ldrow(mdiag, I + 1, n);
-    dn = ldrow(dv, I + 1, nrb * 16);
+    const V4 p2 = ld4(P2, I);
     const uint32_t mask = Dmask[I];
     V4 accD = zero4;
 #pragma unroll
@@ -763,7 +760,7 @@ __global__ __launch_bounds__(256) void k_wide_sweep(int n, int W, int St, int d,
       }
     V4 acc;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = fw1 * accD[v] + fw1s * mI[v] * p2[v];
+    for (int v = 0; v < 4; ++v) acc[v] = fw1 * accD[v] + fw1s * stgr[trow<FT>(v, rsub)] * p2[v];
 #pragma unroll
     for (int s = 0; s < NB; ++s)
       if (I - NB + s >= 0) {
@@ -775,7 +772,7 @@ __global__ __launch_bounds__(256) void k_wide_sweep(int n, int W, int St, int d,
     for (int v = 0; v < 4; ++v) y = mma(stg[NB * 256 + v * 64 + lane], acc[v], y);
     V4 z;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) z[v] = y[v] * dI[v];
+    for (int v = 0; v < 4; ++v) z[v] = y[v] * stgr[16 + trow<FT>(v, rsub)];
     st4(Y, I, z);
 #pragma unroll
     for (int s = 0; s + 1 < NB; ++s) yw[s] = yw[s + 1];
