@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--shell-solve", action="store_true",
                     help="also time the shell's Newton-Krylov solve in both precisions (minutes)")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--sweep", choices=["train", "learned", "secant"],
+                    help="run one phase of the 200-point shell sweep instead of the benchmark")
+    ap.add_argument("--sweep-dir", default=os.path.join(ROOT, "gpurun_out", "sweep"))
+    ap.add_argument("--sweep-precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--sweep-deadline", type=float, default=1000.0,
+                    help="seconds after which a sweep phase stops and saves the points it has solved")
     return ap.parse_args()
 
 
@@ -359,6 +365,211 @@ def krylov_solve(fse, torch, amp=0.1):
             "converged": bool(hist[-1] < 1e-8)}
 
 
+# ----------------------------------------------------------------------------- shell sweep
+SWEEP_W = (0.93, 0.97)       # omega_1 / omega_n (first natural frequency 100 Hz)
+SWEEP_A = (6.0, 14.0)        # forcing amplitude scale a: loads 40 a and 20 a N
+SWEEP_RATIO = 2 ** -0.5      # omega_2 / omega_1
+SWEEP_TOL = 1e-8
+
+
+def sweep_points():
+    """The 200 points of the shell sweep as (omega_1 / omega_n, a).  Training: a 10 x 10 grid over
+    the box, amplitude rows visited as a serpentine in frequency (frequency sweeps up and down at
+    rising amplitude).  Evaluation: a second 10 x 10 grid strictly inside the box, interleaved
+    with the first (grid coordinates 0.45 + 0.9 k), visited as a serpentine in the opposite
+    amplitude direction, so that it starts next to the last training point."""
+    def axis(lo, hi, t):
+        return lo + (hi - lo) * np.asarray(t) / 9.0
+
+    gi = np.arange(10)
+    ge = 0.45 + 0.9 * np.arange(10)
+    train, evalp = [], []
+    for r, k in enumerate(gi):
+        ws = axis(*SWEEP_W, gi if r % 2 == 0 else gi[::-1])
+        train += [(w, axis(*SWEEP_A, k)) for w in ws]
+    for r, k in enumerate(ge[::-1]):
+        ws = axis(*SWEEP_W, ge if r % 2 == 0 else ge[::-1])
+        evalp += [(w, axis(*SWEEP_A, k)) for w in ws]
+    return np.array(train), np.array(evalp)
+
+
+def chord_solve(fse, torch, ctx, om, Z, st, rate=0.25, max_steps=30, rtol=1e-4):
+    """Newton-Krylov with Jacobian reuse for one point (omega host [2], Z torch [2n][U] in place):
+    chord steps with the stored Jacobian, and a full Newton-Krylov step (new sensitivities) when
+    none is stored, when the last step contracted ||R|| by less than `rate`, or when ||R|| grew.
+    Stops at the first iterate with ||R||_2 < SWEEP_TOL, which is the one returned.
+    -> (corrections, of which full Newton steps, final ||R||)."""
+    Zk = torch.empty_like(Z)
+    its = refr = 0
+    prev = None
+    refresh = not st.get("have_J", False)
+    while True:
+        Zk.copy_(Z)
+        if refresh:
+            rn, _, _ = fse.fse_newton_krylov_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
+            st["have_J"] = True
+            refr += 1
+        else:
+            rn, _, _ = fse.fse_newton_krylov_chord_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
+        if rn < SWEEP_TOL:
+            Z.copy_(Zk)
+            return its, refr - (1 if refresh else 0), rn
+        if its >= max_steps or not np.isfinite(rn):
+            raise RuntimeError(f"no convergence at omega {om}: ||R|| {rn:.3e} after {its} corrections")
+        refresh = prev is not None and rn > rate * prev
+        if prev is not None and rn > prev:
+            Z.copy_(Zk)          # the last correction made things worse: redo it with a new Jacobian
+            rn = prev
+        its += 1
+        prev = rn
+
+
+def _sweep_ctx(fse, torch, prec):
+    from fse_inputs import workload
+    wl = workload("C3")
+    ctx = fse.fse_init_torus(wl.system, wl.torus, precision=prec)
+    U, St, bw, kt = fse.fse_get_layout(ctx)
+    wn = 2 * np.pi * 100.0
+    return wl, ctx, kt, wn
+
+
+def _sweep_params(wn, pt):
+    """Point (omega_1 / omega_n, a) -> (omega [2], amplitudes [2], continuation vector, features)."""
+    w1 = pt[0] * wn
+    om = np.array([w1, SWEEP_RATIO * w1])
+    amp = np.array([pt[1], pt[1]])
+    return om, amp, np.concatenate([om, amp]), np.array([w1, SWEEP_RATIO, pt[1]])
+
+
+def run_sweep(fse, torch, phase, sweep_dir, prec_name, deadline):
+    """One phase of the 200-point shell sweep; prints one JSON line.
+    train:   the 100 training points with the secant predictor (point 0 from its linear harmonic
+             response); writes the converged tori (FP32) and the last two (FP64) to sweep_dir.
+    learned: POD (rank 64) of the training tori, the MLP 3 -> 256 -> 256 -> 64 trained on the GPU,
+             then the 100 evaluation points, each from the better of the secant and the learned
+             (BF16 matrix-core inference) prediction by ||R||.
+    secant:  the 100 evaluation points with the secant predictor alone.
+    Both evaluation phases start from the last two training points and solve every point to
+    ||R||_2 < 1e-8 with the same Newton-Krylov iteration with Jacobian reuse.  A phase still
+    running `deadline` seconds after its start stops and reports (and saves) the points it has."""
+    prec = fse.FSE_PREC_MIXED_FP32 if prec_name == "mixed" else fse.FSE_PREC_FP64
+    os.makedirs(sweep_dir, exist_ok=True)
+    train, evalp = sweep_points()
+    progress(f"sweep {phase}: init ({prec_name})")
+    wl, ctx, kt, wn = _sweep_ctx(fse, torch, prec)
+    N = 2 * wl.system.n * ctx.U
+    st = {}
+    recs = []
+    t_all = time.perf_counter()
+    done = 0
+    if phase == "train":
+        pts = train
+        Zs = torch.empty((len(pts), 2 * wl.system.n, ctx.U), dtype=torch.float32, device="cuda")
+        prev = os.path.join(sweep_dir, "train_mixed.json") if prec_name == "mixed" else None
+        if os.path.exists(os.path.join(sweep_dir, "train_points.npy")):
+            # resume: keep the points solved by an earlier run of this phase
+            done = len(np.load(os.path.join(sweep_dir, "train_points.npy")))
+            Zs[:done].copy_(torch.from_numpy(np.load(os.path.join(sweep_dir, "train_Z_f32.npy"))))
+            last = np.load(os.path.join(sweep_dir, "train_last2.npy"))
+            hist = [(_sweep_params(wn, train[done - 2])[2], torch.tensor(last[0], device="cuda")),
+                    (_sweep_params(wn, train[done - 1])[2], torch.tensor(last[1], device="cuda"))]
+            recs = json.load(open(prev))["records"] if prev and os.path.exists(prev) else []
+            progress(f"sweep train: resuming after {done} points")
+        else:
+            om0, amp0, _, _ = _sweep_params(wn, pts[0])
+            from fse_inputs import workload
+            Zlin = workload("C3", omega1=om0[0]).initial_iterate(kt) * pts[0][1]
+            Z = torch.tensor(Zlin, dtype=torch.float64, device="cuda")
+            hist = []
+    else:
+        last = np.load(os.path.join(sweep_dir, "train_last2.npy"))
+        train = np.load(os.path.join(sweep_dir, "train_points.npy"))
+        hist = [(_sweep_params(wn, train[-2])[2], torch.tensor(last[0], device="cuda")),
+                (_sweep_params(wn, train[-1])[2], torch.tensor(last[1], device="cuda"))]
+        pts = evalp
+        lp = None
+        if phase == "learned":
+            X = torch.tensor(np.load(os.path.join(sweep_dir, "train_Z_f32.npy")), device="cuda").double()
+            feats = np.array([_sweep_params(wn, p)[3] for p in train])
+            lp = fse.fse_learned_create(ctx, n_in=3, hidden=256, rank=64)
+            rng = np.random.default_rng(7)
+            params = []
+            for fi, fo in ((3, 256), (256, 256), (256, 64)):
+                params += [rng.normal(scale=(1.0 / fi) ** 0.5, size=(fo, fi)).ravel(), np.zeros(fo)]
+            lp.set_params(np.concatenate(params).astype(np.float32))
+            t0 = time.perf_counter()
+            sig = lp.fit_pod(X)
+            loss = lp.train(feats, X, epochs=3000, lr=1e-3, wd=1e-5)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            mean, modes = lp.get_pod()
+            Xc = X.reshape(len(train), N) - mean
+            proj_err = float((Xc - (Xc @ modes) @ modes.T).norm() / Xc.norm())
+            del X, Xc
+            torch.cuda.empty_cache()
+            progress(f"sweep learned: POD + MLP in {t_train:.1f} s, loss {loss[0]:.3e} -> {loss[-1]:.3e}")
+    for j, pt in enumerate(pts):
+        if j < done:
+            continue
+        if time.perf_counter() - t_all > deadline:
+            progress(f"sweep {phase}: deadline reached after {j} points")
+            break
+        om, amp, pvec, feat = _sweep_params(wn, pt)
+        fse.fse_set_forcing(ctx, amp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = {"omega_ratio": float(pt[0]), "a": float(pt[1])}
+        if len(hist) >= 2:
+            Z = fse.fse_secant_predict(ctx, hist[-2][0], hist[-1][0], pvec, hist[-2][1], hist[-1][1])
+        elif len(hist) == 1:
+            Z = hist[-1][1].clone()
+        if phase == "learned":
+            _, rs, _ = fse.fse_shooting_residual_jacobian(ctx, om[None], Z[None])
+            Zl = lp.predict_batch(feat[None], bf16=True)[0]
+            _, rl, _ = fse.fse_shooting_residual_jacobian(ctx, om[None], Zl[None])
+            rec["R_secant"], rec["R_learned"] = float(rs[0]), float(rl[0])
+            rec["learned_used"] = bool(np.isfinite(rl[0]) and rl[0] < rs[0])
+            if rec["learned_used"]:
+                Z = Zl
+        its, full, rn = chord_solve(fse, torch, ctx, om, Z, st)
+        torch.cuda.synchronize()
+        rec.update({"corrections": its, "full_newton_steps": full, "R_final": rn,
+                    "seconds": time.perf_counter() - t0})
+        recs.append(rec)
+        if phase == "train":
+            Zs[j].copy_(Z)
+        hist = (hist + [(pvec, Z.clone())])[-2:]
+        progress(f"sweep {phase} {j + 1}/{len(pts)}: {its} corrections ({full} full), ||R|| {rn:.2e}, "
+                 f"{rec['seconds']:.1f} s" + (f", learned {rec['learned_used']}" if phase == "learned" else ""))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    if phase == "train":
+        np.save(os.path.join(sweep_dir, "train_Z_f32.npy"), Zs[:len(recs)].cpu().numpy())
+        np.save(os.path.join(sweep_dir, "train_points.npy"), pts[:len(recs)])
+        np.save(os.path.join(sweep_dir, "train_last2.npy"), np.stack([h[1].cpu().numpy() for h in hist]))
+    if phase == "train":
+        total += sum(r["seconds"] for r in recs[:done])   # the earlier runs' share
+    c = np.array([r["corrections"] for r in recs], float)
+    sec = np.array([r["seconds"] for r in recs])
+    out = {"metric": "Newton corrections and seconds per point to ||R||_2 < 1e-8 (shell sweep)",
+           "phase": phase, "precision": prec_name, "points": len(recs),
+           "corrections_per_point": float(c.mean()),
+           "full_newton_steps_per_point": float(np.mean([r["full_newton_steps"] for r in recs])),
+           "seconds_per_point": float(sec.mean()), "seconds_total": float(sec.sum()), "wall_s": total,
+           "max_final_residual": float(max(r["R_final"] for r in recs)),
+           "config": {"workload": "synthetic shell 1872 DOF, d=2, 128 trajectories, H=20, S1=1024",
+                      "box": {"omega1_over_omega_n": SWEEP_W, "a": SWEEP_A, "omega2_over_omega1": SWEEP_RATIO}},
+           "records": recs}
+    if phase == "learned":
+        out.update({"learned_used_fraction": float(np.mean([r["learned_used"] for r in recs])),
+                    "train_s": t_train, "loss_first_last": [float(loss[0]), float(loss[-1])],
+                    "pod_sigma_first_last": [float(sig[0]), float(sig[-1])], "pod_projection_error": proj_err,
+                    "median_R_secant": float(np.median([r["R_secant"] for r in recs])),
+                    "median_R_learned": float(np.median([r["R_learned"] for r in recs]))})
+    json.dump(out, open(os.path.join(sweep_dir, f"{phase}_{prec_name}.json"), "w"))
+    print(json.dumps({k: v for k, v in out.items() if k != "records"}), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -372,6 +583,9 @@ def main():
 
     import paper_2508_06302_amd as fse
     torch.cuda.set_device(0)
+    if args.sweep:
+        run_sweep(fse, torch, args.sweep, args.sweep_dir, args.sweep_precision, args.sweep_deadline)
+        return
     sh = run_shell(fse, torch, fse.FSE_PREC_FP64, args.steps, args.warmup)
     wl, St, bw = sh["wl"], sh["St"], sh["bw"]
     n, S1 = wl.system.n, wl.torus.S1

@@ -284,6 +284,22 @@ fse_status fse_newton_krylov_step(fse_ctx *ctx, double *omega, double *Z0, doubl
                                   int32_t maxit, int32_t precond, double *res_norm, int32_t *gmres_iters,
                                   double *gmres_relres);
 
+/* Simplified (chord) Newton step for continuation sweeps, where the Jacobian changes little
+ * from one point to the next: R at (omega HOST [d], Z0 device [2n][U]) from the states alone
+ * (no sensitivities are propagated), then J dZ = -R by GMRES as in fse_newton_krylov_step but
+ * with the stored J, that of the last fse_shooting_residual_matfree or fse_newton_krylov_step
+ * evaluation on this context (its Phi_s and its rotation R(rho), possibly at another Z0, omega
+ * or forcing), and Z0 <- Z0 + dZ.  The preconditioner blocks of the stored J are factored at
+ * the first chord step after an evaluation and reused until the next one.  This is Newton's
+ * method with a frozen Jacobian: it converges linearly, at a rate set by how far the stored J
+ * is from the Jacobian at the current point.  d = e only (FSE_E_UNSUPPORTED otherwise);
+ * FSE_E_INVAL without stored sensitivities (any call that writes the context's sensitivity
+ * buffer, e.g. fse_shooting_residual_jacobian with J or fse_lyapunov, discards them).
+ * Outputs and workspace as fse_newton_krylov_step. */
+fse_status fse_newton_krylov_chord_step(fse_ctx *ctx, const double *omega, double *Z0, double rtol,
+                                        int32_t restart, int32_t maxit, int32_t precond, double *res_norm,
+                                        int32_t *gmres_iters, double *gmres_relres);
+
 /* ---------------------------------------------------------------- hyper-time domain
  * FSE-Shooting with the sampled initial states as unknowns (Sec. 3.4, Eq. FSES_T):
  *     R(zbar(0), omega) = (I (x) Gamma R(rho) Gamma^-1) zbar(2 pi) - zbar(0),

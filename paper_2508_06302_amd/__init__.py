@@ -146,6 +146,15 @@ def _dev(x, shape):
     return t
 
 
+def _inout(t, numel, name):
+    """An array the library updates in place: a contiguous float64 CUDA tensor of numel entries."""
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and t.numel() == numel):
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of {numel} entries (updated in place)")
+    return C.c_void_p(t.data_ptr())
+
+
 def fse_integrate_batch(ctx: Context, omega, Z0, want_phi=False):
     """omega [B][d] (host), Z0 [B][2n][U] -> zT [B][2n][S~], Phi [B][S~][2n][2n] or None."""
     torch = _torch()
@@ -209,7 +218,7 @@ def fse_newton_step(ctx: Context, omega, Z0):
     ctx.bind_stream()
     om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
-    ctx.check(ctx.lib.fse_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
+    ctx.check(ctx.lib.fse_newton_step(ctx.h, _p(om, C.c_double), _inout(Z0, 2 * ctx.n * ctx.U, "Z0"),
                                       C.byref(rn)))
     _omega_back(omega, om)
     return rn.value
@@ -221,7 +230,7 @@ def fse_newton_solve(ctx: Context, omega, Z0, tol=1e-8, maxit=20):
     ctx.bind_stream()
     om = _omega_inout(omega, ctx.d, ctx.e)
     it, rn = C.c_int32(), C.c_double()
-    st = ctx.lib.fse_newton_solve(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()),
+    st = ctx.lib.fse_newton_solve(ctx.h, _p(om, C.c_double), _inout(Z0, 2 * ctx.n * ctx.U, "Z0"),
                                   tol, maxit, C.byref(it), C.byref(rn))
     _omega_back(omega, om)
     ctx.check(st)
@@ -421,11 +430,28 @@ def fse_newton_krylov_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxi
     rn = C.c_double()
     its = C.c_int32()
     rel = C.c_double()
-    st = ctx.lib.fse_newton_krylov_step(ctx.h, _p(om, C.c_double), C.c_void_p(Z0.data_ptr()), float(rtol),
+    st = ctx.lib.fse_newton_krylov_step(ctx.h, _p(om, C.c_double), _inout(Z0, 2 * ctx.n * ctx.U, "Z0"), float(rtol),
                                         int(restart), int(maxit), int(bool(precond)), C.byref(rn),
                                         C.byref(its), C.byref(rel))
     ctx.check(st)
     _omega_back(omega, om)
+    return rn.value, its.value, rel.value
+
+
+def fse_newton_krylov_chord_step(ctx: Context, omega, Z0, rtol=1e-10, restart=30, maxit=300, precond=True):
+    """Simplified Newton step with the stored Jacobian (that of the last matrix-free
+    evaluation): Z0 (torch cuda [2n][U], in place) <- Z0 + dZ with J_stored dZ = -R(omega, Z0),
+    R from the states alone -> (||R|| before, GMRES iterations, relative linear residual)."""
+    _torch()
+    ctx.bind_stream()
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.float64).reshape(ctx.d))
+    rn = C.c_double()
+    its = C.c_int32()
+    rel = C.c_double()
+    st = ctx.lib.fse_newton_krylov_chord_step(ctx.h, _p(om, C.c_double), _inout(Z0, 2 * ctx.n * ctx.U, "Z0"), float(rtol),
+                                              int(restart), int(maxit), int(bool(precond)), C.byref(rn),
+                                              C.byref(its), C.byref(rel))
+    ctx.check(st)
     return rn.value, its.value, rel.value
 
 
@@ -471,7 +497,7 @@ def fse_multiple_newton_step(ctx: Context, M, omega, Zs):
     ctx.bind_stream()
     om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
-    ctx.check(ctx.lib.fse_multiple_newton_step(ctx.h, int(M), _p(om, C.c_double), C.c_void_p(Zs.data_ptr()),
+    ctx.check(ctx.lib.fse_multiple_newton_step(ctx.h, int(M), _p(om, C.c_double), _inout(Zs, int(M) * 2 * ctx.n * ctx.U, "Zs"),
                                                C.byref(rn)))
     _omega_back(omega, om)
     return rn.value
@@ -484,7 +510,7 @@ def fse_hypertime_newton_step(ctx: Context, omega, zbar0):
     ctx.bind_stream()
     om = _omega_inout(omega, ctx.d, ctx.e)
     rn = C.c_double()
-    ctx.check(ctx.lib.fse_hypertime_newton_step(ctx.h, _p(om, C.c_double), C.c_void_p(zbar0.data_ptr()),
+    ctx.check(ctx.lib.fse_hypertime_newton_step(ctx.h, _p(om, C.c_double), _inout(zbar0, 2 * ctx.n * ctx.Stilde, "zbar0"),
                                                 C.byref(rn)))
     _omega_back(omega, om)
     return rn.value

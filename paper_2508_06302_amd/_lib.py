@@ -15,6 +15,7 @@ EXPORTS = ["fse_init_torus", "fse_get_layout", "fse_set_stream", "fse_integrate_
            "fse_newton_solve", "fse_lyapunov", "fse_set_forcing", "fse_set_newmark", "fse_set_contacts", "fse_secant_predict",
            "fse_continuation", "fse_continuation_learned", "fse_residual_dp", "fse_arclength",
            "fse_shooting_residual_matfree", "fse_jacobian_apply", "fse_jacobian_apply_noalloc", "fse_newton_krylov_step",
+           "fse_newton_krylov_chord_step",
            "fse_hypertime_residual_jacobian", "fse_hypertime_newton_step", "fse_multiple_residual_jacobian",
            "fse_multiple_newton_step", "fse_learned_create",
            "fse_learned_num_params", "fse_learned_inputs", "fse_learned_set_params",
@@ -83,6 +84,8 @@ def load(path: str = LIB_PATH):
     lib.fse_multiple_newton_step.argtypes = [vp, C.c_int32, f64p, vp, f64p]
     lib.fse_newton_krylov_step.argtypes = [vp, f64p, vp, C.c_double, C.c_int32, C.c_int32, C.c_int32, f64p,
                                            i32p, f64p]
+    lib.fse_newton_krylov_chord_step.argtypes = [vp, f64p, vp, C.c_double, C.c_int32, C.c_int32, C.c_int32,
+                                                 f64p, i32p, f64p]
     lib.fse_arclength.argtypes = [vp, C.c_int32, f64p, vp, C.c_double, C.c_double, C.c_int32, vp, f64p,
                                   f64p, i32p, f64p]
     f32p = C.POINTER(C.c_float)

@@ -408,6 +408,7 @@ fse_status init_impl(const fse_system *sys, const fse_torus_desc *desc, fse_ctx 
   FSE_TRY(alloc(ctx, (void **)&ctx->zTw, sizeof(double) * (size_t)2 * n * W));
   FSE_TRY(alloc(ctx, (void **)&ctx->status_d, sizeof(DevStatus)));
   FSE_TRY(alloc(ctx, (void **)&ctx->rot_d, sizeof(double) * ctx->Bmax * std::max(ctx->L, 1)));
+  FSE_TRY(alloc(ctx, (void **)&ctx->rot_mf, sizeof(double) * std::max(ctx->L, 1)));
   FSE_TRY(alloc(ctx, (void **)&ctx->work_R, sizeof(double) * ctx->Bmax * 2 * n * ctx->U));
   FSE_TRY(alloc(ctx, (void **)&ctx->Zwork, sizeof(double) * std::max(ctx->Bmax, 2) * 2 * n * ctx->U));
   FSE_TRY(alloc(ctx, (void **)&ctx->norm_d, sizeof(double) * ctx->Bmax));
@@ -421,7 +422,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->f3_ptr, ctx->f3_jkl, ctx->f3_v, ctx->kt_ptr, ctx->kt_idx, ctx->kt_c,
                   ctx->G_d, ctx->Gi_d, ctx->sidx_d, ctx->Sdim_d, ctx->ktable_d, ctx->omega_d,
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
-                  ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->work_R, ctx->Zwork, ctx->Jw,
+                  ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->rot_mf, ctx->work_R, ctx->Zwork, ctx->Jw,
                   ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
                   ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult,
                   ctx->ct_ptr, ctx->ct_idx, ctx->ct_c, ctx->uhist, ctx->cn_ptr, ctx->cn_v};
@@ -489,6 +490,12 @@ fse_status integrate_impl(fse_ctx *ctx, int B, const double *omega, const double
     return FSE_E_INVAL;
   }
   FSE_TRY(upload_omega(ctx, B, omega));
+  if (Phi && Phi == ctx->PhiQU) {
+    // the sensitivities kept for the matrix-free Jacobian are about to be overwritten
+    ctx->mf_ready = false;
+    ctx->mf_stored = false;
+    ctx->pc_ready = false;
+  }
   FSE_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
   if (ctx->samples_in)
     FSE_TRY(launch_samples_in(ctx, B, Z0));  // Z0 holds the samples zbar(0) [B][2n][S~]

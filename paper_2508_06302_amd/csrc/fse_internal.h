@@ -135,7 +135,10 @@ struct fse_ctx {
   double *wfac = nullptr;           // factors of T(q_{k+1}) for every step and trajectory
   size_t wfac_elems = 0;
   // matrix-free Newton-Krylov (k_krylov.hip)
-  bool mf_ready = false;            // PhiQU and rot_d hold the sensitivities of one evaluation
+  bool mf_ready = false;            // PhiQU holds the sensitivities of the evaluation at the current Z0
+  bool mf_stored = false;           // PhiQU and rot_mf hold those of some earlier evaluation (chord steps)
+  bool pc_ready = false;            // the preconditioner blocks in kr belong to the stored sensitivities
+  double *rot_mf = nullptr;         // [L] rotation angles of the stored evaluation
   double *kr = nullptr;             // Krylov basis, work vectors, preconditioner blocks
   size_t kr_elems = 0;
   int32_t *kr_piv = nullptr;        // pivots of the preconditioner blocks
@@ -192,7 +195,9 @@ fse_status launch_state(fse_ctx *ctx, int B);
 fse_status launch_sens(fse_ctx *ctx, int B, double *PhiQU);
 fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R);
 // (I (x) R(rho) Gamma^-1) zT - Z0 for terminal samples zT [2n][Wmax]
-fse_status launch_dft(fse_ctx *ctx, int B, const double *zT, const double *Z0, double *R);
+// rot: rotation angles [B][L] (device), or null for those of the last uploaded omega (rot_d)
+fse_status launch_dft(fse_ctx *ctx, int B, const double *zT, const double *Z0, double *R,
+                      const double *rot = nullptr);
 fse_status launch_jacobian(fse_ctx *ctx, int B, const double *PhiQU, double *J, size_t ldJ);
 fse_status launch_dRdw(fse_ctx *ctx, double *out, const double *R, const double *Z0, double omega1);
 fse_status launch_border(fse_ctx *ctx, double *Jb, size_t ldJ, const double *R, const double *Z0,

@@ -226,6 +226,7 @@ fse_status kr_alloc(fse_ctx *ctx, int restart) {
     ctx->kr = nullptr;
     ctx->kr_piv = nullptr;
     ctx->kr_elems = 0;
+    ctx->pc_ready = false;
     if (hipMalloc((void **)&ctx->kr, sizeof(double) * need) != hipSuccess ||
         hipMalloc((void **)&ctx->kr_piv, sizeof(int32_t) * (n2 + 2 * L * n2)) != hipSuccess) {
       ctx->err = "hipMalloc failed for the Krylov workspace";
@@ -280,7 +281,8 @@ Krylov kr_view(fse_ctx *ctx, int restart) {
   return k;
 }
 
-// out = J v with the sensitivities of the last evaluation (ctx->PhiQU, rotation in ctx->rot_d);
+// out = J v with the stored sensitivities (ctx->PhiQU) and the rotation of the same evaluation
+// (ctx->rot_mf);
 // with unknown frequencies, out = [J v_Z + dR/domega_u v_w; phase rows . v_Z]
 fse_status kr_matvec(const Krylov &k, const double *v, double *out) {
   fse_ctx *ctx = k.ctx;
@@ -290,7 +292,7 @@ fse_status kr_matvec(const Krylov &k, const double *v, double *out) {
   hipLaunchKernelGGL(k_phi_apply, dim3(St, (k.n2 + kPhiRows - 1) / kPhiRows), dim3(256), sizeof(double) * k.n2,
                      ctx->stream, ctx->PhiQU, k.xs, k.n2, W, k.ys);
   FSE_HIP(hipGetLastError());
-  FSE_TRY(launch_dft(ctx, 1, k.ys, v, out));
+  FSE_TRY(launch_dft(ctx, 1, k.ys, v, out, ctx->rot_mf));
   if (k.nu > 0) {
     hipLaunchKernelGGL(k_add_cols, dim3((k.N + 255) / 256), dim3(256), 0, ctx->stream, k.Bc, k.N, k.nu, v + k.N,
                        out);
@@ -311,12 +313,13 @@ fse_status kr_precond_build(const Krylov &k) {
   hipLaunchKernelGGL(k_phi_mean, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, ctx->stream, ctx->PhiQU, k.n2,
                      ctx->St, k.Pbar);
   hipLaunchKernelGGL(k_pc_blocks, dim3((unsigned)((4 * nn + 255) / 256), k.L + 1), dim3(256), 0, ctx->stream,
-                     k.Pbar, ctx->rot_d, k.n2, k.L, k.blocks);
+                     k.Pbar, ctx->rot_mf, k.n2, k.L, k.blocks);
   FSE_HIP(hipGetLastError());
   for (int l = 0; l <= k.L; ++l) {
     const int m = l == 0 ? k.n2 : 2 * k.n2;
     FSE_TRY(dense_lu_factor(ctx, k.blocks + block_off(k, l), m, k.piv + vec_off(k, l)));
   }
+  ctx->pc_ready = true;
   return FSE_OK;
 }
 
@@ -433,9 +436,13 @@ fse_status kr_gmres(const Krylov &k, const double *b, bool precond, double rtol,
 fse_status kr_evaluate(fse_ctx *ctx, const double *omega, const double *Z0, double *R, double *rn) {
   FSE_TRY(ensure_phi_buffer(ctx));
   FSE_TRY(integrate_points(ctx, 1, omega, Z0, nullptr, ctx->PhiQU));
+  FSE_HIP(hipMemcpyAsync(ctx->rot_mf, ctx->rot_d, sizeof(double) * std::max(ctx->L, 1), hipMemcpyDeviceToDevice,
+                         ctx->stream));
   FSE_TRY(launch_dft_residual(ctx, 1, Z0, R));
   FSE_TRY(launch_norms(ctx, 1, R, rn));
   ctx->mf_ready = true;
+  ctx->mf_stored = true;
+  ctx->pc_ready = false;
   return FSE_OK;
 }
 
@@ -492,7 +499,7 @@ fse_status fse_jacobian_apply_noalloc(fse_ctx *ctx, const double *v, double *Jv)
   hipLaunchKernelGGL(k_phi_apply, dim3(St, (unsigned)((n2 + kPhiRows - 1) / kPhiRows)), dim3(256),
                      sizeof(double) * n2, ctx->stream, ctx->PhiQU, xs, (int)n2, (int)W, ys);
   FSE_HIP(hipGetLastError());
-  FSE_TRY(launch_dft(ctx, 1, ys, v, Jv));
+  FSE_TRY(launch_dft(ctx, 1, ys, v, Jv, ctx->rot_mf));
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   return FSE_OK;
 }
@@ -532,6 +539,41 @@ fse_status fse_newton_krylov_step(fse_ctx *ctx, double *omega, double *Z0, doubl
   }
   FSE_HIP(hipStreamSynchronize(ctx->stream));
   ctx->mf_ready = false;  // Z0 moved: the stored sensitivities belong to the old point
+  return FSE_OK;
+}
+
+fse_status fse_newton_krylov_chord_step(fse_ctx *ctx, const double *omega, double *Z0, double rtol,
+                                        int32_t restart, int32_t maxit, int32_t precond, double *res_norm,
+                                        int32_t *gmres_iters, double *gmres_relres) {
+  if (!ctx || !omega || !Z0 || restart < 1 || restart > 500 || maxit < 1 || !(rtol > 0.0)) return FSE_E_INVAL;
+  if (ctx->d != ctx->e) {
+    ctx->err = "chord steps need every base frequency known (d = e)";
+    return FSE_E_UNSUPPORTED;
+  }
+  if (!ctx->mf_stored) {
+    ctx->err = "no stored sensitivities: call fse_shooting_residual_matfree or fse_newton_krylov_step first";
+    return FSE_E_INVAL;
+  }
+  FSE_TRY(kr_alloc(ctx, restart));
+  const Krylov k = kr_view(ctx, restart);
+  // the residual at (omega, Z0) from the states alone; PhiQU and rot_mf are left as they are
+  FSE_TRY(integrate_points(ctx, 1, omega, Z0, nullptr, nullptr));
+  FSE_TRY(launch_dft_residual(ctx, 1, Z0, k.r));
+  double rn = 0.0;
+  FSE_TRY(launch_norms(ctx, 1, k.r, &rn));
+  if (res_norm) *res_norm = rn;
+  const int N = k.N, nbk = (N + 255) / 256;
+  hipLaunchKernelGGL(k_scale, dim3(nbk), dim3(256), 0, ctx->stream, N, -1.0, k.r, k.b);
+  FSE_HIP(hipGetLastError());
+  if (precond && !ctx->pc_ready) FSE_TRY(kr_precond_build(k));
+  int its = 0;
+  double rel = 0.0;
+  FSE_TRY(kr_gmres(k, k.b, precond != 0, rtol, restart, maxit, &its, &rel));
+  if (gmres_iters) *gmres_iters = its;
+  if (gmres_relres) *gmres_relres = rel;
+  FSE_TRY(launch_axpby(ctx, N, 1.0, Z0, 1.0, k.x, Z0));
+  FSE_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->mf_ready = false;
   return FSE_OK;
 }
 

@@ -947,10 +947,10 @@ fse_status launch_dft_residual(fse_ctx *ctx, int B, const double *Z0, double *R)
   return launch_dft(ctx, B, ctx->zTw, Z0, R);
 }
 
-fse_status launch_dft(fse_ctx *ctx, int B, const double *zT, const double *Z0, double *R) {
+fse_status launch_dft(fse_ctx *ctx, int B, const double *zT, const double *Z0, double *R, const double *rot) {
   const int total = B * 2 * ctx->n * (ctx->L + 1);
   hipLaunchKernelGGL(k_dft_residual, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, zT,
-                     ctx->Wmax, ctx->Gi_d, ctx->rot_d, Z0, ctx->n, ctx->U, ctx->L, ctx->St, B, R);
+                     ctx->Wmax, ctx->Gi_d, rot ? rot : ctx->rot_d, Z0, ctx->n, ctx->U, ctx->L, ctx->St, B, R);
   FSE_HIP(hipGetLastError());
   return FSE_OK;
 }
