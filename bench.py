@@ -55,7 +55,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--sweep", choices=["train", "learned", "secant"],
                     help="run one phase of the 200-point shell sweep instead of the benchmark")
-    ap.add_argument("--sweep-dir", default=os.path.join(ROOT, "gpurun_out", "sweep"))
+    ap.add_argument("--sweep-dir", default=os.path.join(ROOT, "gpurun_out", "sweep"),
+                    help="where a sweep phase writes its results")
+    ap.add_argument("--sweep-in", default=None,
+                    help="where a sweep phase reads the training results (default: --sweep-dir)")
     ap.add_argument("--sweep-precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--sweep-deadline", type=float, default=1000.0,
                     help="seconds after which a sweep phase stops and saves the points it has solved")
@@ -441,15 +444,17 @@ def _sweep_params(wn, pt):
     return om, amp, np.concatenate([om, amp]), np.array([w1, SWEEP_RATIO, pt[1]])
 
 
-def run_sweep(fse, torch, phase, sweep_dir, prec_name, deadline):
+def run_sweep(fse, torch, phase, sweep_dir, sweep_in, prec_name, deadline):
     """One phase of the 200-point shell sweep; prints one JSON line.
     train:   the 100 training points with the secant predictor (point 0 from its linear harmonic
-             response); writes the converged tori (FP32) and the last two (FP64) to sweep_dir.
+             response); writes the converged tori (FP32) and the last two (FP64) to sweep_dir, and
+             resumes after the points already in sweep_in.
     learned: POD (rank 64) of the training tori, the MLP 3 -> 256 -> 256 -> 64 trained on the GPU,
              then the 100 evaluation points, each from the better of the secant and the learned
              (BF16 matrix-core inference) prediction by ||R||.
     secant:  the 100 evaluation points with the secant predictor alone.
-    Both evaluation phases start from the last two training points and solve every point to
+    The evaluation phases read the training results from sweep_in, start from the last two
+    training points and solve every point to
     ||R||_2 < 1e-8 with the same Newton-Krylov iteration with Jacobian reuse.  A phase still
     running `deadline` seconds after its start stops and reports (and saves) the points it has."""
     prec = fse.FSE_PREC_MIXED_FP32 if prec_name == "mixed" else fse.FSE_PREC_FP64
@@ -465,12 +470,12 @@ def run_sweep(fse, torch, phase, sweep_dir, prec_name, deadline):
     if phase == "train":
         pts = train
         Zs = torch.empty((len(pts), 2 * wl.system.n, ctx.U), dtype=torch.float32, device="cuda")
-        prev = os.path.join(sweep_dir, "train_mixed.json") if prec_name == "mixed" else None
-        if os.path.exists(os.path.join(sweep_dir, "train_points.npy")):
+        prev = os.path.join(sweep_in, "train_mixed.json") if prec_name == "mixed" else None
+        if os.path.exists(os.path.join(sweep_in, "train_points.npy")):
             # resume: keep the points solved by an earlier run of this phase
-            done = len(np.load(os.path.join(sweep_dir, "train_points.npy")))
-            Zs[:done].copy_(torch.from_numpy(np.load(os.path.join(sweep_dir, "train_Z_f32.npy"))))
-            last = np.load(os.path.join(sweep_dir, "train_last2.npy"))
+            done = len(np.load(os.path.join(sweep_in, "train_points.npy")))
+            Zs[:done].copy_(torch.from_numpy(np.load(os.path.join(sweep_in, "train_Z_f32.npy"))))
+            last = np.load(os.path.join(sweep_in, "train_last2.npy"))
             hist = [(_sweep_params(wn, train[done - 2])[2], torch.tensor(last[0], device="cuda")),
                     (_sweep_params(wn, train[done - 1])[2], torch.tensor(last[1], device="cuda"))]
             recs = json.load(open(prev))["records"] if prev and os.path.exists(prev) else []
@@ -482,14 +487,23 @@ def run_sweep(fse, torch, phase, sweep_dir, prec_name, deadline):
             Z = torch.tensor(Zlin, dtype=torch.float64, device="cuda")
             hist = []
     else:
-        last = np.load(os.path.join(sweep_dir, "train_last2.npy"))
-        train = np.load(os.path.join(sweep_dir, "train_points.npy"))
+        last = np.load(os.path.join(sweep_in, "train_last2.npy"))
+        train = np.load(os.path.join(sweep_in, "train_points.npy"))
         hist = [(_sweep_params(wn, train[-2])[2], torch.tensor(last[0], device="cuda")),
                 (_sweep_params(wn, train[-1])[2], torch.tensor(last[1], device="cuda"))]
         pts = evalp
+        prev = os.path.join(sweep_in, f"{phase}_{prec_name}.json")
+        if os.path.exists(prev) and os.path.exists(os.path.join(sweep_in, f"{phase}_{prec_name}_last2.npy")):
+            # resume after the evaluation points an earlier run of this phase solved
+            recs = json.load(open(prev))["records"]
+            done = len(recs)
+            last = np.load(os.path.join(sweep_in, f"{phase}_{prec_name}_last2.npy"))
+            hist = [(_sweep_params(wn, evalp[done - 2])[2], torch.tensor(last[0], device="cuda")),
+                    (_sweep_params(wn, evalp[done - 1])[2], torch.tensor(last[1], device="cuda"))]
+            progress(f"sweep {phase}: resuming after {done} points")
         lp = None
         if phase == "learned":
-            X = torch.tensor(np.load(os.path.join(sweep_dir, "train_Z_f32.npy")), device="cuda").double()
+            X = torch.tensor(np.load(os.path.join(sweep_in, "train_Z_f32.npy")), device="cuda").double()
             feats = np.array([_sweep_params(wn, p)[3] for p in train])
             lp = fse.fse_learned_create(ctx, n_in=3, hidden=256, rank=64)
             rng = np.random.default_rng(7)
@@ -547,8 +561,10 @@ def run_sweep(fse, torch, phase, sweep_dir, prec_name, deadline):
         np.save(os.path.join(sweep_dir, "train_Z_f32.npy"), Zs[:len(recs)].cpu().numpy())
         np.save(os.path.join(sweep_dir, "train_points.npy"), pts[:len(recs)])
         np.save(os.path.join(sweep_dir, "train_last2.npy"), np.stack([h[1].cpu().numpy() for h in hist]))
-    if phase == "train":
-        total += sum(r["seconds"] for r in recs[:done])   # the earlier runs' share
+    else:
+        np.save(os.path.join(sweep_dir, f"{phase}_{prec_name}_last2.npy"),
+                np.stack([h[1].cpu().numpy() for h in hist]))
+    total += sum(r["seconds"] for r in recs[:done])   # the earlier runs' share
     c = np.array([r["corrections"] for r in recs], float)
     sec = np.array([r["seconds"] for r in recs])
     out = {"metric": "Newton corrections and seconds per point to ||R||_2 < 1e-8 (shell sweep)",
@@ -584,7 +600,8 @@ def main():
     import paper_2508_06302_amd as fse
     torch.cuda.set_device(0)
     if args.sweep:
-        run_sweep(fse, torch, args.sweep, args.sweep_dir, args.sweep_precision, args.sweep_deadline)
+        run_sweep(fse, torch, args.sweep, args.sweep_dir, args.sweep_in or args.sweep_dir, args.sweep_precision,
+                  args.sweep_deadline)
         return
     sh = run_shell(fse, torch, fse.FSE_PREC_FP64, args.steps, args.warmup)
     wl, St, bw = sh["wl"], sh["St"], sh["bw"]

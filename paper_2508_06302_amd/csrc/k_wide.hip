@@ -381,12 +381,93 @@ __global__ void k_wide_predict(WideSys sy, TrajParams P, int k, const double *__
 }
 
 // r = S qh + f_nl(qh) - b for a block of rows and a group of 64 trajectories, the rows of qh the
-// block reads staged in LDS (span rows from rlo[block]).
+// block reads staged in LDS (span rows from rlo[block]).  One wave per row: the staged rows
+// (about 100 KB for the shell's band) allow one block per CU, so the block carries 16 waves.
+// The term lists of a row are wave-uniform (scalar loads); they are walked eight terms at a
+// time, all index and value loads and LDS reads of the eight issued before their products, so
+// that their latencies overlap instead of adding up term by term.  The sum runs in list order.
 constexpr int kResRows = 16;
-__global__ __launch_bounds__(256) void k_wide_resid(WideSys sy, const int32_t *__restrict__ rlo, int span,
-                                                    const double *__restrict__ qh, const double *__restrict__ bk,
-                                                    double *__restrict__ r, const int32_t *__restrict__ conv,
-                                                    const int32_t *__restrict__ ctl) {
+constexpr int kResThreads = 64 * kResRows;
+constexpr int kTermBatch = 8;
+
+// The term lists never change while a kernel runs; read through the constant address space, a
+// wave-uniform address compiles to scalar loads (the barrier before the row loop would otherwise
+// keep the compiler from proving them unclobbered, and it would use vector loads).
+template <class T>
+using const_as = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ __forceinline__ const_as<T> as_const(const T *p) {
+  return (const_as<T>)p;
+}
+
+__device__ __forceinline__ double res_lin(const_as<double> val, const_as<int32_t> ci, int p, int e,
+                                          const double *__restrict__ sq, int lo, int lane, double v) {
+  for (; p + kTermBatch <= e; p += kTermBatch) {
+    double a[kTermBatch], x[kTermBatch];
+    int c[kTermBatch];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) c[t] = ci[p + t];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) a[t] = val[p + t];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) x[t] = sq[(c[t] - lo) * kLanes + lane];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) v += a[t] * x[t];
+  }
+  for (; p < e; ++p) v += val[p] * sq[(ci[p] - lo) * kLanes + lane];
+  return v;
+}
+
+__device__ __forceinline__ double res_quad(const_as<double> val, const_as<int32_t> jk, int p, int e,
+                                           const double *__restrict__ sq, int lo, int lane, double v) {
+  for (; p + kTermBatch <= e; p += kTermBatch) {
+    double a[kTermBatch], x[kTermBatch], y[kTermBatch];
+    int c[2 * kTermBatch];
+#pragma unroll
+    for (int t = 0; t < 2 * kTermBatch; ++t) c[t] = jk[2 * p + t];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) a[t] = val[p + t];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) {
+      x[t] = sq[(c[2 * t] - lo) * kLanes + lane];
+      y[t] = sq[(c[2 * t + 1] - lo) * kLanes + lane];
+    }
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) v += a[t] * x[t] * y[t];
+  }
+  for (; p < e; ++p) v += val[p] * sq[(jk[2 * p] - lo) * kLanes + lane] * sq[(jk[2 * p + 1] - lo) * kLanes + lane];
+  return v;
+}
+
+__device__ __forceinline__ double res_cub(const_as<double> val, const_as<int32_t> jkl, int p, int e,
+                                          const double *__restrict__ sq, int lo, int lane, double v) {
+  for (; p + kTermBatch <= e; p += kTermBatch) {
+    double a[kTermBatch], x[kTermBatch], y[kTermBatch], z[kTermBatch];
+    int c[3 * kTermBatch];
+#pragma unroll
+    for (int t = 0; t < 3 * kTermBatch; ++t) c[t] = jkl[3 * p + t];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) a[t] = val[p + t];
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) {
+      x[t] = sq[(c[3 * t] - lo) * kLanes + lane];
+      y[t] = sq[(c[3 * t + 1] - lo) * kLanes + lane];
+      z[t] = sq[(c[3 * t + 2] - lo) * kLanes + lane];
+    }
+#pragma unroll
+    for (int t = 0; t < kTermBatch; ++t) v += a[t] * x[t] * y[t] * z[t];
+  }
+  for (; p < e; ++p)
+    v += val[p] * sq[(jkl[3 * p] - lo) * kLanes + lane] * sq[(jkl[3 * p + 1] - lo) * kLanes + lane] *
+         sq[(jkl[3 * p + 2] - lo) * kLanes + lane];
+  return v;
+}
+
+__global__ __launch_bounds__(kResThreads) void k_wide_resid(WideSys sy, const int32_t *__restrict__ rlo, int span,
+                                                            const double *__restrict__ qh,
+                                                            const double *__restrict__ bk, double *__restrict__ r,
+                                                            const int32_t *__restrict__ conv,
+                                                            const int32_t *__restrict__ ctl) {
   extern __shared__ double sq[];
   if (ctl[1]) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -399,19 +480,24 @@ __global__ __launch_bounds__(256) void k_wide_resid(WideSys sy, const int32_t *_
     sq[e] = (j < sy.n && ww < sy.W) ? qh[(size_t)j * ld + ww] : 0.0;
   }
   __syncthreads();
-  const int b = (w < sy.W ? w : sy.W - 1) / sy.St;
-  const double *Sv = sy.Sv + (size_t)b * sy.nnz;
-  for (int ii = i0 + wv; ii < i0 + kResRows && ii < sy.n; ii += 4) {
-    const int i = __builtin_amdgcn_readfirstlane(ii);  // wave-uniform: index lists load as scalars
-    double v = 0.0;
-    for (int p = sy.rp[i]; p < sy.rp[i + 1]; ++p) v += Sv[p] * sq[(sy.ci[p] - lo) * kLanes + lane];
-    for (int p = sy.f2_ptr[i]; p < sy.f2_ptr[i + 1]; ++p)
-      v += sy.f2_v[p] * sq[(sy.f2_jk[2 * p] - lo) * kLanes + lane] * sq[(sy.f2_jk[2 * p + 1] - lo) * kLanes + lane];
-    for (int p = sy.f3_ptr[i]; p < sy.f3_ptr[i + 1]; ++p)
-      v += sy.f3_v[p] * sq[(sy.f3_jkl[3 * p] - lo) * kLanes + lane] *
-           sq[(sy.f3_jkl[3 * p + 1] - lo) * kLanes + lane] * sq[(sy.f3_jkl[3 * p + 2] - lo) * kLanes + lane];
-    if (w < sy.W) r[(size_t)i * ld + w] = v - bk[(size_t)i * ld + w];
+  const int i = __builtin_amdgcn_readfirstlane(i0 + wv);  // wave-uniform: index lists load as scalars
+  if (i >= sy.n) return;
+  // the point of this group's trajectories: uniform over the wave whenever S~ is a multiple of 64
+  const int b = __builtin_amdgcn_readfirstlane((w0 < sy.W ? w0 : sy.W - 1) / sy.St);
+  const int bl = (w < sy.W ? w : sy.W - 1) / sy.St;
+  const_as<int32_t> rp = as_const(sy.rp), p2 = as_const(sy.f2_ptr), p3 = as_const(sy.f3_ptr);
+  double v;
+  if (__builtin_amdgcn_ballot_w64(bl != b) == 0) {
+    v = res_lin(as_const(sy.Sv + (size_t)b * sy.nnz), as_const(sy.ci), rp[i], rp[i + 1], sq, lo, lane, 0.0);
+  } else {
+    // trajectories of two points in one group: the step-matrix values per lane
+    const double *Sv = sy.Sv + (size_t)bl * sy.nnz;
+    v = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) v += Sv[p] * sq[(sy.ci[p] - lo) * kLanes + lane];
   }
+  v = res_quad(as_const(sy.f2_v), as_const(sy.f2_jk), p2[i], p2[i + 1], sq, lo, lane, v);
+  v = res_cub(as_const(sy.f3_v), as_const(sy.f3_jkl), p3[i], p3[i + 1], sq, lo, lane, v);
+  if (w < sy.W) r[(size_t)i * ld + w] = v - bk[(size_t)i * ld + w];
 }
 
 // dq = S^-1 r per point (FP64 matrix cores: one wave per 16 rows x 16 trajectories, K = n),
@@ -422,7 +508,11 @@ __global__ __launch_bounds__(256) void k_wide_resid(WideSys sy, const int32_t *_
 // longer halves).  No geometric extrapolation from the ratio of successive updates: with a lumped
 // mass whose entries span orders of magnitude, S^-1 K_t is far from normal and that ratio
 // underestimates the next update.
-__global__ __launch_bounds__(256) void k_wide_chord(int n, int W, int St, int ldw, int ntile_pt,
+constexpr int kChordKSplit = 4;                    // waves per 16 x 16 tile, one K range each
+constexpr int kChordThreads = 256 * kChordKSplit;  // 4 row blocks x kChordKSplit waves
+constexpr int kChordBatch = 8;                     // K steps whose loads are issued together
+
+__global__ __launch_bounds__(kChordThreads) void k_wide_chord(int n, int W, int St, int ldw, int ntile_pt,
                                                     const double *__restrict__ Sinv, const double *__restrict__ r,
                                                     double *__restrict__ qh, unsigned long long *__restrict__ acc,
                                                     int32_t *__restrict__ conv, double *__restrict__ ndprev,
@@ -430,24 +520,57 @@ __global__ __launch_bounds__(256) void k_wide_chord(int n, int W, int St, int ld
                                                     int k, double tol, DevStatus *st) {
   if (ctl[1]) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rsub = wv & 3, kc = wv >> 2;                 // row block within the block, K range
   const int b = blockIdx.y / ntile_pt, ct = blockIdx.y - b * ntile_pt;
   const int col = ct * 16 + (lane & 15);                 // trajectory within the point
   const int w = b * St + col;
   const bool valid = col < St && w < W;
   const bool act = valid && !conv[w];
   unsigned long long *accA = acc + (size_t)(it & 1) * 2 * ldw;
-  const int rb = blockIdx.x * 4 + wv;                    // 16-row block of this wave
-  if (__syncthreads_or(act)) {
+  const int rb = blockIdx.x * 4 + rsub;                  // 16-row block of this wave
+  __shared__ f64x4 part[kChordKSplit - 1][4][64];        // partial tiles of K ranges 1..
+  const bool any = __syncthreads_or(act);
+  f64x4 c = {0.0, 0.0, 0.0, 0.0};
+  if (any) {
     const double *A = Sinv + (size_t)b * n * n;
-    f64x4 c = {0.0, 0.0, 0.0, 0.0};
     const int arow = rb * 16 + (lane & 15);
     const bool arow_ok = arow < n;
-    for (int k0 = 0; k0 < n; k0 += 4) {
-      const int kk = k0 + (lane >> 4);
-      // S^-1 is symmetric: A[arow][kk] is read as A[kk][arow] (16 consecutive rows per k)
-      const double av = (arow_ok && kk < n) ? A[(size_t)kk * n + arow] : 0.0;
-      const double bv = (valid && kk < n) ? r[(size_t)kk * ldw + w] : 0.0;
+    // clamped indices: every load is in bounds and unconditional, operands outside are zeroed
+    const int arc = min(arow, n - 1), wc = min(w, W - 1);
+    const int nk = (n + 3) / 4, per = (nk + kChordKSplit - 1) / kChordKSplit;
+    const int s1 = min(nk, (kc + 1) * per);
+    int ks = kc * per;
+    // S^-1 is symmetric: A[arow][kk] is read as A[kk][arow] (16 consecutive rows per k)
+    for (; ks + kChordBatch <= s1; ks += kChordBatch) {
+      double av[kChordBatch], bv[kChordBatch];
+#pragma unroll
+      for (int t = 0; t < kChordBatch; ++t) {
+        const int kk = 4 * (ks + t) + (lane >> 4), kq = min(kk, n - 1);
+        av[t] = A[(size_t)kq * n + arc];
+        bv[t] = r[(size_t)kq * ldw + wc];
+        if (!(arow_ok && kk < n)) av[t] = 0.0;
+        if (!(valid && kk < n)) bv[t] = 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < kChordBatch; ++t) c = mma(av[t], bv[t], c);
+    }
+    for (; ks < s1; ++ks) {
+      const int kk = 4 * ks + (lane >> 4), kq = min(kk, n - 1);
+      double av = A[(size_t)kq * n + arc], bv = r[(size_t)kq * ldw + wc];
+      if (!(arow_ok && kk < n)) av = 0.0;
+      if (!(valid && kk < n)) bv = 0.0;
       c = mma(av, bv, c);
+    }
+    if (kc > 0) part[kc - 1][rsub][lane] = c;
+  }
+  __syncthreads();
+  if (any && kc == 0) {
+    // the K ranges in order
+#pragma unroll
+    for (int q = 0; q < kChordKSplit - 1; ++q) {
+      const f64x4 pq = part[q][rsub][lane];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) c[v] += pq[v];
     }
     double md = 0.0, mq = 0.0;
 #pragma unroll
@@ -938,9 +1061,9 @@ fse_status wide_state_pass(fse_ctx *ctx, int B, int budget) {
     hipLaunchKernelGGL(k_wide_predict, g2, dim3(64), 0, ctx->stream, sy, P, k, ctx->omega_d, ctx->sidx_d,
                        ctx->Sdim_d, q, ws->u, ws->a, ws->bk, ws->qh, ws->acc, ws->conv, ws->ndprev, ws->ctl);
     for (int it = 0; it < budget; ++it) {
-      hipLaunchKernelGGL(k_wide_resid, gr, dim3(256), rl, ctx->stream, sy, ws->rlo, ws->span_r, ws->qh,
+      hipLaunchKernelGGL(k_wide_resid, gr, dim3(kResThreads), rl, ctx->stream, sy, ws->rlo, ws->span_r, ws->qh,
                          ws->bk, ws->r, ws->conv, ws->ctl);
-      hipLaunchKernelGGL(k_wide_chord, gc, dim3(256), 0, ctx->stream, n, W, ctx->St, ld, ntile_pt, ws->Sinv,
+      hipLaunchKernelGGL(k_wide_chord, gc, dim3(kChordThreads), 0, ctx->stream, n, W, ctx->St, ld, ntile_pt, ws->Sinv,
                          ws->r, ws->qh, ws->acc, ws->conv, ws->ndprev, ws->ctl, it, budget - 1,
                          (int)(budget >= ctx->maxit), k, ctx->tol, ctx->status_d);
     }

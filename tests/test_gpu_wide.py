@@ -156,12 +156,26 @@ def _c3_state_tol():
     return max(RTOL, 10.0 * max(vals))
 
 
+def _fp32_phi_bar(wl):
+    """A priori bound on the relative error of FP32 sensitivities over one period: the FP32
+    banded LDL^T solve of an SPD step matrix errs by about u32 kappa_s per step, with kappa_s the
+    2-norm condition number of the diagonally scaled step matrix (the unscaled one, 6.8e3 on the
+    shell, reflects only the spread of the lumped masses); summed linearly over the S1 steps, with
+    a factor 4 for the two triangular solves and the two recursion updates of each step."""
+    h = 2 * np.pi / wl.torus.S1                     # average acceleration: c0 = 4 / h^2, c2 = 2 / h
+    w1, sysm = wl.omega[0], wl.system
+    S = w1 ** 2 * (4 / h ** 2) * sysm.M + w1 * (2 / h) * sysm.D + sysm.K
+    dinv = 1.0 / np.sqrt(np.diag(S))
+    ev = np.linalg.eigvalsh(S * dinv[:, None] * dinv[None, :])
+    return 4.0 * wl.torus.S1 * 2.0 ** -24 * ev[-1] / ev[0]
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_c3_full_size_sampled(prec):
     """The 1872-DOF shell at full size (128 trajectories, S1 = 1024, all 3744 sensitivity
     columns): states and sampled sensitivity columns of three trajectories against the oracle
     (stored values).  States within the measured conditioning bar of _c3_state_tol (5.2e-10),
-    sensitivity columns 1e-9 (FP64) or 1e-4 (mixed)."""
+    sensitivity columns 1e-9 (FP64) or the a priori FP32 bound of _fp32_phi_bar (mixed, 9.8e-4)."""
     import torch
     gold, cols = _golden_c3()
     stol = _c3_state_tol()
@@ -174,7 +188,8 @@ def test_c3_full_size_sampled(prec):
     tm = fse().fse_last_timing(ctx)
     log(f"C3 timing {tm}")
     n = wl.system.n
-    ptol = 1e-9 if prec == 0 else 1e-4
+    ptol = 1e-9 if prec == 0 else _fp32_phi_bar(wl)
+    log(f"sensitivity bar {ptol:.2e}")
     for s, (zg, pg) in gold.items():
         z = zT[0, :, s].cpu().numpy()
         p = phi[0, s][:, cols].cpu().numpy()
