@@ -373,6 +373,7 @@ SWEEP_W = (0.93, 0.97)       # omega_1 / omega_n (first natural frequency 100 Hz
 SWEEP_A = (6.0, 14.0)        # forcing amplitude scale a: loads 40 a and 20 a N
 SWEEP_RATIO = 2 ** -0.5      # omega_2 / omega_1
 SWEEP_TOL = 1e-8
+SWEEP_EPOCHS = 10000         # full-batch AdamW steps of the predictor's training
 
 
 def sweep_points():
@@ -449,7 +450,8 @@ def run_sweep(fse, torch, phase, sweep_dir, sweep_in, prec_name, deadline):
     train:   the 100 training points with the secant predictor (point 0 from its linear harmonic
              response); writes the converged tori (FP32) and the last two (FP64) to sweep_dir, and
              resumes after the points already in sweep_in.
-    learned: POD (rank 64) of the training tori, the MLP 3 -> 256 -> 256 -> 64 trained on the GPU,
+    learned: POD (rank 64) of the training tori, the MLP 3 -> 256 -> 256 -> 64 trained on the GPU
+             (SWEEP_EPOCHS steps),
              then the 100 evaluation points, each from the better of the secant and the learned
              (BF16 matrix-core inference) prediction by ||R||.
     secant:  the 100 evaluation points with the secant predictor alone.
@@ -513,7 +515,7 @@ def run_sweep(fse, torch, phase, sweep_dir, sweep_in, prec_name, deadline):
             lp.set_params(np.concatenate(params).astype(np.float32))
             t0 = time.perf_counter()
             sig = lp.fit_pod(X)
-            loss = lp.train(feats, X, epochs=3000, lr=1e-3, wd=1e-5)
+            loss = lp.train(feats, X, epochs=SWEEP_EPOCHS, lr=1e-3, wd=1e-5)
             torch.cuda.synchronize()
             t_train = time.perf_counter() - t0
             mean, modes = lp.get_pod()

@@ -393,8 +393,10 @@ fse_status fse_learned_fit(fse_learned *m, int32_t B, const float *x, const floa
                            double lr, double wd, double *loss_hist);
 
 /* Trains on m_snap points: params P HOST [m_snap][n_in] (FP64), snapshots X device
- * [m_snap][N] (the ones given to fse_learned_fit_pod).  Inputs and POD coefficients are
- * standardised with the training set's mean and deviation; full-batch AdamW (lr,
+ * [m_snap][N] (the ones given to fse_learned_fit_pod).  Inputs are standardised per component
+ * with the training set's mean and deviation; the POD coefficients are centred and divided by
+ * one common scale, the RMS deviation of the snapshots from their mean, so that the loss is the
+ * mean squared error of Z(0) in the POD subspace (the modes are orthonormal); full-batch AdamW (lr,
  * beta 0.9 / 0.999, eps 1e-8, decoupled weight decay wd) for `epochs` steps.
  * loss_hist (HOST, may be NULL): [epochs] training loss in normalised units. */
 fse_status fse_learned_train(fse_learned *m, int32_t m_snap, const double *P, const double *X,

@@ -250,6 +250,9 @@ fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // solve with the factor for one right-hand side (in place; enqueued, no synchronisation)
 fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv);
 fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs);
+// `count` independent systems of one size: system z at A + z sA, pivots piv + z sp, rhs + z sx
+fse_status dense_lu_apply_batched(fse_ctx *ctx, const double *A, size_t sA, int N, const int32_t *piv,
+                                  size_t sp, double *rhs, size_t sx, int count);
 fse_status launch_axpby(fse_ctx *ctx, int N, double a, const double *x, double b, const double *z, double *y);
 fse_status launch_axpy(fse_ctx *ctx, int N, double alpha, const double *x, double *y);
 fse_status launch_lincomb(fse_ctx *ctx, int N, const double *x, double alpha, const double *d, double *y);

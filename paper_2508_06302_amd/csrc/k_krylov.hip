@@ -330,9 +330,12 @@ fse_status kr_precond_apply(const Krylov &k, const double *v, double *out) {
   hipLaunchKernelGGL(k_pc_gather, dim3(nbk), dim3(nth), 0, ctx->stream, const_cast<double *>(v), k.n2, k.U, k.bv,
                      0);
   FSE_HIP(hipGetLastError());
-  for (int l = 0; l <= k.L; ++l) {
-    const int m = l == 0 ? k.n2 : 2 * k.n2;
-    FSE_TRY(dense_lu_apply(ctx, k.blocks + block_off(k, l), m, k.piv + vec_off(k, l), k.bv + vec_off(k, l)));
+  // the zero-harmonic block, then the L harmonic-pair blocks (one size, evenly spaced) as a batch
+  FSE_TRY(dense_lu_apply(ctx, k.blocks, k.n2, k.piv, k.bv));
+  if (k.L > 0) {
+    const size_t m = 2 * (size_t)k.n2;
+    FSE_TRY(dense_lu_apply_batched(ctx, k.blocks + block_off(k, 1), m * m, (int)m, k.piv + vec_off(k, 1), m,
+                                   k.bv + vec_off(k, 1), m, k.L));
   }
   hipLaunchKernelGGL(k_pc_gather, dim3(nbk), dim3(nth), 0, ctx->stream, out, k.n2, k.U, k.bv, 1);
   FSE_HIP(hipGetLastError());

@@ -605,7 +605,12 @@ fse_status fse_learned_train(fse_learned *m, int32_t m_snap, const double *P, co
   std::vector<double> c((size_t)ms * R);
   FSE_HIP(hipMemcpyAsync(c.data(), m->coef, sizeof(double) * c.size(), hipMemcpyDeviceToHost, s));
   FSE_HIP(hipStreamSynchronize(s));
-  // standardisation (unit deviation; components without spread keep deviation 1)
+  // Inputs: unit deviation per component (components without spread keep deviation 1).
+  // Coefficients: centred and divided by one common scale, the RMS deviation of the training
+  // snapshots from their mean (sqrt of the summed coefficient variances).  The modes are
+  // orthonormal, so the training loss is then the mean squared error of the predicted Z(0) in the
+  // POD subspace; a scale per coefficient would weight a mode that carries 1e-6 of the variance
+  // like the leading one.
   m->mu_p.assign(nin, 0.0);
   m->sd_p.assign(nin, 0.0);
   m->mu_c.assign(R, 0.0);
@@ -624,8 +629,11 @@ fse_status fse_learned_train(fse_learned *m, int32_t m_snap, const double *P, co
       const double dv = c[(size_t)j * R + r] - m->mu_c[r];
       m->sd_c[r] += dv * dv / ms;
     }
-  for (auto *v : {&m->sd_p, &m->sd_c})
-    for (double &x : *v) x = (x > 0.0) ? std::sqrt(x) : 1.0;
+  for (double &x : m->sd_p) x = (x > 0.0) ? std::sqrt(x) : 1.0;
+  double var_c = 0.0;
+  for (double x : m->sd_c) var_c += x;
+  const double sc = var_c > 0.0 ? std::sqrt(var_c) : 1.0;
+  for (double &x : m->sd_c) x = sc;
   std::vector<float> xf((size_t)ms * nin), tf((size_t)ms * R);
   for (int j = 0; j < ms; ++j) {
     for (int k = 0; k < nin; ++k)

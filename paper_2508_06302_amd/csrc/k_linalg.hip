@@ -283,10 +283,14 @@ __global__ __launch_bounds__(256) void k_lu_gemm(double *__restrict__ B, int N, 
 
 // Blocked triangular solves with the factors of B (row i of U^T and of L^T is contiguous:
 // memory row i).  y[r0:r0+nb] -= M[r0:r0+nb, cols] x[cols] for the already solved
-// columns, one wave per row.
+// columns, one wave per row.  The solve kernels take a batch of independent systems of one
+// size, system z at A + z sA, its vectors at x + z sx and its pivots at piv + z sp.
 __global__ __launch_bounds__(256) void k_lu_gemv(const double *__restrict__ A, int N, int r0, int nb,
                                                  int c0, int c1, const double *__restrict__ x,
-                                                 double *__restrict__ y) {
+                                                 double *__restrict__ y, size_t sA, size_t sx) {
+  A += blockIdx.y * sA;
+  x += blockIdx.y * sx;
+  y += blockIdx.y * sx;
   const int lane = threadIdx.x & 63;
   const int r = r0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= r0 + nb) return;
@@ -300,7 +304,9 @@ __global__ __launch_bounds__(256) void k_lu_gemv(const double *__restrict__ A, i
 // Diagonal block of the substitution, one wave: forward (upper = false: U^T with its
 // diagonal) or backward (upper = true: unit L^T) over rows [r0, r0+nb), nb <= 64.
 __global__ __launch_bounds__(64) void k_lu_diag(const double *__restrict__ A, int N, int r0, int nb,
-                                                bool upper, double *__restrict__ y) {
+                                                bool upper, double *__restrict__ y, size_t sA, size_t sx) {
+  A += blockIdx.x * sA;
+  y += blockIdx.x * sx;
   const int lane = threadIdx.x;
   double x = lane < nb ? y[r0 + lane] : 0.0;
   if (!upper) {
@@ -326,8 +332,10 @@ __global__ __launch_bounds__(64) void k_lu_diag(const double *__restrict__ A, in
 constexpr int kUnpermLds = 16384;
 
 __global__ __launch_bounds__(1024) void k_lu_unpermute(double *__restrict__ x, int N,
-                                                       const int32_t *__restrict__ piv) {
+                                                       const int32_t *__restrict__ piv, size_t sx, size_t sp) {
   extern __shared__ double xs[];
+  x += blockIdx.x * sx;
+  piv += blockIdx.x * sp;
   if (N <= kUnpermLds) {
     // the two memories get separate code so that no pointer may point to either
     for (int i = threadIdx.x; i < N; i += blockDim.x) xs[i] = x[i];
@@ -583,30 +591,37 @@ fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv) {
   return FSE_OK;
 }
 
-fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs) {
-  // U^T v = r (forward, memory rows), then L^T w = v (backward), then x = Pi^T w
+fse_status dense_lu_apply_batched(fse_ctx *ctx, const double *A, size_t sA, int N, const int32_t *piv,
+                                  size_t sp, double *rhs, size_t sx, int count) {
+  if (count < 1) return FSE_OK;
+  // U^T v = r (forward, memory rows), then L^T w = v (backward), then x = Pi^T w; every launch
+  // covers the `count` systems at once
   for (int r0 = 0; r0 < N; r0 += 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
     if (r0 > 0)
-      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4), dim3(256), 0, ctx->stream, A, N, r0, nb, 0, r0,
-                         rhs, rhs);
-    hipLaunchKernelGGL(k_lu_diag, dim3(1), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs);
+      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, 0, r0,
+                         rhs, rhs, sA, sx);
+    hipLaunchKernelGGL(k_lu_diag, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs, sA, sx);
   }
   const int last = ((N - 1) / 64) * 64;
   for (int r0 = last; r0 >= 0; r0 -= 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
     if (r0 + nb < N)
-      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4), dim3(256), 0, ctx->stream, A, N, r0, nb, r0 + nb, N,
-                         rhs, rhs);
-    hipLaunchKernelGGL(k_lu_diag, dim3(1), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs);
+      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, r0 + nb,
+                         N, rhs, rhs, sA, sx);
+    hipLaunchKernelGGL(k_lu_diag, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs, sA, sx);
   }
   const size_t lds = N <= kUnpermLds ? sizeof(double) * N : 0;
   if (lds > 64 * 1024)
     FSE_HIP(hipFuncSetAttribute((const void *)k_lu_unpermute, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(sizeof(double) * kUnpermLds)));
-  hipLaunchKernelGGL(k_lu_unpermute, dim3(1), dim3(1024), lds, ctx->stream, rhs, N, piv);
+  hipLaunchKernelGGL(k_lu_unpermute, dim3(count), dim3(1024), lds, ctx->stream, rhs, N, piv, sx, sp);
   FSE_HIP(hipGetLastError());
   return FSE_OK;
+}
+
+fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs) {
+  return dense_lu_apply_batched(ctx, A, 0, N, piv, 0, rhs, 0, 1);
 }
 
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
