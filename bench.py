@@ -400,32 +400,50 @@ def sweep_points():
 def chord_solve(fse, torch, ctx, om, Z, st, rate=0.25, max_steps=30, rtol=1e-4):
     """Newton-Krylov with Jacobian reuse for one point (omega host [2], Z torch [2n][U] in place):
     chord steps with the stored Jacobian, and a full Newton-Krylov step (new sensitivities) when
-    none is stored, when the last step contracted ||R|| by less than `rate`, or when ||R|| grew.
-    Stops at the first iterate with ||R||_2 < SWEEP_TOL, which is the one returned.
-    -> (corrections, of which full Newton steps, final ||R||)."""
+    none is stored or when the last step contracted ||R|| by less than `rate`.  When a step does
+    not lower ||R||_2 by 1 % below the best iterate so far, the next step is a full Newton step from
+    that best iterate; if its update does not lower it either, the point ends there (not
+    converged, Z = the best iterate).  Stops at the first iterate with ||R||_2 < SWEEP_TOL, which
+    is the one returned.  -> (corrections, of which full Newton steps, final ||R||, converged)."""
     Zk = torch.empty_like(Z)
+    Zb = torch.empty_like(Z)
     its = refr = 0
-    prev = None
+    prev, best = None, np.inf
+    redo = from_best = False
     refresh = not st.get("have_J", False)
+    st["gmres"] = []
     while True:
         Zk.copy_(Z)
         if refresh:
-            rn, _, _ = fse.fse_newton_krylov_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
+            rn, g, _ = fse.fse_newton_krylov_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
             st["have_J"] = True
             refr += 1
         else:
-            rn, _, _ = fse.fse_newton_krylov_chord_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
+            rn, g, _ = fse.fse_newton_krylov_chord_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
+        st["gmres"].append(("full" if refresh else "chord", int(g)))
+        progress(f"  {'full' if refresh else 'chord'} step: ||R|| {rn:.3e} before, {g} GMRES iterations")
         if rn < SWEEP_TOL:
             Z.copy_(Zk)
-            return its, refr - (1 if refresh else 0), rn
+            return its, refr - (1 if refresh else 0), rn, True
         if its >= max_steps or not np.isfinite(rn):
-            raise RuntimeError(f"no convergence at omega {om}: ||R|| {rn:.3e} after {its} corrections")
-        refresh = prev is not None and rn > rate * prev
-        if prev is not None and rn > prev:
-            Z.copy_(Zk)          # the last correction made things worse: redo it with a new Jacobian
-            rn = prev
+            Z.copy_(Zb)
+            return its, refr - (1 if refresh else 0), best, False
+        if redo:
+            # a full step from the best iterate (whose residual this is): judge its update next
+            redo, from_best, refresh = False, True, False
+        elif rn < 0.99 * best:
+            best, from_best = rn, False
+            Zb.copy_(Zk)
+            refresh = prev is not None and rn > rate * prev
+            prev = rn
+        elif from_best:
+            # not even a fresh Newton step from the best iterate lowers ||R||: the floor is here
+            Z.copy_(Zb)
+            return its, refr - (1 if refresh else 0), best, False
+        else:
+            Z.copy_(Zb)
+            redo, refresh = True, True
         its += 1
-        prev = rn
 
 
 def _sweep_ctx(fse, torch, prec):
@@ -547,10 +565,10 @@ def run_sweep(fse, torch, phase, sweep_dir, sweep_in, prec_name, deadline):
             rec["learned_used"] = bool(np.isfinite(rl[0]) and rl[0] < rs[0])
             if rec["learned_used"]:
                 Z = Zl
-        its, full, rn = chord_solve(fse, torch, ctx, om, Z, st)
+        its, full, rn, ok = chord_solve(fse, torch, ctx, om, Z, st)
         torch.cuda.synchronize()
-        rec.update({"corrections": its, "full_newton_steps": full, "R_final": rn,
-                    "seconds": time.perf_counter() - t0})
+        rec.update({"corrections": its, "full_newton_steps": full, "R_final": rn, "converged": ok,
+                    "seconds": time.perf_counter() - t0, "gmres": st["gmres"]})
         recs.append(rec)
         if phase == "train":
             Zs[j].copy_(Z)
@@ -575,6 +593,7 @@ def run_sweep(fse, torch, phase, sweep_dir, sweep_in, prec_name, deadline):
            "full_newton_steps_per_point": float(np.mean([r["full_newton_steps"] for r in recs])),
            "seconds_per_point": float(sec.mean()), "seconds_total": float(sec.sum()), "wall_s": total,
            "max_final_residual": float(max(r["R_final"] for r in recs)),
+           "not_converged": int(sum(1 for r in recs if not r.get("converged", True))),
            "config": {"workload": "synthetic shell 1872 DOF, d=2, 128 trajectories, H=20, S1=1024",
                       "box": {"omega1_over_omega_n": SWEEP_W, "a": SWEEP_A, "omega2_over_omega1": SWEEP_RATIO}},
            "records": recs}
