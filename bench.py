@@ -400,7 +400,8 @@ def sweep_points():
 def chord_solve(fse, torch, ctx, om, Z, st, rate=0.25, max_steps=30, rtol=1e-4):
     """Newton-Krylov with Jacobian reuse for one point (omega host [2], Z torch [2n][U] in place):
     chord steps with the stored Jacobian, and a full Newton-Krylov step (new sensitivities) when
-    none is stored or when the last step contracted ||R|| by less than `rate`.  When a step does
+    none is stored or when the last step contracted ||R|| by less than `rate` (after a check of
+    ||R|| from the states alone, so that no sensitivities are computed at a converged iterate).  When a step does
     not lower ||R||_2 by 1 % below the best iterate so far, the next step is a full Newton step from
     that best iterate; if its update does not lower it either, the point ends there (not
     converged, Z = the best iterate).  Stops at the first iterate with ||R||_2 < SWEEP_TOL, which
@@ -414,6 +415,13 @@ def chord_solve(fse, torch, ctx, om, Z, st, rate=0.25, max_steps=30, rtol=1e-4):
     st["gmres"] = []
     while True:
         Zk.copy_(Z)
+        if refresh and st.get("have_J", False):
+            # a refresh costs a sensitivity evaluation: first see, from the states alone, whether
+            # the iterate has already converged
+            _, rc, _ = fse.fse_shooting_residual_jacobian(ctx, np.asarray(om)[None], Z[None])
+            progress(f"  check: ||R|| {rc[0]:.3e}")
+            if rc[0] < SWEEP_TOL:
+                return its, refr, float(rc[0]), True
         if refresh:
             rn, g, _ = fse.fse_newton_krylov_step(ctx, om, Z, rtol=rtol, restart=30, maxit=120)
             st["have_J"] = True
