@@ -423,7 +423,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->G_d, ctx->Gi_d, ctx->sidx_d, ctx->Sdim_d, ctx->ktable_d, ctx->omega_d,
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->rot_mf, ctx->work_R, ctx->Zwork, ctx->Jw,
-                  ctx->piv_d, ctx->lu_scr, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
+                  ctx->piv_d, ctx->lu_scr, ctx->lu32, ctx->ir, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
                   ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult,
                   ctx->ct_ptr, ctx->ct_idx, ctx->ct_c, ctx->uhist, ctx->cn_ptr, ctx->cn_v};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);
@@ -743,7 +743,7 @@ fse_status fse_newton_step(fse_ctx *ctx, double *omega, double *Z0, double *res_
   FSE_TRY(newton_system(ctx, omega, Z0, ctx->Jw, rhs, &rn));
   if (res_norm) *res_norm = rn;
   // [J dRu; P 0] x = [R; 0], then Z0 -= x_Z, omega_u -= x_omega
-  FSE_TRY(dense_lu_solve(ctx, ctx->Jw, Nb, rhs));
+  FSE_TRY(newton_dense_solve(ctx, ctx->Jw, Nb, rhs));
   FSE_TRY(launch_axpy(ctx, N, -1.0, rhs, Z0));
   if (nu > 0) {
     std::vector<double> xw(nu);
@@ -774,7 +774,7 @@ fse_status fse_newton_solve(fse_ctx *ctx, double *omega, double *Z0, double tol,
       FSE_TRY(newton_system(ctx, om.data(), Z0, ctx->Jw, rhs, &r0));
     }
     // rhs <- (Newton matrix)^-1 [R; 0]; the Newton direction is its negative
-    FSE_TRY(dense_lu_solve(ctx, ctx->Jw, Nb, rhs));
+    FSE_TRY(newton_dense_solve(ctx, ctx->Jw, Nb, rhs));
     have_J = false;
     if (nu > 0) {
       FSE_HIP(hipMemcpyAsync(xw.data(), rhs + N, sizeof(double) * nu, hipMemcpyDeviceToHost, ctx->stream));
@@ -1052,7 +1052,7 @@ fse_status arc_corrector(fse_ctx *ctx, const double *omega_ref, double *X, const
       ctx->err = "arclength corrector did not reach the residual tolerance";
       return FSE_E_NOCONV;
     }
-    FSE_TRY(dense_lu_solve(ctx, A, Na, rhs));
+    FSE_TRY(newton_dense_solve(ctx, A, Na, rhs));
     FSE_TRY(launch_axpy(ctx, Na, -1.0, rhs, X));
   }
 }
@@ -1065,7 +1065,7 @@ fse_status arc_tangent(fse_ctx *ctx, double *A, double *y, double *t) {
   FSE_HIP(hipMemsetAsync(y, 0, sizeof(double) * Na, ctx->stream));
   FSE_HIP(hipMemcpyAsync(y + Na - 1, &one, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   FSE_HIP(hipStreamSynchronize(ctx->stream));
-  FSE_TRY(dense_lu_solve(ctx, A, Na, y));
+  FSE_TRY(newton_dense_solve(ctx, A, Na, y));
   double nrm = 0.0;
   FSE_TRY(launch_norm(ctx, y, (size_t)Na, &nrm));
   if (!(nrm > 0.0) || !std::isfinite(nrm)) {

@@ -119,6 +119,11 @@ struct fse_ctx {
   std::vector<double> amp;      // forcing amplitudes [e]
   int32_t *piv_d = nullptr;
   int piv_n = 0;
+  float *lu32 = nullptr;            // FP32 factor + one FP32 vector (mixed-precision dense solve)
+  size_t lu32_elems = 0;
+  double *ir = nullptr;             // refinement vectors b, x, r
+  size_t ir_elems = 0;
+  int last_refine = 0;              // refinement steps of the last mixed dense solve (-1: FP64 used)
   double *lu_scr = nullptr;
   double *norm_d = nullptr;         // [Bmax] squared residual norms
   double *jacP = nullptr;           // [S~][U][U] Jacobian right factor
@@ -250,6 +255,10 @@ fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // solve with the factor for one right-hand side (in place; enqueued, no synchronisation)
 fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv);
 fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs);
+// FP32 LU of a copy of A with FP64 iterative refinement against A (kept); FP64 LU if that fails
+fse_status dense_lu_solve_refined(fse_ctx *ctx, double *A, int N, double *rhs);
+// the dense solve of the Newton and arclength systems: refined in the mixed mode, FP64 otherwise
+fse_status newton_dense_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // `count` independent systems of one size: system z at A + z sA, pivots piv + z sp, rhs + z sx
 fse_status dense_lu_apply_batched(fse_ctx *ctx, const double *A, size_t sA, int N, const int32_t *piv,
                                   size_t sp, double *rhs, size_t sx, int count);

@@ -20,26 +20,27 @@ constexpr int kLuBlock = 64;  // outer block (also the largest TRSM triangle)
 
 // Factor the leaf panel B[j0:N, j0:j0+nb] (nb <= kLuLeaf) with partial pivoting;
 // interchanges are applied inside the panel only.
-__global__ __launch_bounds__(1024) void k_lu_leaf(double *__restrict__ B, int N, int j0, int nb,
+template <typename T>
+__global__ __launch_bounds__(1024) void k_lu_leaf(T *__restrict__ B, int N, int j0, int nb,
                                                   int32_t *__restrict__ piv, DevStatus *st) {
-  __shared__ double sv[16];
+  __shared__ T sv[16];
   __shared__ int si[16];
   __shared__ int piv_s;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
   for (int c = 0; c < nb; ++c) {
     const int j = j0 + c;
-    const double *col = B + (size_t)j * N;
-    double best = -1.0;
+    const T *col = B + (size_t)j * N;
+    T best = T(-1);
     int bi = j;
     for (int i = j + tid; i < N; i += nt) {
-      const double v = fabs(col[i]);
+      const T v = fabs(col[i]);
       if (v > best) {
         best = v;
         bi = i;
       }
     }
     for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o);
+      const T ov = __shfl_xor(best, o);
       const int oi = __shfl_xor(bi, o);
       if (ov > best || (ov == best && oi < bi)) {
         best = ov;
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(1024) void k_lu_leaf(double *__restrict__ B, int N,
     }
     __syncthreads();
     if (tid == 0) {
-      double b = sv[0];
+      T b = sv[0];
       int ix = si[0];
       for (int w = 1; w < (nt >> 6); ++w)
         if (sv[w] > b || (sv[w] == b && si[w] < ix)) {
@@ -61,23 +62,23 @@ __global__ __launch_bounds__(1024) void k_lu_leaf(double *__restrict__ B, int N,
         }
       piv_s = ix;
       piv[j] = ix;
-      if (!(b > 0.0) || !isfinite(b)) atomicOr(&st->flags, (int)DEV_SINGULAR);
+      if (!(b > T(0)) || !isfinite(b)) atomicOr(&st->flags, (int)DEV_SINGULAR);
     }
     __syncthreads();
     const int p = piv_s;
     if (p != j && tid < nb) {
-      double *cc = B + (size_t)(j0 + tid) * N;
-      const double t = cc[j];
+      T *cc = B + (size_t)(j0 + tid) * N;
+      const T t = cc[j];
       cc[j] = cc[p];
       cc[p] = t;
     }
     __syncthreads();
-    const double inv = 1.0 / col[j];
+    const T inv = T(1) / col[j];
     for (int i = j + 1 + tid; i < N; i += nt) {
-      const double l = col[i] * inv;
+      const T l = col[i] * inv;
       B[(size_t)j * N + i] = l;
       for (int c2 = c + 1; c2 < nb; ++c2) {
-        double *cc = B + (size_t)(j0 + c2) * N;
+        T *cc = B + (size_t)(j0 + c2) * N;
         cc[i] -= l * cc[j];
       }
     }
@@ -89,39 +90,39 @@ __global__ __launch_bounds__(1024) void k_lu_leaf(double *__restrict__ B, int N,
 // (r < RPT) of the NB columns, so each column costs one block reduction for the pivot and one
 // exchange of the pivot row and row j through LDS, and the rank-1 update never leaves the
 // registers.  Pivots and arithmetic are those of k_lu_leaf.  Needs N - j0 <= 1024 RPT.
-template <int NB, int RPT>
-__global__ __launch_bounds__(1024) void k_lu_leaf_reg(double *__restrict__ B, int N, int j0, int nb,
+template <typename T, int NB, int RPT>
+__global__ __launch_bounds__(1024) void k_lu_leaf_reg(T *__restrict__ B, int N, int j0, int nb,
                                                       int32_t *__restrict__ piv, DevStatus *st) {
   constexpr int NT = 1024;
-  __shared__ double sv[NT / 64];
+  __shared__ T sv[NT / 64];
   __shared__ int si[NT / 64];
-  __shared__ double prow[NB], jrow[NB];
+  __shared__ T prow[NB], jrow[NB];
   __shared__ int piv_s;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  double v[RPT][NB];
+  T v[RPT][NB];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int i = j0 + tid + r * NT;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) v[r][c] = (i < N && c < nb) ? B[(size_t)(j0 + c) * N + i] : 0.0;
+    for (int c = 0; c < NB; ++c) v[r][c] = (i < N && c < nb) ? B[(size_t)(j0 + c) * N + i] : T(0);
   }
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c >= nb) break;
     const int j = j0 + c;
-    double best = -1.0;
+    T best = T(-1);
     int bi = j;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = j0 + tid + r * NT;
-      const double a = fabs(v[r][c]);
+      const T a = fabs(v[r][c]);
       if (i >= j && i < N && a > best) {
         best = a;
         bi = i;
       }
     }
     for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o);
+      const T ov = __shfl_xor(best, o);
       const int oi = __shfl_xor(bi, o);
       if (ov > best || (ov == best && oi < bi)) {
         best = ov;
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(1024) void k_lu_leaf_reg(double *__restrict__ B, in
     }
     __syncthreads();
     if (tid == 0) {
-      double b = sv[0];
+      T b = sv[0];
       int ix = si[0];
       for (int w = 1; w < NT / 64; ++w)
         if (sv[w] > b || (sv[w] == b && si[w] < ix)) {
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(1024) void k_lu_leaf_reg(double *__restrict__ B, in
         }
       piv_s = ix;
       piv[j] = ix;
-      if (!(b > 0.0) || !isfinite(b)) atomicOr(&st->flags, (int)DEV_SINGULAR);
+      if (!(b > T(0)) || !isfinite(b)) atomicOr(&st->flags, (int)DEV_SINGULAR);
     }
     __syncthreads();
     const int p = piv_s;
@@ -175,12 +176,12 @@ __global__ __launch_bounds__(1024) void k_lu_leaf_reg(double *__restrict__ B, in
           }
       }
     }
-    const double inv = 1.0 / prow[c];
+    const T inv = T(1) / prow[c];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int i = j0 + tid + r * NT;
       if (i > j && i < N) {
-        const double l = v[r][c] * inv;
+        const T l = v[r][c] * inv;
         v[r][c] = l;
 #pragma unroll
         for (int c2 = c + 1; c2 < NB; ++c2) v[r][c2] -= l * prow[c2];
@@ -199,15 +200,16 @@ __global__ __launch_bounds__(1024) void k_lu_leaf_reg(double *__restrict__ B, in
 }
 
 // Interchanges piv[k0..k1) applied in order to the columns [c0, c1) of B.
-__global__ void k_lu_swap(double *__restrict__ B, int N, int c0, int c1, int k0, int k1,
+template <typename T>
+__global__ void k_lu_swap(T *__restrict__ B, int N, int c0, int c1, int k0, int k1,
                           const int32_t *__restrict__ piv) {
   const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= c1) return;
-  double *cc = B + (size_t)c * N;
+  T *cc = B + (size_t)c * N;
   for (int k = k0; k < k1; ++k) {
     const int p = piv[k];
     if (p != k) {
-      const double t = cc[k];
+      const T t = cc[k];
       cc[k] = cc[p];
       cc[p] = t;
     }
@@ -216,9 +218,10 @@ __global__ void k_lu_swap(double *__restrict__ B, int N, int c0, int c1, int k0,
 
 // B[j0:j0+nb, c0:c0+nc] <- L11^-1 B[j0:j0+nb, c0:c0+nc], L11 the unit lower triangle of
 // B[j0:j0+nb, j0:j0+nb] (nb <= 64) staged in LDS.  One wave per column, lane r holds row r.
-__global__ __launch_bounds__(256) void k_lu_trsm(double *__restrict__ B, int N, int j0, int nb, int c0,
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_trsm(T *__restrict__ B, int N, int j0, int nb, int c0,
                                                  int nc) {
-  __shared__ double L[kLuBlock][kLuBlock + 1];
+  __shared__ T L[kLuBlock][kLuBlock + 1];
   for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
     const int r = e % nb, c = e / nb;
     L[r][c] = B[(size_t)(j0 + c) * N + j0 + r];
@@ -227,10 +230,10 @@ __global__ __launch_bounds__(256) void k_lu_trsm(double *__restrict__ B, int N, 
   const int lane = threadIdx.x & 63;
   const int col = c0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (col >= c0 + nc) return;
-  double *cc = B + (size_t)col * N + j0;
-  double x = lane < nb ? cc[lane] : 0.0;
+  T *cc = B + (size_t)col * N + j0;
+  T x = lane < nb ? cc[lane] : T(0);
   for (int r = 0; r < nb - 1; ++r) {
-    const double xr = __shfl(x, r);
+    const T xr = __shfl(x, r);
     if (lane > r) x -= L[lane][r] * xr;
   }
   if (lane < nb) cc[lane] = x;
@@ -238,26 +241,27 @@ __global__ __launch_bounds__(256) void k_lu_trsm(double *__restrict__ B, int N, 
 
 // C -= A Bm on column-major sub-blocks of B: C = B[r0:r0+m, c0:c0+n], A = B[r0:r0+m, k0:k0+kk],
 // Bm = B[k0:k0+kk, c0:c0+n].  64 x 64 tiles, 16-deep k slices staged in LDS.
-__global__ __launch_bounds__(256) void k_lu_gemm(double *__restrict__ B, int N, int r0, int m, int c0,
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_gemm(T *__restrict__ B, int N, int r0, int m, int c0,
                                                  int n, int k0, int kk) {
-  __shared__ double As[16][68];
-  __shared__ double Bs[16][68];
+  __shared__ T As[16][68];
+  __shared__ T Bs[16][68];
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   const int i0 = r0 + blockIdx.x * 64, jb = c0 + blockIdx.y * 64;
-  double acc[4][4] = {};
+  T acc[4][4] = {};
   for (int ks = 0; ks < kk; ks += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
       const int i = e & 63, k = e >> 6;
       const int gi = i0 + i, gk = k0 + ks + k;
-      As[k][i] = (gi < r0 + m && ks + k < kk) ? B[(size_t)gk * N + gi] : 0.0;
+      As[k][i] = (gi < r0 + m && ks + k < kk) ? B[(size_t)gk * N + gi] : T(0);
       const int k2 = e & 15, j = e >> 4;
       const int gj = jb + j, gk2 = k0 + ks + k2;
-      Bs[k2][j] = (gj < c0 + n && ks + k2 < kk) ? B[(size_t)gj * N + gk2] : 0.0;
+      Bs[k2][j] = (gj < c0 + n && ks + k2 < kk) ? B[(size_t)gj * N + gk2] : T(0);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      double a[4], b[4];
+      T a[4], b[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) a[u] = As[k][tr + 16 * u];
 #pragma unroll
@@ -285,17 +289,18 @@ __global__ __launch_bounds__(256) void k_lu_gemm(double *__restrict__ B, int N, 
 // memory row i).  y[r0:r0+nb] -= M[r0:r0+nb, cols] x[cols] for the already solved
 // columns, one wave per row.  The solve kernels take a batch of independent systems of one
 // size, system z at A + z sA, its vectors at x + z sx and its pivots at piv + z sp.
-__global__ __launch_bounds__(256) void k_lu_gemv(const double *__restrict__ A, int N, int r0, int nb,
-                                                 int c0, int c1, const double *__restrict__ x,
-                                                 double *__restrict__ y, size_t sA, size_t sx) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_gemv(const T *__restrict__ A, int N, int r0, int nb,
+                                                 int c0, int c1, const T *__restrict__ x,
+                                                 T *__restrict__ y, size_t sA, size_t sx) {
   A += blockIdx.y * sA;
   x += blockIdx.y * sx;
   y += blockIdx.y * sx;
   const int lane = threadIdx.x & 63;
   const int r = r0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= r0 + nb) return;
-  const double *row = A + (size_t)r * N;
-  double s = 0.0;
+  const T *row = A + (size_t)r * N;
+  T s = T(0);
   for (int c = c0 + lane; c < c1; c += 64) s += row[c] * x[c];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (lane == 0) y[r] -= s;
@@ -303,23 +308,24 @@ __global__ __launch_bounds__(256) void k_lu_gemv(const double *__restrict__ A, i
 
 // Diagonal block of the substitution, one wave: forward (upper = false: U^T with its
 // diagonal) or backward (upper = true: unit L^T) over rows [r0, r0+nb), nb <= 64.
-__global__ __launch_bounds__(64) void k_lu_diag(const double *__restrict__ A, int N, int r0, int nb,
-                                                bool upper, double *__restrict__ y, size_t sA, size_t sx) {
+template <typename T>
+__global__ __launch_bounds__(64) void k_lu_diag(const T *__restrict__ A, int N, int r0, int nb,
+                                                bool upper, T *__restrict__ y, size_t sA, size_t sx) {
   A += blockIdx.x * sA;
   y += blockIdx.x * sx;
   const int lane = threadIdx.x;
-  double x = lane < nb ? y[r0 + lane] : 0.0;
+  T x = lane < nb ? y[r0 + lane] : T(0);
   if (!upper) {
     for (int r = 0; r < nb; ++r) {
-      const double d = A[(size_t)(r0 + r) * N + r0 + r];
-      const double xr = __shfl(x, r) / d;
+      const T d = A[(size_t)(r0 + r) * N + r0 + r];
+      const T xr = __shfl(x, r) / d;
       if (lane == r) x = xr;
       // rows below: memory row (r0+lane), column (r0+r)
       if (lane > r && lane < nb) x -= A[(size_t)(r0 + lane) * N + r0 + r] * xr;
     }
   } else {
     for (int r = nb - 1; r >= 0; --r) {
-      const double xr = __shfl(x, r);
+      const T xr = __shfl(x, r);
       if (lane < r) x -= A[(size_t)(r0 + lane) * N + r0 + r] * xr;
     }
   }
@@ -331,9 +337,11 @@ __global__ __launch_bounds__(64) void k_lu_diag(const double *__restrict__ A, in
 // staged in LDS so the serial chain of swaps runs at LDS latency.
 constexpr int kUnpermLds = 16384;
 
-__global__ __launch_bounds__(1024) void k_lu_unpermute(double *__restrict__ x, int N,
+template <typename T>
+__global__ __launch_bounds__(1024) void k_lu_unpermute(T *__restrict__ x, int N,
                                                        const int32_t *__restrict__ piv, size_t sx, size_t sp) {
-  extern __shared__ double xs[];
+  extern __shared__ __align__(16) unsigned char xs_raw[];
+  T *xs = reinterpret_cast<T *>(xs_raw);
   x += blockIdx.x * sx;
   piv += blockIdx.x * sp;
   if (N <= kUnpermLds) {
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(1024) void k_lu_unpermute(double *__restrict__ x, i
       for (int k = N - 1; k >= 0; --k) {
         const int p = piv[k];
         if (p != k) {
-          const double t = xs[k];
+          const T t = xs[k];
           xs[k] = xs[p];
           xs[p] = t;
         }
@@ -356,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_lu_unpermute(double *__restrict__ x, i
     for (int k = N - 1; k >= 0; --k) {
       const int p = piv[k];
       if (p != k) {
-        const double t = x[k];
+        const T t = x[k];
         x[k] = x[p];
         x[p] = t;
       }
@@ -507,21 +515,24 @@ __global__ __launch_bounds__(1024) void k_householder(double *__restrict__ Y, in
 
 namespace {
 
-void lu_gemm(fse_ctx *ctx, double *B, int N, int r0, int m, int c0, int n, int k0, int kk) {
+template <typename T>
+void lu_gemm(fse_ctx *ctx, T *B, int N, int r0, int m, int c0, int n, int k0, int kk) {
   if (m <= 0 || n <= 0 || kk <= 0) return;
   dim3 g((m + 63) / 64, (n + 63) / 64);
-  hipLaunchKernelGGL(k_lu_gemm, g, dim3(256), 0, ctx->stream, B, N, r0, m, c0, n, k0, kk);
+  hipLaunchKernelGGL(k_lu_gemm<T>, g, dim3(256), 0, ctx->stream, B, N, r0, m, c0, n, k0, kk);
 }
 
-void lu_swap(fse_ctx *ctx, double *B, int N, int c0, int c1, int k0, int k1) {
+template <typename T>
+void lu_swap(fse_ctx *ctx, T *B, int N, int c0, int c1, int k0, int k1) {
   if (c1 <= c0 || k1 <= k0) return;
-  hipLaunchKernelGGL(k_lu_swap, dim3((c1 - c0 + 255) / 256), dim3(256), 0, ctx->stream, B, N, c0, c1, k0,
+  hipLaunchKernelGGL(k_lu_swap<T>, dim3((c1 - c0 + 255) / 256), dim3(256), 0, ctx->stream, B, N, c0, c1, k0,
                      k1, ctx->piv_d);
 }
 
-void lu_trsm(fse_ctx *ctx, double *B, int N, int j0, int nb, int c0, int nc) {
+template <typename T>
+void lu_trsm(fse_ctx *ctx, T *B, int N, int j0, int nb, int c0, int nc) {
   if (nc <= 0 || nb <= 1) return;
-  hipLaunchKernelGGL(k_lu_trsm, dim3((nc + 3) / 4), dim3(256), 0, ctx->stream, B, N, j0, nb, c0, nc);
+  hipLaunchKernelGGL(k_lu_trsm<T>, dim3((nc + 3) / 4), dim3(256), 0, ctx->stream, B, N, j0, nb, c0, nc);
 }
 
 // Leaf width for a panel of m rows: as wide as the register-resident leaf holds
@@ -534,21 +545,23 @@ int leaf_width(int m) {
   return kLuLeaf;
 }
 
-void lu_leaf(fse_ctx *ctx, double *B, int N, int j0, int nb) {
+template <typename T>
+void lu_leaf(fse_ctx *ctx, T *B, int N, int j0, int nb) {
   const int m = N - j0;
   if (nb <= 8 && m <= 1024 * kRegRows8)
-    hipLaunchKernelGGL((k_lu_leaf_reg<8, kRegRows8>), dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb,
+    hipLaunchKernelGGL((k_lu_leaf_reg<T, 8, kRegRows8>), dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb,
                        ctx->piv_d, ctx->status_d);
   else if (nb <= 4 && m <= 1024 * kRegRows4)
-    hipLaunchKernelGGL((k_lu_leaf_reg<4, kRegRows4>), dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb,
+    hipLaunchKernelGGL((k_lu_leaf_reg<T, 4, kRegRows4>), dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb,
                        ctx->piv_d, ctx->status_d);
   else
-    hipLaunchKernelGGL(k_lu_leaf, dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb, ctx->piv_d,
+    hipLaunchKernelGGL(k_lu_leaf<T>, dim3(1), dim3(1024), 0, ctx->stream, B, N, j0, nb, ctx->piv_d,
                        ctx->status_d);
 }
 
 // Recursive panel B[j0:N, j0:j0+nb], nb <= kLuBlock.
-void lu_panel(fse_ctx *ctx, double *B, int N, int j0, int nb) {
+template <typename T>
+void lu_panel(fse_ctx *ctx, T *B, int N, int j0, int nb) {
   const int lw = leaf_width(N - j0);
   if (nb <= lw) {
     lu_leaf(ctx, B, N, j0, nb);
@@ -563,13 +576,37 @@ void lu_panel(fse_ctx *ctx, double *B, int N, int j0, int nb) {
   lu_swap(ctx, B, N, j0, j0 + n1, j0 + n1, j0 + nb);
 }
 
-}  // namespace
+// ---------------------------------------------------------------- mixed-precision solve
+__global__ void k_narrow(size_t n, const double *__restrict__ a, float *__restrict__ b) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
 
-fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv) {
+__global__ void k_widen_add(int N, const float *__restrict__ d, double *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) x[i] += (double)d[i];
+}
+
+// r = b - A x for the row-major N x N matrix A, one wave per row, FP64
+__global__ __launch_bounds__(256) void k_resid_rows(const double *__restrict__ A, int N,
+                                                    const double *__restrict__ x, const double *__restrict__ b,
+                                                    double *__restrict__ r) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const double *a = A + (size_t)row * N;
+  double s = 0.0;
+  for (int c = lane; c < N; c += 64) s += a[c] * x[c];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) r[row] = b[row] - s;
+}
+
+template <typename T>
+fse_status lu_factor_t(fse_ctx *ctx, T *A, int N, int32_t *piv) {
   FSE_TRY(reset_status(ctx));
   int32_t *const saved = ctx->piv_d;
   ctx->piv_d = piv;  // the panel routines take the pivots from the context
-  double *B = A;     // B = J^T column-major
+  T *B = A;          // B = J^T column-major
   for (int j0 = 0; j0 < N; j0 += kLuBlock) {
     const int nb = (N - j0) < kLuBlock ? (N - j0) : kLuBlock;
     lu_panel(ctx, B, N, j0, nb);
@@ -591,37 +628,136 @@ fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv) {
   return FSE_OK;
 }
 
-fse_status dense_lu_apply_batched(fse_ctx *ctx, const double *A, size_t sA, int N, const int32_t *piv,
-                                  size_t sp, double *rhs, size_t sx, int count) {
+template <typename T>
+fse_status lu_apply_t(fse_ctx *ctx, const T *A, size_t sA, int N, const int32_t *piv, size_t sp, T *rhs,
+                      size_t sx, int count) {
   if (count < 1) return FSE_OK;
   // U^T v = r (forward, memory rows), then L^T w = v (backward), then x = Pi^T w; every launch
   // covers the `count` systems at once
   for (int r0 = 0; r0 < N; r0 += 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
     if (r0 > 0)
-      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, 0, r0,
+      hipLaunchKernelGGL(k_lu_gemv<T>, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, 0, r0,
                          rhs, rhs, sA, sx);
-    hipLaunchKernelGGL(k_lu_diag, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs, sA, sx);
+    hipLaunchKernelGGL(k_lu_diag<T>, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs, sA, sx);
   }
   const int last = ((N - 1) / 64) * 64;
   for (int r0 = last; r0 >= 0; r0 -= 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
     if (r0 + nb < N)
-      hipLaunchKernelGGL(k_lu_gemv, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, r0 + nb,
+      hipLaunchKernelGGL(k_lu_gemv<T>, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, r0 + nb,
                          N, rhs, rhs, sA, sx);
-    hipLaunchKernelGGL(k_lu_diag, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs, sA, sx);
+    hipLaunchKernelGGL(k_lu_diag<T>, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs, sA, sx);
   }
-  const size_t lds = N <= kUnpermLds ? sizeof(double) * N : 0;
+  const size_t lds = N <= kUnpermLds ? sizeof(T) * N : 0;
   if (lds > 64 * 1024)
-    FSE_HIP(hipFuncSetAttribute((const void *)k_lu_unpermute, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * kUnpermLds)));
-  hipLaunchKernelGGL(k_lu_unpermute, dim3(count), dim3(1024), lds, ctx->stream, rhs, N, piv, sx, sp);
+    FSE_HIP(hipFuncSetAttribute((const void *)k_lu_unpermute<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(T) * kUnpermLds)));
+  hipLaunchKernelGGL(k_lu_unpermute<T>, dim3(count), dim3(1024), lds, ctx->stream, rhs, N, piv, sx, sp);
   FSE_HIP(hipGetLastError());
   return FSE_OK;
 }
 
+fse_status ensure_pivots(fse_ctx *ctx, int N) {
+  if (ctx->piv_n < N) {
+    if (ctx->piv_d) (void)hipFree(ctx->piv_d);
+    ctx->piv_d = nullptr;
+    ctx->piv_n = 0;
+    if (hipMalloc((void **)&ctx->piv_d, sizeof(int32_t) * N) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the pivots";
+      return FSE_E_NOMEM;
+    }
+    ctx->piv_n = N;
+  }
+  return FSE_OK;
+}
+
+}  // namespace
+
+fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv) { return lu_factor_t(ctx, A, N, piv); }
+
+fse_status dense_lu_apply_batched(fse_ctx *ctx, const double *A, size_t sA, int N, const int32_t *piv,
+                                  size_t sp, double *rhs, size_t sx, int count) {
+  return lu_apply_t(ctx, A, sA, N, piv, sp, rhs, sx, count);
+}
+
 fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs) {
   return dense_lu_apply_batched(ctx, A, 0, N, piv, 0, rhs, 0, 1);
+}
+
+// Mixed-precision dense solve (FP32 LU, FP64 iterative refinement): A (row-major FP64, kept)
+// is rounded to FP32 and factored; then d = LU32^-1 r, x += d, r = b - A x in FP64 until
+// ||r|| <= 1e-13 ||b||.  If the refinement stalls above 1e-10 ||b|| (A too ill-conditioned for
+// the FP32 factor) or the FP32 factor is singular, the FP64 LU solves the system instead.
+fse_status dense_lu_solve_refined(fse_ctx *ctx, double *A, int N, double *rhs) {
+  constexpr int kMaxRefine = 10;
+  FSE_TRY(ensure_pivots(ctx, N));
+  const size_t nn = (size_t)N * N;
+  if (ctx->lu32_elems < nn + N) {
+    if (ctx->lu32) (void)hipFree(ctx->lu32);
+    ctx->lu32 = nullptr;
+    ctx->lu32_elems = 0;
+    if (hipMalloc((void **)&ctx->lu32, sizeof(float) * (nn + N)) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the FP32 factor";
+      return FSE_E_NOMEM;
+    }
+    ctx->lu32_elems = nn + N;
+  }
+  if (ctx->ir_elems < 3 * (size_t)N) {
+    if (ctx->ir) (void)hipFree(ctx->ir);
+    ctx->ir = nullptr;
+    ctx->ir_elems = 0;
+    if (hipMalloc((void **)&ctx->ir, sizeof(double) * 3 * N) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the refinement vectors";
+      return FSE_E_NOMEM;
+    }
+    ctx->ir_elems = 3 * (size_t)N;
+  }
+  float *A32 = ctx->lu32, *d32 = ctx->lu32 + nn;
+  double *b = ctx->ir, *x = b + N, *r = x + N;
+  const int nbk = (N + 255) / 256;
+  hipLaunchKernelGGL(k_narrow, dim3(4096), dim3(256), 0, ctx->stream, nn, A, A32);
+  FSE_HIP(hipGetLastError());
+  ctx->last_refine = -1;
+  const fse_status fs = lu_factor_t(ctx, A32, N, ctx->piv_d);
+  if (fs != FSE_OK && fs != FSE_E_SINGULAR) return fs;
+  if (fs == FSE_OK) {
+    FSE_HIP(hipMemcpyAsync(b, rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    FSE_HIP(hipMemcpyAsync(r, rhs, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+    FSE_HIP(hipMemsetAsync(x, 0, sizeof(double) * N, ctx->stream));
+    double nb = 0.0;
+    FSE_TRY(launch_norm(ctx, b, (size_t)N, &nb));
+    if (!(nb > 0.0)) {
+      FSE_HIP(hipMemsetAsync(rhs, 0, sizeof(double) * N, ctx->stream));
+      FSE_HIP(hipStreamSynchronize(ctx->stream));
+      ctx->last_refine = 0;
+      return FSE_OK;
+    }
+    double prev = INFINITY, nr = INFINITY;
+    int it = 0;
+    for (; it < kMaxRefine; ++it) {
+      hipLaunchKernelGGL(k_narrow, dim3(nbk), dim3(256), 0, ctx->stream, (size_t)N, r, d32);
+      FSE_TRY(lu_apply_t(ctx, (const float *)A32, 0, N, ctx->piv_d, 0, d32, 0, 1));
+      hipLaunchKernelGGL(k_widen_add, dim3(nbk), dim3(256), 0, ctx->stream, N, d32, x);
+      hipLaunchKernelGGL(k_resid_rows, dim3((N + 3) / 4), dim3(256), 0, ctx->stream, A, N, x, b, r);
+      FSE_HIP(hipGetLastError());
+      FSE_TRY(launch_norm(ctx, r, (size_t)N, &nr));
+      if (nr <= 1e-13 * nb || !(nr < 0.5 * prev)) break;
+      prev = nr;
+    }
+    if (nr <= 1e-10 * nb) {
+      FSE_HIP(hipMemcpyAsync(rhs, x, sizeof(double) * N, hipMemcpyDeviceToDevice, ctx->stream));
+      FSE_HIP(hipStreamSynchronize(ctx->stream));
+      ctx->last_refine = it + 1;
+      return FSE_OK;
+    }
+  }
+  // the FP32 factor does not carry this system: plain FP64 LU (A is still intact)
+  return dense_lu_solve(ctx, A, N, rhs);
+}
+
+fse_status newton_dense_solve(fse_ctx *ctx, double *A, int N, double *rhs) {
+  return ctx->prec == FSE_PREC_MIXED_FP32 ? dense_lu_solve_refined(ctx, A, N, rhs) : dense_lu_solve(ctx, A, N, rhs);
 }
 
 fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs) {

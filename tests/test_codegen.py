@@ -1,8 +1,8 @@
 """Machine-code checks of the LDS-heavy trajectory kernels (host compile only, no GPU).
 
 The fused trajectory kernel and the omega_1 sensitivity kernels keep their banded factors and
-tensors in LDS, and the wide-band kernels stage state rows, factor rings and operand blocks
-there.  Every LDS access must compile to a ds_* instruction: a generic (flat) access to
+tensors in LDS, the wide-band kernels stage state rows, factor rings and operand blocks there,
+and the dense LU stages its panels, triangles and permutations there (in FP64 and FP32).  Every LDS access must compile to a ds_* instruction: a generic (flat) access to
 LDS with a 16-byte load at an 8-byte-aligned address is the code-generation outcome that lined
 up with the memory-aperture faults the fused kernel once had, and typing every pointer with its
 address space removed it.  This test fails if any flat memory instruction reappears in those
@@ -17,7 +17,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_2508_06302_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-UNITS = ["k_fused.hip", "k_wsens.hip", "k_wide.hip"]
+UNITS = ["k_fused.hip", "k_wsens.hip", "k_wide.hip", "k_linalg.hip"]
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not installed")
