@@ -255,7 +255,8 @@ fse_status dense_lu_solve(fse_ctx *ctx, double *A, int N, double *rhs);
 // solve with the factor for one right-hand side (in place; enqueued, no synchronisation)
 fse_status dense_lu_factor(fse_ctx *ctx, double *A, int N, int32_t *piv);
 fse_status dense_lu_apply(fse_ctx *ctx, const double *A, int N, const int32_t *piv, double *rhs);
-// FP32 LU of a copy of A with FP64 iterative refinement against A (kept); FP64 LU if that fails
+// FP32 LU of a copy of A with FP64 iterative refinement against A (kept) to 1e-10 of the
+// right-hand side; FP64 LU if that fails
 fse_status dense_lu_solve_refined(fse_ctx *ctx, double *A, int N, double *rhs);
 // the dense solve of the Newton and arclength systems: refined in the mixed mode, FP64 otherwise
 fse_status newton_dense_solve(fse_ctx *ctx, double *A, int N, double *rhs);
