@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--sweep", choices=["train", "learned", "secant"],
                     help="run one phase of the 200-point shell sweep instead of the benchmark")
-    ap.add_argument("--sweep-dir", default=os.path.join(ROOT, "gpurun_out", "sweep"),
+    ap.add_argument("--sweep-dir", default=os.path.join(ROOT, "sweep_results"),
                     help="where a sweep phase writes its results")
     ap.add_argument("--sweep-in", default=None,
                     help="where a sweep phase reads the training results (default: --sweep-dir)")
