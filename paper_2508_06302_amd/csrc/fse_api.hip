@@ -423,7 +423,7 @@ void free_all(fse_ctx *ctx) {
                   ctx->G_d, ctx->Gi_d, ctx->sidx_d, ctx->Sdim_d, ctx->ktable_d, ctx->omega_d,
                   ctx->qhist, ctx->u0, ctx->zTw, ctx->state_scr, ctx->PhiA, ctx->PhiQU,
                   ctx->sens_scr, ctx->status_d, ctx->rot_d, ctx->rot_mf, ctx->work_R, ctx->Zwork, ctx->Jw,
-                  ctx->piv_d, ctx->lu_scr, ctx->lu32, ctx->ir, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
+                  ctx->piv_d, ctx->lu_scr, ctx->lu32, ctx->ir, ctx->lu_part, ctx->norm_d, ctx->jacP, ctx->sens_gscr,
                   ctx->Sp, ctx->Mwp, ctx->Dwp, ctx->Kp, ctx->work_b, ctx->dzw, ctx->zeros_d, ctx->arc, ctx->wfac, ctx->kr, ctx->kr_piv, ctx->ht, ctx->mult,
                   ctx->ct_ptr, ctx->ct_idx, ctx->ct_c, ctx->uhist, ctx->cn_ptr, ctx->cn_v};
   if (ctx->f2_pk) (void)hipFree(ctx->f2_pk);

@@ -124,6 +124,8 @@ struct fse_ctx {
   double *ir = nullptr;             // refinement vectors b, x, r
   size_t ir_elems = 0;
   int last_refine = 0;              // refinement steps of the last mixed dense solve (-1: FP64 used)
+  void *lu_part = nullptr;          // partial sums of the dense substitutions
+  size_t lu_part_bytes = 0;
   double *lu_scr = nullptr;
   double *norm_d = nullptr;         // [Bmax] squared residual norms
   double *jacP = nullptr;           // [S~][U][U] Jacobian right factor

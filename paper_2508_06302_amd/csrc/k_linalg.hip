@@ -286,47 +286,62 @@ __global__ __launch_bounds__(256) void k_lu_gemm(T *__restrict__ B, int N, int r
 }
 
 // Blocked triangular solves with the factors of B (row i of U^T and of L^T is contiguous:
-// memory row i).  y[r0:r0+nb] -= M[r0:r0+nb, cols] x[cols] for the already solved
-// columns, one wave per row.  The solve kernels take a batch of independent systems of one
-// size, system z at A + z sA, its vectors at x + z sx and its pivots at piv + z sp.
+// memory row i).  For the rows [r0, r0+nb) the already solved columns [c0, c1) contribute
+// M[r0:r0+nb, cols] x[cols]; they are split into chunks of kGemvChunk columns, one work-group per
+// 4 rows and chunk (one wave per row), each writing its partial sums, which the diagonal kernel
+// then adds in chunk order.  The solve kernels take a batch of independent systems of one size,
+// system z at A + z sA, its vectors at x + z sx, its pivots at piv + z sp and its partial sums at
+// part + z spp.
+constexpr int kGemvChunk = 1024;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_gemv(const T *__restrict__ A, int N, int r0, int nb,
                                                  int c0, int c1, const T *__restrict__ x,
-                                                 T *__restrict__ y, size_t sA, size_t sx) {
-  A += blockIdx.y * sA;
-  x += blockIdx.y * sx;
-  y += blockIdx.y * sx;
+                                                 T *__restrict__ part, size_t sA, size_t sx, size_t spp) {
+  A += blockIdx.z * sA;
+  x += blockIdx.z * sx;
+  part += blockIdx.z * spp;
   const int lane = threadIdx.x & 63;
-  const int r = r0 + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (r >= r0 + nb) return;
-  const T *row = A + (size_t)r * N;
+  const int rr = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (rr >= nb) return;
+  const int ch = blockIdx.y;
+  const int ca = c0 + ch * kGemvChunk, cb = min(c1, ca + kGemvChunk);
+  const T *row = A + (size_t)(r0 + rr) * N;
   T s = T(0);
-  for (int c = c0 + lane; c < c1; c += 64) s += row[c] * x[c];
+  for (int c = ca + lane; c < cb; c += 64) s += row[c] * x[c];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) y[r] -= s;
+  if (lane == 0) part[(size_t)ch * 64 + rr] = s;
 }
 
 // Diagonal block of the substitution, one wave: forward (upper = false: U^T with its
-// diagonal) or backward (upper = true: unit L^T) over rows [r0, r0+nb), nb <= 64.
+// diagonal) or backward (upper = true: unit L^T) over rows [r0, r0+nb), nb <= 64, after the
+// nch partial sums of the solved columns are subtracted.  The block is staged in LDS first
+// (coalesced rows), so the dependent chain of the substitution runs at LDS latency.
 template <typename T>
 __global__ __launch_bounds__(64) void k_lu_diag(const T *__restrict__ A, int N, int r0, int nb,
-                                                bool upper, T *__restrict__ y, size_t sA, size_t sx) {
+                                                bool upper, T *__restrict__ y, const T *__restrict__ part,
+                                                int nch, size_t sA, size_t sx, size_t spp) {
+  __shared__ T Ds[64][65];
   A += blockIdx.x * sA;
   y += blockIdx.x * sx;
+  part += blockIdx.x * spp;
   const int lane = threadIdx.x;
+  for (int row = 0; row < nb; ++row) Ds[row][lane] = lane < nb ? A[(size_t)(r0 + row) * N + r0 + lane] : T(0);
   T x = lane < nb ? y[r0 + lane] : T(0);
+  if (lane < nb)
+    for (int ch = 0; ch < nch; ++ch) x -= part[(size_t)ch * 64 + lane];
+  __syncthreads();
   if (!upper) {
     for (int r = 0; r < nb; ++r) {
-      const T d = A[(size_t)(r0 + r) * N + r0 + r];
-      const T xr = __shfl(x, r) / d;
+      const T xr = __shfl(x, r) / Ds[r][r];
       if (lane == r) x = xr;
       // rows below: memory row (r0+lane), column (r0+r)
-      if (lane > r && lane < nb) x -= A[(size_t)(r0 + lane) * N + r0 + r] * xr;
+      if (lane > r && lane < nb) x -= Ds[lane][r] * xr;
     }
   } else {
     for (int r = nb - 1; r >= 0; --r) {
       const T xr = __shfl(x, r);
-      if (lane < r) x -= A[(size_t)(r0 + lane) * N + r0 + r] * xr;
+      if (lane < r) x -= Ds[lane][r] * xr;
     }
   }
   if (lane < nb) y[r0 + lane] = x;
@@ -632,22 +647,40 @@ template <typename T>
 fse_status lu_apply_t(fse_ctx *ctx, const T *A, size_t sA, int N, const int32_t *piv, size_t sp, T *rhs,
                       size_t sx, int count) {
   if (count < 1) return FSE_OK;
+  // partial sums of the solved columns: [count][chunks][64]
+  const size_t nchmax = (size_t)(N + kGemvChunk - 1) / kGemvChunk, spp = nchmax * 64;
+  const size_t need = sizeof(T) * spp * (size_t)count;
+  if (ctx->lu_part_bytes < need) {
+    if (ctx->lu_part) (void)hipFree(ctx->lu_part);
+    ctx->lu_part = nullptr;
+    ctx->lu_part_bytes = 0;
+    if (hipMalloc(&ctx->lu_part, need) != hipSuccess) {
+      ctx->err = "hipMalloc failed for the substitution partial sums";
+      return FSE_E_NOMEM;
+    }
+    ctx->lu_part_bytes = need;
+  }
+  T *part = (T *)ctx->lu_part;
   // U^T v = r (forward, memory rows), then L^T w = v (backward), then x = Pi^T w; every launch
   // covers the `count` systems at once
   for (int r0 = 0; r0 < N; r0 += 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
-    if (r0 > 0)
-      hipLaunchKernelGGL(k_lu_gemv<T>, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, 0, r0,
-                         rhs, rhs, sA, sx);
-    hipLaunchKernelGGL(k_lu_diag<T>, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs, sA, sx);
+    const int nch = (r0 + kGemvChunk - 1) / kGemvChunk;
+    if (nch > 0)
+      hipLaunchKernelGGL(k_lu_gemv<T>, dim3((nb + 3) / 4, nch, count), dim3(256), 0, ctx->stream, A, N, r0, nb, 0,
+                         r0, rhs, part, sA, sx, spp);
+    hipLaunchKernelGGL(k_lu_diag<T>, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, false, rhs, part, nch,
+                       sA, sx, spp);
   }
   const int last = ((N - 1) / 64) * 64;
   for (int r0 = last; r0 >= 0; r0 -= 64) {
     const int nb = (N - r0) < 64 ? (N - r0) : 64;
-    if (r0 + nb < N)
-      hipLaunchKernelGGL(k_lu_gemv<T>, dim3((nb + 3) / 4, count), dim3(256), 0, ctx->stream, A, N, r0, nb, r0 + nb,
-                         N, rhs, rhs, sA, sx);
-    hipLaunchKernelGGL(k_lu_diag<T>, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs, sA, sx);
+    const int nch = (N - r0 - nb + kGemvChunk - 1) / kGemvChunk;
+    if (nch > 0)
+      hipLaunchKernelGGL(k_lu_gemv<T>, dim3((nb + 3) / 4, nch, count), dim3(256), 0, ctx->stream, A, N, r0, nb,
+                         r0 + nb, N, rhs, part, sA, sx, spp);
+    hipLaunchKernelGGL(k_lu_diag<T>, dim3(count), dim3(64), 0, ctx->stream, A, N, r0, nb, true, rhs, part, nch,
+                       sA, sx, spp);
   }
   const size_t lds = N <= kUnpermLds ? sizeof(T) * N : 0;
   if (lds > 64 * 1024)
